@@ -1,0 +1,179 @@
+"""Benchmark of the fused axisymmetric Shan–Chen step on one MI355X.
+
+Workload: Rayleigh–Plateau liquid thread on a 4096 x 512 (z, r) lattice,
+thread radius 64 with a 0.1 R cos(2 pi z / nz) perturbation, G = -5.5,
+free-slip outer wall, tau = 0.8 (the scheme diverges at tau = 0.7 for this
+G; tau does not change the work per node).  Synthetic, seeded inputs resident
+in HBM before the timed region.
+
+One step = one launch of the fused kernel over all 2,097,152 nodes.  Prints
+one JSON line: FP64 MLUPS as ``value``, the FP32-shifted-storage MLUPS, the
+HBM roofline of the dominant (FP64 step) kernel and the CPU oracle timed on
+the host cores over a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+NZ, NR = 4096, 512
+G, TAU, RADIUS, EPS = -5.5, 0.8, 64.0, 0.1
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+BYTES_PER_LU = {"f64": 9 * 2 * 8, "f32": 9 * 2 * 4}  # read + write every population once
+KERNEL_SOURCES = ("paper_1310_1871_amd/csrc/step_kernel.hpp", "paper_1310_1871_amd/csrc/lattice.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_axi_step_4096x512.md")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(tag):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if absent or taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(rf"traffic_bytes_per_launch_{tag}:\s*([0-9.eE+]+)", txt)
+    return float(m.group(1)) if m else None
+
+
+def workload_density():
+    from lbm_inputs import coexistence_densities, thread_density
+    rg, rl = coexistence_densities(G)
+    return thread_density(NZ, NR, RADIUS, rl, rg, 2.0, EPS, 1), rl, rg
+
+
+def time_gpu(precision, rho, rho_ref, steps, warmup):
+    import torch
+    from paper_1310_1871_amd import lbm_axi as L
+    p = L.make_params(NZ, NR, G=G, tau=TAU, wall=L.WALL_FREESLIP, axisym=1, precision=precision, rho_ref=rho_ref)
+    sim = L.AxiLBM(p, torch.from_numpy(rho).cuda())
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    sim.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    diag = sim.reduce()
+    sim.close()
+    return ms / steps, diag
+
+
+def copy_calibration():
+    """A plain device copy of known size (256 MiB read + 256 MiB written),
+    whose FETCH_SIZE / WRITE_SIZE counters calibrate the step kernel's."""
+    import torch
+    a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
+
+def cpu_baseline(rho, budget_s=12.0):
+    """The oracle as it stands, on the host cores, over whole steps of the
+    same 4096 x 512 workload until about budget_s seconds have elapsed."""
+    import ctypes
+    import numpy as np
+    import oracle as O
+    p = O.make_params(NZ, NR, G=G, tau=TAU, wall=O.WALL_FREESLIP, axisym=1)
+    f = O.equilibrium(p, rho, np.zeros_like(rho), np.zeros_like(rho))
+    t_start = time.perf_counter()
+    f = O.run(p, f, 1)  # one step sizes the sample
+    t1 = time.perf_counter() - t_start
+    steps = max(1, int(budget_s / max(t1, 1e-3)))
+    t_start = time.perf_counter()
+    f = O.run(p, f, steps)
+    el = time.perf_counter() - t_start
+    try:
+        cores = ctypes.CDLL("libgomp.so.1").omp_get_max_threads()
+    except OSError:
+        cores = os.cpu_count()
+    return {"value": NZ * NR * steps / el / 1e6, "unit": "MLUPS", "cores": int(cores), "kind": "oracle",
+            "sample": f"{steps} full steps of the 4096x512 thread workload (FP64 C oracle, OpenMP), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
+    ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain copy kernel of known size (for counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see the design notes "
+              "on z-slab sharding); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    rho, rl, rg = workload_density()
+    print(f"bench: thread {NZ}x{NR} FP64 {args.steps} steps (+{args.warmup} warm-up)", file=sys.stderr, flush=True)
+    ms64, diag64 = time_gpu(0, rho, 0.0, args.steps, args.warmup)
+    lups = NZ * NR
+    mlups64 = lups / (ms64 * 1e-3) / 1e6
+    achieved = BYTES_PER_LU["f64"] * lups / (ms64 * 1e-3) / 1e9
+    out = {
+        "metric": "MLUPS & % HBM roofline, FP64 vs FP32-storage; adjoint fwd+bwd / fwd ratio",
+        "value": round(mlups64, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms64, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "rayleigh_plateau_thread_4096x512", "nz": NZ, "nr": NR, "G": G, "tau": TAU,
+                   "wall": "free-slip", "thread_radius": RADIUS, "perturbation": "0.1 R cos(2 pi z / nz)",
+                   "rho_l": round(rl, 5), "rho_g": round(rg, 5), "bytes_per_lu": BYTES_PER_LU["f64"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("f64"),
+                     "kernel": "axi_tile_kernel<FP64>"},
+        "diagnostics_f64": {"mass_3d": diag64[0], "kinetic_energy": diag64[2]},
+    }
+    if not args.skip_fp32:
+        print(f"bench: thread {NZ}x{NR} FP32-shifted storage", file=sys.stderr, flush=True)
+        ms32, diag32 = time_gpu(1, rho, rl, args.steps, args.warmup)
+        mlups32 = lups / (ms32 * 1e-3) / 1e6
+        ach32 = BYTES_PER_LU["f32"] * lups / (ms32 * 1e-3) / 1e9
+        out["fp32_storage"] = {"value": round(mlups32, 2), "unit": "MLUPS", "ms_per_step": round(ms32, 6),
+                               "speedup_vs_f64": round(ms64 / ms32, 3), "rho_ref": round(rl, 5),
+                               "roofline": {"bound": "hbm", "achieved": round(ach32, 1), "peak": HBM_PEAK_GBS,
+                                            "unit": "GB/s", "frac": round(ach32 / HBM_PEAK_GBS, 4),
+                                            "traffic": measured_traffic("f32")},
+                               "mass_3d_rel_diff_vs_f64": abs(diag32[0] - diag64[0]) / diag64[0]}
+    out["adjoint"] = None
+    if args.copy_calibration:
+        copy_calibration()
+    if not args.skip_cpu:
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(rho)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

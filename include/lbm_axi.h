@@ -1,0 +1,129 @@
+/*
+ * lbm_axi — axisymmetric Shan–Chen lattice Boltzmann on one MI355X (gfx950).
+ *
+ * C ABI of the hot path of Srivastava, Perlekar, ten Thije Boonkkamp, Verma,
+ * Toschi, "Axisymmetric Multiphase Lattice Boltzmann Method"
+ * (arXiv:1310.1871): the fused per-timestep D2Q9 update on the (z, r)
+ * half-plane.
+ *
+ * Geometry (paper Sec. II.E): node (k, j) sits at z = k (k = 0..nz-1,
+ * periodic) and r = j + 1/2 (j = 0..nr-1).  The axis r = 0 is a mid-grid
+ * specular reflector; the outer wall r = nr is mid-grid bounce-back
+ * (no-slip) or mid-grid specular reflection (free-slip).
+ *
+ * Field arrays passed through this interface are double[nr][nz], row-major,
+ * z contiguous, in device memory unless the argument name starts with h_.
+ * The caller allocates every device buffer (including the workspace) and
+ * owns the HIP stream; the library never frees caller memory and never
+ * allocates device memory.  Calls are asynchronous on the handle's stream
+ * unless stated otherwise.
+ *
+ * Return codes: LBM_AXI_OK (0) or a negative LBM_AXI_E* code; the message of
+ * the last failure on the calling thread is lbm_axi_last_error().
+ */
+#ifndef LBM_AXI_H
+#define LBM_AXI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_AXI_OK 0
+#define LBM_AXI_EINVAL (-1)     /* invalid argument or parameter */
+#define LBM_AXI_ENOMEM (-2)     /* workspace too small */
+#define LBM_AXI_EHIP (-3)       /* HIP runtime error (message in last_error) */
+#define LBM_AXI_ENONFINITE (-4) /* a reduced diagnostic is NaN or Inf */
+#define LBM_AXI_EUNSUP (-5)     /* combination not supported */
+
+#define LBM_AXI_WALL_NOSLIP 0   /* mid-grid bounce-back */
+#define LBM_AXI_WALL_FREESLIP 1 /* mid-grid specular reflection */
+
+#define LBM_AXI_FP64 0          /* populations stored and collided in FP64 */
+#define LBM_AXI_FP32_SHIFTED 1  /* FP32 storage of f_i - W_i rho_ref, FP32 collision */
+
+typedef struct lbm_axi_params {
+    int32_t nz;        /* nodes along z (>= 1) */
+    int32_t nr;        /* nodes along r (>= 6: reach of the derivative stencils) */
+    double G;          /* Shan–Chen coupling (Sec. II.A, Eq. scforce); G < -6 is outside the
+                          stability rule of thumb of Sec. II.D */
+    double tau;        /* BGK relaxation time (> 1/2); nu = (tau - 1/2)/3 */
+    double psi_rho0;   /* rho_0 of psi = rho_0 (1 - exp(-rho/rho_0)) (> 0; the paper uses 1) */
+    double gz;         /* body acceleration along +z (pipe-flow test, Sec. III.A) */
+    int32_t wall;      /* LBM_AXI_WALL_NOSLIP or LBM_AXI_WALL_FREESLIP */
+    int32_t axisym;    /* 1: axisymmetric method; 0: plain planar Shan–Chen (test mode) */
+    int32_t precision; /* LBM_AXI_FP64 or LBM_AXI_FP32_SHIFTED */
+    int32_t flags;     /* reserved, must be 0 */
+    double rho_ref;    /* shift of the FP32 storage (ignored in FP64) */
+} lbm_axi_params;
+
+typedef struct lbm_axi_ctx* lbm_axi_t;
+
+/* Bytes of device workspace lbm_axi_create needs for these parameters (two
+ * population buffers plus reduction scratch).  0 if the parameters are
+ * invalid. */
+size_t lbm_axi_workspace_bytes(const lbm_axi_params* p);
+
+/* Validate p, bind the caller's workspace and stream, and initialise the
+ * populations to f_i = f^eq_i(rho0, u0) (appendix, Eq. e_distribution),
+ * the post-streaming state at t = 0.  d_rho0/d_uz0/d_ur0 are device fields;
+ * d_uz0 and d_ur0 may be NULL (zero velocity).  The workspace must be at
+ * least lbm_axi_workspace_bytes(p) bytes and 256-byte aligned and stays owned
+ * by the caller; it must outlive the handle.  hip_stream is a hipStream_t
+ * (NULL: the null stream).  On success *out receives the handle. */
+int lbm_axi_create(const lbm_axi_params* p, const double* d_rho0, const double* d_uz0,
+                   const double* d_ur0, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                   lbm_axi_t* out);
+
+/* Advance n >= 0 full time steps (Sec. II, Eq. lbm2d_mod_new with the
+ * Shan–Chen force of Eq. scforce, the axisymmetric extra force of
+ * Eq. scAxisExtra, the source terms of Eqs. condition_h/H_terms and the
+ * boundary rules of Sec. II.E).  Asynchronous. */
+int lbm_axi_step(lbm_axi_t h, int64_t n);
+
+/* Density rho = sum f_i (Eq. hydro_var) and hydrodynamic velocity
+ * u = (sum c_i f_i + F/2)/rho (Eq. uhydro, F the total force) of the current
+ * state, in FP64, into device fields double[nr][nz].  Any pointer may be
+ * NULL to skip that field.  Asynchronous. */
+int lbm_axi_moments(lbm_axi_t h, double* d_rho, double* d_uz, double* d_ur);
+
+/* FP64 global diagnostics of the current state, reduced on the device in a
+ * fixed order and copied to host memory h_out[LBM_AXI_NREDUCE]:
+ *   [0] 3D mass      sum 2 pi r rho           (Sec. II.B, Sec. II.C)
+ *   [1] 3D z-momentum sum 2 pi r rho u_z
+ *   [2] kinetic energy E_ke = pi sum r rho |u|^2   (Sec. III)
+ *   [3] 2D mass      sum rho
+ * Synchronises the stream.  Returns LBM_AXI_ENONFINITE (with h_out filled)
+ * if any value is NaN or Inf. */
+#define LBM_AXI_NREDUCE 4
+int lbm_axi_reduce(lbm_axi_t h, double* h_out);
+
+/* Size in bytes of the population state (9 nz nr values of the storage
+ * type, in the library's structure-of-arrays layout [9][nr][nz]). */
+size_t lbm_axi_state_bytes(lbm_axi_t h);
+
+/* Device-to-device copy of the current state into d_dst / from d_src
+ * (lbm_axi_state_bytes bytes, the library's layout).  Checkpoint/resume.
+ * Asynchronous. */
+int lbm_axi_get_state(lbm_axi_t h, void* d_dst);
+int lbm_axi_set_state(lbm_axi_t h, const void* d_src);
+
+/* Rebind the stream later calls are issued on. */
+int lbm_axi_set_stream(lbm_axi_t h, void* hip_stream);
+
+/* Replace G and tau of an existing handle (same validation as create). */
+int lbm_axi_set_coupling(lbm_axi_t h, double G, double tau);
+
+/* Release the handle (not the caller's workspace).  NULL is ignored. */
+void lbm_axi_destroy(lbm_axi_t h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* lbm_axi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_AXI_H */

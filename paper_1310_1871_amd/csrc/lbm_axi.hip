@@ -1,0 +1,309 @@
+// C ABI of the axisymmetric Shan–Chen lattice Boltzmann library (declared in
+// include/lbm_axi.h): parameter validation, workspace layout, launches of
+// the fused step kernel on the caller's stream, moments and FP64
+// reductions, state checkpointing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/lbm_axi.h"
+#include "lattice.hpp"
+#include "step_kernel.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(LBM_AXI_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                      \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// tile shape of the fused kernel per precision
+constexpr int kTZ = 64;
+constexpr int kTR64 = 16;
+constexpr int kTR32 = 16;
+
+int tile_r(int precision) { return precision == LBM_AXI_FP64 ? kTR64 : kTR32; }
+
+size_t storage_size(int precision) { return precision == LBM_AXI_FP64 ? sizeof(double) : sizeof(float); }
+
+struct Layout {
+    size_t state_bytes;   // one population buffer
+    size_t off_b;         // second buffer
+    size_t off_partials;  // [max blocks][4] doubles
+    size_t off_red;       // [4] doubles
+    size_t total;
+    int tiles_z, tiles_r, nblocks;
+};
+
+int check_params(const lbm_axi_params* p) {
+    if (!p) return fail(LBM_AXI_EINVAL, "params is NULL");
+    if (p->nz < 1) return fail(LBM_AXI_EINVAL, "nz must be >= 1 (got %d)", p->nz);
+    if (p->nr < 6) return fail(LBM_AXI_EINVAL, "nr must be >= 6 for the derivative stencils (got %d)", p->nr);
+    if ((long long)p->nz * p->nr > (1LL << 30)) return fail(LBM_AXI_EINVAL, "grid too large");
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_AXI_EINVAL, "tau must be > 1/2 (got %g)", p->tau);
+    if (!std::isfinite(p->G)) return fail(LBM_AXI_EINVAL, "G must be finite");
+    if (!(p->psi_rho0 > 0.0) || !std::isfinite(p->psi_rho0)) return fail(LBM_AXI_EINVAL, "psi_rho0 must be > 0");
+    if (!std::isfinite(p->gz)) return fail(LBM_AXI_EINVAL, "gz must be finite");
+    if (p->wall != LBM_AXI_WALL_NOSLIP && p->wall != LBM_AXI_WALL_FREESLIP)
+        return fail(LBM_AXI_EINVAL, "wall must be 0 (no-slip) or 1 (free-slip)");
+    if (p->axisym != 0 && p->axisym != 1) return fail(LBM_AXI_EINVAL, "axisym must be 0 or 1");
+    if (p->precision != LBM_AXI_FP64 && p->precision != LBM_AXI_FP32_SHIFTED)
+        return fail(LBM_AXI_EINVAL, "precision must be 0 (FP64) or 1 (FP32 shifted)");
+    if (p->flags != 0) return fail(LBM_AXI_EUNSUP, "flags must be 0");
+    if (!std::isfinite(p->rho_ref)) return fail(LBM_AXI_EINVAL, "rho_ref must be finite");
+    return LBM_AXI_OK;
+}
+
+Layout layout_of(const lbm_axi_params* p) {
+    Layout L{};
+    const size_t n = (size_t)p->nz * p->nr;
+    L.state_bytes = 9 * n * storage_size(p->precision);
+    L.tiles_z = (p->nz + kTZ - 1) / kTZ;
+    L.tiles_r = (p->nr + tile_r(p->precision) - 1) / tile_r(p->precision);
+    L.nblocks = L.tiles_z * L.tiles_r;
+    L.off_b = align_up(L.state_bytes);
+    L.off_partials = L.off_b + align_up(L.state_bytes);
+    L.off_red = L.off_partials + align_up((size_t)L.nblocks * 4 * sizeof(double));
+    L.total = L.off_red + align_up(4 * sizeof(double));
+    return L;
+}
+
+// f_i = f^eq_i(rho, u) with u^eq = u (initial state, no force shift)
+template <class P>
+__global__ void init_equilibrium_kernel(typename P::S* f, const double* rho, const double* uz,
+                                        const double* ur, long long n, double rho_ref) {
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const double r = rho[x];
+    const double vz = uz ? uz[x] : 0.0;
+    const double vr = ur ? ur[x] : 0.0;
+    const double qq = 1.5 * (vz * vz + vr * vr);
+#pragma unroll
+    for (int i = 0; i < lbm::kQ; ++i) {
+        const double cu = lbm::cz(i) * vz + lbm::cr(i) * vr;
+        const double poly = 3.0 * cu + 4.5 * cu * cu - qq;
+        const double w = lbm::weight(i);
+        double v = P::kShift ? w * ((r - rho_ref) + r * poly) : w * r * (1.0 + poly);
+        f[(long long)i * n + x] = typename P::S(v);
+    }
+}
+
+// fixed-order sum of the per-block partials into out[4]
+__global__ void finalize_reduce_kernel(const double* partials, int nblocks, double* out) {
+    __shared__ double s[4][256];
+    const int t = threadIdx.x;
+    for (int m = 0; m < 4; ++m) {
+        double v = 0.0;
+        for (int b = t; b < nblocks; b += 256) v += partials[(long long)b * 4 + m];
+        s[m][t] = v;
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int m = 0; m < 4; ++m) s[m][t] += s[m][t + w];
+        __syncthreads();
+    }
+    if (t < 4) out[t] = s[t][0];
+}
+
+}  // namespace
+
+struct lbm_axi_ctx {
+    lbm_axi_params p;
+    char* ws;
+    size_t ws_bytes;
+    Layout L;
+    int cur;  // index of the buffer holding the current state
+    hipStream_t stream;
+};
+
+namespace {
+
+void* state_ptr(lbm_axi_ctx* h, int which) { return h->ws + (which == 0 ? 0 : h->L.off_b); }
+
+lbm::StepArgs make_args(lbm_axi_ctx* h) {
+    lbm::StepArgs a{};
+    a.plane = (long long)h->p.nz * h->p.nr;
+    a.nz = h->p.nz;
+    a.nr = h->p.nr;
+    a.tiles_r = h->L.tiles_r;
+    a.big_nz = h->p.nz >= kTZ + 6 ? 1 : 0;
+    a.wall = h->p.wall;
+    a.axisym = h->p.axisym;
+    a.G = h->p.G;
+    a.tau = h->p.tau;
+    a.rho0 = h->p.psi_rho0;
+    a.gz = h->p.gz;
+    a.rho_ref = h->p.precision == LBM_AXI_FP64 ? 0.0 : h->p.rho_ref;
+    return a;
+}
+
+template <bool kMoments>
+int launch_tile(lbm_axi_ctx* h, const lbm::StepArgs& a) {
+    const dim3 grid(h->L.nblocks), block(256);
+    if (h->p.precision == LBM_AXI_FP64)
+        hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, kTZ, kTR64, kMoments>), grid, block, 0, h->stream, a);
+    else
+        hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, kTZ, kTR32, kMoments>), grid, block, 0, h->stream, a);
+    HIP_TRY(hipGetLastError(), "step kernel launch");
+    return LBM_AXI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_axi_workspace_bytes(const lbm_axi_params* p) {
+    if (check_params(p) != LBM_AXI_OK) return 0;
+    return layout_of(p).total;
+}
+
+int lbm_axi_create(const lbm_axi_params* p, const double* d_rho0, const double* d_uz0, const double* d_ur0,
+                   void* d_workspace, size_t ws_bytes, void* hip_stream, lbm_axi_t* out) {
+    int rc = check_params(p);
+    if (rc != LBM_AXI_OK) return rc;
+    if (!out) return fail(LBM_AXI_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d_rho0) return fail(LBM_AXI_EINVAL, "d_rho0 is NULL");
+    if (!d_workspace) return fail(LBM_AXI_EINVAL, "workspace is NULL");
+    if ((uintptr_t)d_workspace % kAlign != 0) return fail(LBM_AXI_EINVAL, "workspace must be 256-byte aligned");
+    const Layout L = layout_of(p);
+    if (ws_bytes < L.total)
+        return fail(LBM_AXI_ENOMEM, "workspace too small: %zu bytes, need %zu", ws_bytes, L.total);
+    auto* h = new (std::nothrow) lbm_axi_ctx{};
+    if (!h) return fail(LBM_AXI_ENOMEM, "host allocation failed");
+    h->p = *p;
+    h->ws = static_cast<char*>(d_workspace);
+    h->ws_bytes = ws_bytes;
+    h->L = L;
+    h->cur = 0;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    const long long n = (long long)p->nz * p->nr;
+    const int threads = 256;
+    const int blocks = (int)((n + threads - 1) / threads);
+    const double rho_ref = p->precision == LBM_AXI_FP64 ? 0.0 : p->rho_ref;
+    if (p->precision == LBM_AXI_FP64)
+        hipLaunchKernelGGL(init_equilibrium_kernel<lbm::PrecF64>, dim3(blocks), dim3(threads), 0, h->stream,
+                           static_cast<double*>(state_ptr(h, 0)), d_rho0, d_uz0, d_ur0, n, rho_ref);
+    else
+        hipLaunchKernelGGL(init_equilibrium_kernel<lbm::PrecF32S>, dim3(blocks), dim3(threads), 0, h->stream,
+                           static_cast<float*>(state_ptr(h, 0)), d_rho0, d_uz0, d_ur0, n, rho_ref);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "init kernel launch");
+    }
+    *out = h;
+    return LBM_AXI_OK;
+}
+
+int lbm_axi_step(lbm_axi_t h, int64_t n) {
+    if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
+    if (n < 0) return fail(LBM_AXI_EINVAL, "n must be >= 0");
+    lbm::StepArgs a = make_args(h);
+    for (int64_t s = 0; s < n; ++s) {
+        a.fin = state_ptr(h, h->cur);
+        a.fout = state_ptr(h, 1 - h->cur);
+        int rc = launch_tile<false>(h, a);
+        if (rc != LBM_AXI_OK) return rc;
+        h->cur = 1 - h->cur;
+    }
+    return LBM_AXI_OK;
+}
+
+int lbm_axi_moments(lbm_axi_t h, double* d_rho, double* d_uz, double* d_ur) {
+    if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
+    lbm::StepArgs a = make_args(h);
+    a.fin = state_ptr(h, h->cur);
+    a.rho_out = d_rho;
+    a.uz_out = d_uz;
+    a.ur_out = d_ur;
+    a.partials = nullptr;
+    return launch_tile<true>(h, a);
+}
+
+int lbm_axi_reduce(lbm_axi_t h, double* h_out) {
+    if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
+    if (!h_out) return fail(LBM_AXI_EINVAL, "h_out is NULL");
+    lbm::StepArgs a = make_args(h);
+    a.fin = state_ptr(h, h->cur);
+    a.partials = reinterpret_cast<double*>(h->ws + h->L.off_partials);
+    int rc = launch_tile<true>(h, a);
+    if (rc != LBM_AXI_OK) return rc;
+    double* d_red = reinterpret_cast<double*>(h->ws + h->L.off_red);
+    hipLaunchKernelGGL(finalize_reduce_kernel, dim3(1), dim3(256), 0, h->stream, a.partials, h->L.nblocks, d_red);
+    HIP_TRY(hipGetLastError(), "reduce kernel launch");
+    HIP_TRY(hipMemcpyAsync(h_out, d_red, LBM_AXI_NREDUCE * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+            "reduce copy");
+    HIP_TRY(hipStreamSynchronize(h->stream), "reduce synchronize");
+    for (int k = 0; k < LBM_AXI_NREDUCE; ++k)
+        if (!std::isfinite(h_out[k])) return fail(LBM_AXI_ENONFINITE, "diagnostic %d is not finite", k);
+    return LBM_AXI_OK;
+}
+
+size_t lbm_axi_state_bytes(lbm_axi_t h) { return h ? h->L.state_bytes : 0; }
+
+int lbm_axi_get_state(lbm_axi_t h, void* d_dst) {
+    if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
+    if (!d_dst) return fail(LBM_AXI_EINVAL, "d_dst is NULL");
+    HIP_TRY(hipMemcpyAsync(d_dst, state_ptr(h, h->cur), h->L.state_bytes, hipMemcpyDeviceToDevice, h->stream),
+            "get_state copy");
+    return LBM_AXI_OK;
+}
+
+int lbm_axi_set_state(lbm_axi_t h, const void* d_src) {
+    if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
+    if (!d_src) return fail(LBM_AXI_EINVAL, "d_src is NULL");
+    HIP_TRY(hipMemcpyAsync(state_ptr(h, h->cur), d_src, h->L.state_bytes, hipMemcpyDeviceToDevice, h->stream),
+            "set_state copy");
+    return LBM_AXI_OK;
+}
+
+int lbm_axi_set_stream(lbm_axi_t h, void* hip_stream) {
+    if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    return LBM_AXI_OK;
+}
+
+int lbm_axi_set_coupling(lbm_axi_t h, double G, double tau) {
+    if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
+    lbm_axi_params q = h->p;
+    q.G = G;
+    q.tau = tau;
+    int rc = check_params(&q);
+    if (rc != LBM_AXI_OK) return rc;
+    h->p = q;
+    return LBM_AXI_OK;
+}
+
+void lbm_axi_destroy(lbm_axi_t h) { delete h; }
+
+const char* lbm_axi_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,398 @@
+// Fused per-timestep kernel of the axisymmetric Shan–Chen lattice Boltzmann
+// method (Srivastava et al., arXiv:1310.1871, Sec. II).
+//
+// One workgroup owns a TZ x TR tile of nodes and does, entirely on chip:
+//   1. reads the post-streaming populations of the tile (kept in registers)
+//      and of a 6-node halo, and forms rho, psi(rho) (Sec. II.A) into LDS;
+//      halo rows below the axis and above the wall hold the mirrored values
+//      (symmetry rule at the axis, zero-derivative rule at the wall,
+//      Sec. II.E), columns wrap periodically;
+//   2. the isotropic d_r psi on a 4-node halo (Sec. II.D, first stencil);
+//   3. the total force F = F^SC (Eq. scforce) + F^{gamma,sym}
+//      (Eq. scAxisExtra, with d_rr = isotropic d_r of d_r and d_zr = 1D d_z of
+//      1D d_r, Sec. II.D) + rho g z^, and the hydrodynamic velocity
+//      u = (j + F/2)/rho (Eq. uhydro) on a 2-node halo; halo rows outside the
+//      domain take the mirrored velocity (u_z even, u_r odd at the axis, both
+//      even at the wall);
+//   4. per tile node: d_r u_z, d_z u_r, d_r u_r (isotropic stencil), the
+//      source h_i (Eqs. condition_h, H_terms), u^eq = (j + tau F)/rho
+//      (Eq. ueq), BGK collision (Eq. lbm2d_mod_new) and push-streaming into
+//      the other buffer with the mid-grid specular axis, bounce-back or
+//      specular wall and periodic z (Sec. II.E).
+// HBM traffic per node and step: 9 population reads + 9 writes; the halos
+// are re-read through L2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+struct StepArgs {
+    const void* fin;   // [9][nr][nz] storage type
+    void* fout;        // [9][nr][nz] storage type (step mode)
+    double* rho_out;   // moments mode, may be null
+    double* uz_out;
+    double* ur_out;
+    double* partials;  // moments mode: [gridDim.x][4] block sums, may be null
+    long long plane;   // nz * nr
+    int nz, nr;
+    int tiles_r;       // tiles along r (tile id = tz * tiles_r + tr)
+    int big_nz;        // 1 if nz >= TZ + 6: periodic wrap needs one add/sub
+    int wall;          // 0 no-slip, 1 free-slip
+    int axisym;        // 1 axisymmetric terms on
+    double G, tau, rho0, gz, rho_ref;
+};
+
+// storage / compute precision of a kernel instance
+template <class S_, class C_, bool kShift_>
+struct Prec {
+    using S = S_;
+    using C = C_;
+    static constexpr bool kShift = kShift_;  // storage holds f_i - W_i rho_ref
+};
+using PrecF64 = Prec<double, double, false>;
+using PrecF32S = Prec<float, float, true>;
+
+__device__ __forceinline__ double dev_exp(double x) { return exp(x); }
+__device__ __forceinline__ float dev_exp(float x) { return expf(x); }
+
+// hardware dispatches workgroup b to XCD b % 8; renumber so that each XCD
+// works on one contiguous run of tiles (neighbouring tiles share its L2)
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb >> 3, rem = nb & 7;
+    const int x = b & 7, k = b >> 3;
+    return x * q + (x < rem ? x : rem) + k;
+}
+
+__device__ __forceinline__ int wrap_z(int z, int nz, bool big) {
+    if (big) {
+        z = z < 0 ? z + nz : z;
+        return z >= nz ? z - nz : z;
+    }
+    int w = z % nz;
+    return w < 0 ? w + nz : w;
+}
+
+// row of the node whose value a (possibly ghost) row takes: mirror about
+// r = 0 below the axis and about r = nr above the wall; clamped into the
+// array for rows no real node ever reads (partial tiles)
+__device__ __forceinline__ int mirror_row(int y, int nr) {
+    y = y < 0 ? -1 - y : y;
+    y = y >= nr ? 2 * nr - 1 - y : y;
+    y = y < 0 ? 0 : y;
+    return y >= nr ? nr - 1 : y;
+}
+
+// isotropic first derivative (Sec. II.D): (1/36) sum_i (8 phi(x+c_i) -
+// phi(x+2 c_i)) c_i,axis, on an LDS window of row pitch W
+template <bool kAlongR, class C>
+__device__ __forceinline__ C d_iso(const C* __restrict__ E, int y, int x, int W) {
+    C s = C(0);
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) {
+        const int c = kAlongR ? cr(i) : cz(i);
+        if (c == 0) continue;
+        const C t = C(8) * E[(y + cr(i)) * W + x + cz(i)] - E[(y + 2 * cr(i)) * W + x + 2 * cz(i)];
+        s += c > 0 ? t : -t;
+    }
+    return s * C(1.0 / 36.0);
+}
+
+template <class P, int TZ, int TR, bool kMoments>
+__global__ __launch_bounds__(256) void axi_tile_kernel(const StepArgs a) {
+    using S = typename P::S;
+    using C = typename P::C;
+    constexpr int NT = 256;
+    constexpr int PZ = TZ + 12, PR = TR + 12;  // psi window (halo 6)
+    constexpr int DZ = TZ + 8, DR = TR + 8;    // d_r psi window (halo 4)
+    constexpr int UZ = TZ + 4, UR = TR + 4;    // velocity window (halo 2)
+    static_assert(NT % TZ == 0, "tile width must divide the workgroup");
+    constexpr int RSTEP = NT / TZ;
+    constexpr int NPT = TZ * TR / NT;          // tile nodes per thread
+    static_assert(NPT * NT == TZ * TR, "tile must be a multiple of the workgroup");
+
+    __shared__ C s_psi[PR * PZ];
+    __shared__ C s_dr[DR * DZ];
+    __shared__ C s_uz[UR * UZ];
+    __shared__ C s_ur[UR * UZ];
+
+    const S* __restrict__ fin = static_cast<const S*>(a.fin);
+    const long long n = a.plane;
+    const int nz = a.nz, nr = a.nr;
+    const bool big = a.big_nz != 0;
+    const int t = threadIdx.x;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tzi = tile / a.tiles_r;
+    const int z0 = tzi * TZ, r0 = (tile - tzi * a.tiles_r) * TR;
+    const C rho0 = C(a.rho0);
+    const C inv_rho0 = C(1.0 / a.rho0);
+    const C rho_ref = C(a.rho_ref);
+
+    auto psi_of = [&](C rho) { return rho0 * (C(1) - dev_exp(-rho * inv_rho0)); };
+
+    // ---- 1a. tile nodes: populations into registers, psi into LDS --------
+    const int lz = t % TZ, lrb = t / TZ;
+    C f[NPT][kQ];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int lr = lrb + k * RSTEP;
+        const int gz = wrap_z(z0 + lz, nz, big);
+        const int gr = mirror_row(r0 + lr, nr);
+        const S* p = fin + (long long)gr * nz + gz;
+        C rho = P::kShift ? rho_ref : C(0);
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            f[k][i] = C(p[i * n]);
+        }
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) rho += f[k][i];
+        s_psi[(lr + 6) * PZ + lz + 6] = psi_of(rho);
+    }
+
+    // ---- 1b. psi on the 6-node halo ring ---------------------------------
+    {
+        constexpr int NBAND = 12 * PZ;  // 6 rows below and 6 above the tile
+        constexpr int NSIDE = 12 * TR;  // 6 columns left and 6 right
+        for (int idx = t; idx < NBAND + NSIDE; idx += NT) {
+            int hr, hz;
+            if (idx < NBAND) {
+                const int b = idx / PZ;
+                hz = idx - b * PZ;
+                hr = b < 6 ? b : TR + b;
+            } else {
+                const int j = idx - NBAND;
+                const int side = j / (6 * TR);
+                const int jj = j - side * 6 * TR;
+                hr = 6 + jj / 6;
+                hz = (side ? TZ + 6 : 0) + (jj - (jj / 6) * 6);
+            }
+            const int gz = wrap_z(z0 - 6 + hz, nz, big);
+            const int gr = mirror_row(r0 - 6 + hr, nr);
+            const S* p = fin + (long long)gr * nz + gz;
+            C v[kQ];
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) v[i] = C(p[i * n]);
+            C rho = P::kShift ? rho_ref : C(0);
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) rho += v[i];
+            s_psi[hr * PZ + hz] = psi_of(rho);
+        }
+    }
+    __syncthreads();
+
+    // ---- 2. isotropic d_r psi on the 4-node halo -------------------------
+    for (int idx = t; idx < DR * DZ; idx += NT) {
+        const int y = idx / DZ, x = idx - y * DZ;
+        s_dr[idx] = d_iso<true>(s_psi, y + 2, x + 2, PZ);
+    }
+    __syncthreads();
+
+    // ---- 3. total force and hydrodynamic velocity ------------------------
+    const C G = C(a.G);
+    const C g18 = G * C(1.0 / 18.0);  // (G/2) c_s^4
+    const C gz_acc = C(a.gz);
+    // force at velocity-window coordinates (uy, ux) of a real row with
+    // radius rr
+    auto force_at = [&](int uy, int ux, C rho, C rr, C& Fz, C& Fr) {
+        const int py = uy + 4, px = ux + 4;  // psi window
+        const int dy = uy + 2, dx = ux + 2;  // d_r psi window
+        C sz = C(0), sr = C(0);
+#pragma unroll
+        for (int i = 1; i < kQ; ++i) {
+            const C ps = s_psi[(py + cr(i)) * PZ + px + cz(i)] * C(weight(i));
+            if (cz(i) != 0) sz += cz(i) > 0 ? ps : -ps;
+            if (cr(i) != 0) sr += cr(i) > 0 ? ps : -ps;
+        }
+        const C psi = s_psi[py * PZ + px];
+        Fz = -G * psi * sz;
+        Fr = -G * psi * sr;
+        if (a.axisym) {
+            const C dr1 = s_dr[dy * DZ + dx];
+            const C drr = d_iso<true>(s_dr, dy, dx, DZ);
+            // mixed derivative: 1D fourth-order d_z of the 1D fourth-order d_r
+            C d1[5];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                const int xx = px - 2 + m;
+                d1[m] = (-s_psi[(py + 2) * PZ + xx] + C(8) * s_psi[(py + 1) * PZ + xx] -
+                         C(8) * s_psi[(py - 1) * PZ + xx] + s_psi[(py - 2) * PZ + xx]) *
+                        C(1.0 / 12.0);
+            }
+            const C dzr = (-d1[4] + C(8) * d1[3] - C(8) * d1[1] + d1[0]) * C(1.0 / 12.0);
+            const C inv_r = C(1) / rr;
+            const C pre = -g18 * psi;
+            Fz += pre * dzr * inv_r;
+            Fr += pre * (drr * inv_r - dr1 * inv_r * inv_r);
+        }
+        Fz += rho * gz_acc;
+    };
+
+    C Fz_t[NPT], Fr_t[NPT];
+    // 3a. tile nodes whose row is real: density and momentum from registers
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int lr = lrb + k * RSTEP;
+        const int gr = r0 + lr;
+        if (gr < nr) {
+            C rho = P::kShift ? rho_ref : C(0), jz = C(0), jr = C(0);
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) rho += f[k][i];
+            jz = (f[k][1] - f[k][3]) + (f[k][5] - f[k][6]) + (f[k][8] - f[k][7]);
+            jr = (f[k][2] - f[k][4]) + (f[k][5] - f[k][8]) + (f[k][6] - f[k][7]);
+            C Fz, Fr;
+            force_at(lr + 2, lz + 2, rho, C(gr) + C(0.5), Fz, Fr);
+            Fz_t[k] = Fz;
+            Fr_t[k] = Fr;
+            const C inv_rho = C(1) / rho;
+            s_uz[(lr + 2) * UZ + lz + 2] = (jz + C(0.5) * Fz) * inv_rho;
+            s_ur[(lr + 2) * UZ + lz + 2] = (jr + C(0.5) * Fr) * inv_rho;
+        } else {
+            Fz_t[k] = C(0);
+            Fr_t[k] = C(0);
+        }
+    }
+    // 3b. every other velocity-window node: ghost rows take the value of
+    // their mirror row (u_r odd at the axis), computed again here
+    {
+        constexpr int NW = UR * UZ;
+        for (int idx = t; idx < NW; idx += NT) {
+            const int uy = idx / UZ, ux = idx - uy * UZ;
+            const int y = r0 - 2 + uy;
+            const bool in_tile = (uy >= 2 && uy < TR + 2 && ux >= 2 && ux < TZ + 2);
+            if (in_tile && y < nr) continue;  // done in 3a
+            int ys = y;
+            C sgn = C(1);
+            if (y < 0) {
+                ys = -1 - y;
+                sgn = C(-1);
+            } else if (y >= nr) {
+                ys = 2 * nr - 1 - y;
+            }
+            const int uys = ys - (r0 - 2);
+            if (ys < 0 || ys >= nr || uys < 0 || uys >= UR) {  // no real node reads this entry
+                s_uz[idx] = C(0);
+                s_ur[idx] = C(0);
+                continue;
+            }
+            const int gz = wrap_z(z0 - 2 + ux, nz, big);
+            const S* p = fin + (long long)ys * nz + gz;
+            C v[kQ];
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) v[i] = C(p[i * n]);
+            C rho = P::kShift ? rho_ref : C(0);
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) rho += v[i];
+            const C jz = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
+            const C jr = (v[2] - v[4]) + (v[5] - v[8]) + (v[6] - v[7]);
+            C Fz, Fr;
+            force_at(uys, ux, rho, C(ys) + C(0.5), Fz, Fr);
+            const C inv_rho = C(1) / rho;
+            s_uz[idx] = (jz + C(0.5) * Fz) * inv_rho;
+            s_ur[idx] = sgn * ((jr + C(0.5) * Fr) * inv_rho);
+        }
+    }
+    __syncthreads();
+
+    // ---- 4. collision + streaming (or moments) for the tile nodes --------
+    const C tau = C(a.tau);
+    const C inv_tau = C(1) / tau;
+    const C mu_fac = (tau - C(0.5)) * C(1.0 / 3.0);  // mu = rho c_s^2 (tau - 1/2)
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int lr = lrb + k * RSTEP;
+        const int gz = z0 + lz, gr = r0 + lr;
+        const bool valid = gz < nz && gr < nr;
+        if (!valid) continue;
+        const int uy = lr + 2, ux = lz + 2;
+        C rho = P::kShift ? rho_ref : C(0);
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) rho += f[k][i];
+        const C jz = (f[k][1] - f[k][3]) + (f[k][5] - f[k][6]) + (f[k][8] - f[k][7]);
+        const C jr = (f[k][2] - f[k][4]) + (f[k][5] - f[k][8]) + (f[k][6] - f[k][7]);
+        const C uz = s_uz[uy * UZ + ux], ur = s_ur[uy * UZ + ux];
+        const C rr = C(gr) + C(0.5);
+
+        if constexpr (kMoments) {
+            const long long x = (long long)gr * nz + gz;
+            if (a.rho_out) a.rho_out[x] = double(rho);
+            if (a.uz_out) a.uz_out[x] = double(uz);
+            if (a.ur_out) a.ur_out[x] = double(ur);
+            const double two_pi_r = 6.283185307179586 * double(rr);
+            part[0] += two_pi_r * double(rho);
+            part[1] += two_pi_r * double(rho) * double(uz);
+            part[2] += 0.5 * two_pi_r * double(rho) * (double(uz) * double(uz) + double(ur) * double(ur));
+            part[3] += double(rho);
+        } else {
+            const C Fz = Fz_t[k], Fr = Fr_t[k];
+            C hz = C(0), hr = C(0), mass = C(0);
+            if (a.axisym) {
+                const C druz = d_iso<true>(s_uz, uy, ux, UZ);
+                const C dzur = d_iso<false>(s_ur, uy, ux, UZ);
+                const C drur = d_iso<true>(s_ur, uy, ux, UZ);
+                const C inv_r = C(1) / rr;
+                const C mu = rho * mu_fac;
+                hz = (mu * (druz + dzur) - rho * ur * uz) * inv_r;
+                hr = (C(2) * mu * (drur - ur * inv_r) - rho * ur * ur) * inv_r;
+                mass = -rho * ur * inv_r;
+            }
+            const C inv_rho = C(1) / rho;
+            const C qz = (jz + tau * Fz) * inv_rho;
+            const C qr = (jr + tau * Fr) * inv_rho;
+            const C qq = C(1.5) * (qz * qz + qr * qr);
+            S* __restrict__ fout = static_cast<S*>(a.fout);
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                const C w = C(weight(i));
+                const C cu = C(cz(i)) * qz + C(cr(i)) * qr;
+                const C poly = C(3) * cu + C(4.5) * cu * cu - qq;
+                // f^eq(rho, u^eq) (Eq. e_distribution with u^eq throughout);
+                // in shifted storage, f^eq - W rho_ref
+                const C feq = P::kShift ? w * ((rho - rho_ref) + rho * poly) : w * rho * (C(1) + poly);
+                const C hi = w * (mass + C(3) * (C(cz(i)) * hz + C(cr(i)) * hr));
+                const C fs = f[k][i] - (f[k][i] - feq) * inv_tau + hi;
+                // push to the neighbour with the pre-streaming boundary rules
+                int tz = gz + cz(i), trr = gr + cr(i), d = i;
+                if (cr(i) < 0 && gr == 0) {
+                    trr = 0;
+                    d = mirror_r(i);
+                } else if (cr(i) > 0 && gr == nr - 1) {
+                    if (a.wall == 0) {
+                        tz = gz;
+                        trr = gr;
+                        d = opposite(i);
+                    } else {
+                        d = mirror_r(i);
+                        trr = gr;
+                    }
+                }
+                tz = tz < 0 ? tz + nz : (tz >= nz ? tz - nz : tz);
+                fout[(long long)d * n + (long long)trr * nz + tz] = S(fs);
+            }
+        }
+    }
+
+    if constexpr (kMoments) {
+        if (a.partials) {
+            __shared__ double s_red[4][NT / 64];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                double v = part[m];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+                if ((t & 63) == 0) s_red[m][t >> 6] = v;
+            }
+            __syncthreads();
+            if (t < 4) {
+                double v = 0.0;
+#pragma unroll
+                for (int w = 0; w < NT / 64; ++w) v += s_red[t][w];
+                a.partials[(long long)blockIdx.x * 4 + t] = v;
+            }
+        }
+    }
+}
+
+}  // namespace lbm

@@ -1,0 +1,213 @@
+"""Thin ctypes binding of the lbm_axi C ABI (include/lbm_axi.h).
+
+Argument marshalling only: PyTorch provides device memory and the stream,
+every step of the method runs in the HIP library.  Importing this module on
+a machine where the built library is missing raises ImportError; there is no
+CPU fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm_axi.so")
+
+OK = 0
+EINVAL = -1
+ENOMEM = -2
+EHIP = -3
+ENONFINITE = -4
+EUNSUP = -5
+
+WALL_NOSLIP = 0
+WALL_FREESLIP = 1
+FP64 = 0
+FP32_SHIFTED = 1
+NREDUCE = 4
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nz", ctypes.c_int32), ("nr", ctypes.c_int32),
+        ("G", ctypes.c_double), ("tau", ctypes.c_double),
+        ("psi_rho0", ctypes.c_double), ("gz", ctypes.c_double),
+        ("wall", ctypes.c_int32), ("axisym", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
+        ("rho_ref", ctypes.c_double),
+    ]
+
+
+def make_params(nz, nr, G=-5.5, tau=1.0, psi_rho0=1.0, gz=0.0, wall=WALL_NOSLIP, axisym=1,
+                precision=FP64, rho_ref=0.0, flags=0):
+    return Params(int(nz), int(nr), float(G), float(tau), float(psi_rho0), float(gz), int(wall),
+                  int(axisym), int(precision), int(flags), float(rho_ref))
+
+
+class LbmAxiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lbm_axi error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, P = ctypes.c_void_p, ctypes.POINTER(Params)
+    sigs = {
+        "lbm_axi_workspace_bytes": (ctypes.c_size_t, [P]),
+        "lbm_axi_create": (ctypes.c_int, [P, vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
+        "lbm_axi_step": (ctypes.c_int, [vp, ctypes.c_int64]),
+        "lbm_axi_moments": (ctypes.c_int, [vp, vp, vp, vp]),
+        "lbm_axi_reduce": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double)]),
+        "lbm_axi_state_bytes": (ctypes.c_size_t, [vp]),
+        "lbm_axi_get_state": (ctypes.c_int, [vp, vp]),
+        "lbm_axi_set_state": (ctypes.c_int, [vp, vp]),
+        "lbm_axi_set_stream": (ctypes.c_int, [vp, vp]),
+        "lbm_axi_set_coupling": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double]),
+        "lbm_axi_destroy": (None, [vp]),
+        "lbm_axi_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def last_error():
+    return lib.lbm_axi_last_error().decode()
+
+
+def check(rc):
+    if rc != OK:
+        raise LbmAxiError(rc, last_error())
+    return rc
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream_handle(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def workspace_bytes(params):
+    return int(lib.lbm_axi_workspace_bytes(ctypes.byref(params)))
+
+
+class AxiLBM:
+    """One axisymmetric Shan–Chen lattice on one GPU.
+
+    ``rho0``, ``uz0``, ``ur0`` are float64 tensors [nr, nz] (velocities may be
+    None) on the device; the populations start at f^eq(rho0, u0).
+    """
+
+    def __init__(self, params, rho0, uz0=None, ur0=None, device="cuda", stream=None):
+        self.params = params
+        self.device = torch.device(device)
+        nbytes = workspace_bytes(params)
+        if nbytes == 0:
+            raise LbmAxiError(EINVAL, last_error())
+        # uint8 storage; torch's caching allocator aligns blocks to >= 512 B
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream
+        rho0 = self._field(rho0)
+        uz0 = self._field(uz0) if uz0 is not None else None
+        ur0 = self._field(ur0) if ur0 is not None else None
+        h = ctypes.c_void_p()
+        check(lib.lbm_axi_create(ctypes.byref(params), _ptr(rho0), _ptr(uz0), _ptr(ur0),
+                                 _ptr(self.workspace), nbytes, _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self._keep = (rho0, uz0, ur0)  # inputs stay alive until the init kernel has run
+
+    def _field(self, a):
+        t = torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
+        if tuple(t.shape) != (self.params.nr, self.params.nz):
+            raise ValueError(f"field shape {tuple(t.shape)} != (nr, nz) = ({self.params.nr}, {self.params.nz})")
+        return t
+
+    @property
+    def nz(self):
+        return self.params.nz
+
+    @property
+    def nr(self):
+        return self.params.nr
+
+    def _sync_stream(self):
+        check(lib.lbm_axi_set_stream(self._h, _stream_handle(self.stream)))
+
+    def step(self, n=1):
+        self._sync_stream()
+        check(lib.lbm_axi_step(self._h, int(n)))
+
+    def moments(self):
+        """(rho, u_z, u_r) float64 tensors [nr, nz] of the current state."""
+        self._sync_stream()
+        shape = (self.nr, self.nz)
+        rho = torch.empty(shape, dtype=torch.float64, device=self.device)
+        uz = torch.empty_like(rho)
+        ur = torch.empty_like(rho)
+        check(lib.lbm_axi_moments(self._h, _ptr(rho), _ptr(uz), _ptr(ur)))
+        return rho, uz, ur
+
+    def reduce(self):
+        """[3D mass, 3D z-momentum, kinetic energy, 2D mass] as Python floats
+        (synchronises the stream)."""
+        self._sync_stream()
+        out = (ctypes.c_double * NREDUCE)()
+        rc = lib.lbm_axi_reduce(self._h, out)
+        vals = [float(v) for v in out]
+        if rc == ENONFINITE:
+            raise LbmAxiError(rc, last_error() + f" {vals}")
+        check(rc)
+        return vals
+
+    def state_bytes(self):
+        return int(lib.lbm_axi_state_bytes(self._h))
+
+    def get_state(self):
+        self._sync_stream()
+        dst = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        check(lib.lbm_axi_get_state(self._h, _ptr(dst)))
+        return dst
+
+    def set_state(self, src):
+        if src.numel() * src.element_size() != self.state_bytes() or not src.is_contiguous():
+            raise ValueError("state buffer of the wrong size or not contiguous")
+        self._sync_stream()
+        check(lib.lbm_axi_set_state(self._h, _ptr(src)))
+
+    def populations(self):
+        """Current populations as a float64 tensor [9, nr, nz] (the shift is
+        added back in FP32 storage)."""
+        raw = self.get_state()
+        if self.params.precision == FP64:
+            return raw.view(torch.float64).reshape(9, self.nr, self.nz).clone()
+        g = raw.view(torch.float32).reshape(9, self.nr, self.nz).to(torch.float64)
+        w = torch.tensor([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, dtype=torch.float64, device=self.device)
+        return g + w[:, None, None] * self.params.rho_ref
+
+    def set_coupling(self, G, tau):
+        check(lib.lbm_axi_set_coupling(self._h, float(G), float(tau)))
+        self.params.G = float(G)
+        self.params.tau = float(tau)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.lbm_axi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

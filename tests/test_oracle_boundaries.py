@@ -12,15 +12,17 @@ import oracle.diagnostics as D
 
 
 @pytest.mark.parametrize("wall", [0, 1])
-@pytest.mark.parametrize("G", [0.0, -5.5])
-def test_rest_state_is_invariant(wall, G):
+@pytest.mark.parametrize("G,rho_val", [(0.0, 0.83), (-5.5, 0.1), (-5.5, 2.3)])
+def test_rest_state_is_invariant(wall, G, rho_val):
     """Uniform density at rest: the Shan–Chen force, the derivative terms and
     the axisymmetric sources all vanish, and every boundary link returns a
     population of the same weight, so f stays W_i rho (to round-off) for 1000
     steps.  A wrong ghost rule for psi (e.g. zero ghosts at the wall) makes
-    the force non-zero on the boundary rows at the first step."""
+    the force non-zero on the boundary rows at the first step.  With G != 0
+    the density is taken outside the spinodal region (dp/drho > 0 for the
+    equation of state of Sec. II.A), where a uniform state is stable."""
     nz, nr = 10, 8
-    rho = np.full((nr, nz), 0.83)
+    rho = np.full((nr, nz), rho_val)
     p = O.make_params(nz, nr, G=G, tau=0.9, wall=wall, axisym=1)
     f0 = O.equilibrium(p, rho, 0 * rho, 0 * rho)
     f1 = O.run(p, f0, 1000)
