@@ -43,11 +43,12 @@ int hip_fail(hipError_t e, const char* what) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// tile shape of the fused kernel per precision
-constexpr int kTZ = 64;
-constexpr int kTR64 = 16;
-constexpr int kTR32 = 16;
+// tile shape and workgroup size of the fused kernel per precision (chosen
+// by timing on MI355X: 4096 x 512 thread workload)
+constexpr int kTZ64 = 64, kTR64 = 32, kNT64 = 512;
+constexpr int kTZ32 = 128, kTR32 = 16, kNT32 = 512;
 
+int tile_z(int precision) { return precision == LBM_AXI_FP64 ? kTZ64 : kTZ32; }
 int tile_r(int precision) { return precision == LBM_AXI_FP64 ? kTR64 : kTR32; }
 
 size_t storage_size(int precision) { return precision == LBM_AXI_FP64 ? sizeof(double) : sizeof(float); }
@@ -65,7 +66,8 @@ int check_params(const lbm_axi_params* p) {
     if (!p) return fail(LBM_AXI_EINVAL, "params is NULL");
     if (p->nz < 1) return fail(LBM_AXI_EINVAL, "nz must be >= 1 (got %d)", p->nz);
     if (p->nr < 6) return fail(LBM_AXI_EINVAL, "nr must be >= 6 for the derivative stencils (got %d)", p->nr);
-    if ((long long)p->nz * p->nr > (1LL << 30)) return fail(LBM_AXI_EINVAL, "grid too large");
+    if (9.0 * (double)p->nz * (double)p->nr * (p->precision == LBM_AXI_FP64 ? 8.0 : 4.0) >= 4294967296.0)
+        return fail(LBM_AXI_EINVAL, "grid too large: the population state must stay below 4 GiB");
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_AXI_EINVAL, "tau must be > 1/2 (got %g)", p->tau);
     if (!std::isfinite(p->G)) return fail(LBM_AXI_EINVAL, "G must be finite");
     if (!(p->psi_rho0 > 0.0) || !std::isfinite(p->psi_rho0)) return fail(LBM_AXI_EINVAL, "psi_rho0 must be > 0");
@@ -84,7 +86,7 @@ Layout layout_of(const lbm_axi_params* p) {
     Layout L{};
     const size_t n = (size_t)p->nz * p->nr;
     L.state_bytes = 9 * n * storage_size(p->precision);
-    L.tiles_z = (p->nz + kTZ - 1) / kTZ;
+    L.tiles_z = (p->nz + tile_z(p->precision) - 1) / tile_z(p->precision);
     L.tiles_r = (p->nr + tile_r(p->precision) - 1) / tile_r(p->precision);
     L.nblocks = L.tiles_z * L.tiles_r;
     L.off_b = align_up(L.state_bytes);
@@ -150,10 +152,11 @@ void* state_ptr(lbm_axi_ctx* h, int which) { return h->ws + (which == 0 ? 0 : h-
 lbm::StepArgs make_args(lbm_axi_ctx* h) {
     lbm::StepArgs a{};
     a.plane = (long long)h->p.nz * h->p.nr;
+    a.state_bytes = (unsigned)h->L.state_bytes;
     a.nz = h->p.nz;
     a.nr = h->p.nr;
     a.tiles_r = h->L.tiles_r;
-    a.big_nz = h->p.nz >= kTZ + 6 ? 1 : 0;
+    a.big_nz = h->p.nz >= tile_z(h->p.precision) + 6 ? 1 : 0;
     a.wall = h->p.wall;
     a.axisym = h->p.axisym;
     a.G = h->p.G;
@@ -166,11 +169,13 @@ lbm::StepArgs make_args(lbm_axi_ctx* h) {
 
 template <bool kMoments>
 int launch_tile(lbm_axi_ctx* h, const lbm::StepArgs& a) {
-    const dim3 grid(h->L.nblocks), block(256);
+    const dim3 grid(h->L.nblocks);
     if (h->p.precision == LBM_AXI_FP64)
-        hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, kTZ, kTR64, kMoments>), grid, block, 0, h->stream, a);
+        hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, kTZ64, kTR64, kNT64, kMoments>), grid, dim3(kNT64), 0,
+                           h->stream, a);
     else
-        hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, kTZ, kTR32, kMoments>), grid, block, 0, h->stream, a);
+        hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, kTZ32, kTR32, kNT32, kMoments>), grid, dim3(kNT32), 0,
+                           h->stream, a);
     HIP_TRY(hipGetLastError(), "step kernel launch");
     return LBM_AXI_OK;
 }

@@ -37,6 +37,7 @@ struct StepArgs {
     double* ur_out;
     double* partials;  // moments mode: [gridDim.x][4] block sums, may be null
     long long plane;   // nz * nr
+    unsigned state_bytes;  // 9 * plane * sizeof(storage) (< 4 GiB)
     int nz, nr;
     int tiles_r;       // tiles along r (tile id = tz * tiles_r + tr)
     int big_nz;        // 1 if nz >= TZ + 6: periodic wrap needs one add/sub
@@ -57,6 +58,21 @@ using PrecF32S = Prec<float, float, true>;
 
 __device__ __forceinline__ double dev_exp(double x) { return exp(x); }
 __device__ __forceinline__ float dev_exp(float x) { return expf(x); }
+
+// 1/x from the hardware reciprocal refined by Newton steps (error well
+// below 1e-15 relative in FP64), cheaper than an IEEE divide
+__device__ __forceinline__ double dev_rcp(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-x, y, 1.0);
+    return __builtin_fma(y, e, y);
+}
+__device__ __forceinline__ float dev_rcp(float x) {
+    float y = __builtin_amdgcn_rcpf(x);
+    float e = __builtin_fmaf(-x, y, 1.0f);
+    return __builtin_fmaf(y, e, y);
+}
 
 // hardware dispatches workgroup b to XCD b % 8; renumber so that each XCD
 // works on one contiguous run of tiles (neighbouring tiles share its L2)
@@ -100,11 +116,32 @@ __device__ __forceinline__ C d_iso(const C* __restrict__ E, int y, int x, int W)
     return s * C(1.0 / 36.0);
 }
 
-template <class P, int TZ, int TR, bool kMoments>
-__global__ __launch_bounds__(256) void axi_tile_kernel(const StepArgs a) {
+// Populations are addressed through a buffer resource: the base and the
+// plane offset i * plane * sizeof(S) are wave-uniform (scalar registers), the
+// per-lane byte offset is 32-bit, so each load or store needs no vector
+// address arithmetic.  Offsets beyond the buffer read as zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
+template <class P, int TZ, int TR, int NT, bool kMoments>
+__global__ __launch_bounds__(NT) void axi_tile_kernel(const StepArgs a) {
     using S = typename P::S;
     using C = typename P::C;
-    constexpr int NT = 256;
     constexpr int PZ = TZ + 12, PR = TR + 12;  // psi window (halo 6)
     constexpr int DZ = TZ + 8, DR = TR + 8;    // d_r psi window (halo 4)
     constexpr int UZ = TZ + 4, UR = TR + 4;    // velocity window (halo 2)
@@ -118,7 +155,8 @@ __global__ __launch_bounds__(256) void axi_tile_kernel(const StepArgs a) {
     __shared__ C s_uz[UR * UZ];
     __shared__ C s_ur[UR * UZ];
 
-    const S* __restrict__ fin = static_cast<const S*>(a.fin);
+    const __amdgpu_buffer_rsrc_t fin = pop_rsrc(a.fin, a.state_bytes);
+    const unsigned plane_bytes = (unsigned)a.plane * (unsigned)sizeof(S);
     const long long n = a.plane;
     const int nz = a.nz, nr = a.nr;
     const bool big = a.big_nz != 0;
@@ -132,30 +170,24 @@ __global__ __launch_bounds__(256) void axi_tile_kernel(const StepArgs a) {
 
     auto psi_of = [&](C rho) { return rho0 * (C(1) - dev_exp(-rho * inv_rho0)); };
 
-    // ---- 1a. tile nodes: populations into registers, psi into LDS --------
-    const int lz = t % TZ, lrb = t / TZ;
-    C f[NPT][kQ];
+    auto rho_of = [&](const C* v) {
+        C s = C(0);
 #pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-        const int lr = lrb + k * RSTEP;
-        const int gz = wrap_z(z0 + lz, nz, big);
-        const int gr = mirror_row(r0 + lr, nr);
-        const S* p = fin + (long long)gr * nz + gz;
-        C rho = P::kShift ? rho_ref : C(0);
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-            f[k][i] = C(p[i * n]);
-        }
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) rho += f[k][i];
-        s_psi[(lr + 6) * PZ + lz + 6] = psi_of(rho);
-    }
+        for (int i = 0; i < kQ; ++i) s += v[i];
+        return P::kShift ? s + rho_ref : s;
+    };
 
-    // ---- 1b. psi on the 6-node halo ring ---------------------------------
+    // ---- 1a. psi on the 6-node halo ring (loads issued before use) -------
     {
         constexpr int NBAND = 12 * PZ;  // 6 rows below and 6 above the tile
         constexpr int NSIDE = 12 * TR;  // 6 columns left and 6 right
-        for (int idx = t; idx < NBAND + NSIDE; idx += NT) {
+        constexpr int NRING = NBAND + NSIDE;
+        constexpr int NIT = (NRING + NT - 1) / NT;
+        C v[NIT][kQ];
+        int slot[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int idx = t + it * NT;
             int hr, hz;
             if (idx < NBAND) {
                 const int b = idx / PZ;
@@ -168,18 +200,33 @@ __global__ __launch_bounds__(256) void axi_tile_kernel(const StepArgs a) {
                 hr = 6 + jj / 6;
                 hz = (side ? TZ + 6 : 0) + (jj - (jj / 6) * 6);
             }
+            const bool live = idx < NRING;
+            slot[it] = live ? hr * PZ + hz : -1;
             const int gz = wrap_z(z0 - 6 + hz, nz, big);
-            const int gr = mirror_row(r0 - 6 + hr, nr);
-            const S* p = fin + (long long)gr * nz + gz;
-            C v[kQ];
+            const int gr = mirror_row(r0 - 6 + (live ? hr : 6), nr);
+            const unsigned node = (unsigned)(gr * nz + gz);
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) v[i] = C(p[i * n]);
-            C rho = P::kShift ? rho_ref : C(0);
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) rho += v[i];
-            s_psi[hr * PZ + hz] = psi_of(rho);
+            for (int i = 0; i < kQ; ++i) v[it][i] = live ? C(buf_load(fin, node * (unsigned)sizeof(S), i * plane_bytes, S())) : C(0);
         }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it)
+            if (slot[it] >= 0) s_psi[slot[it]] = psi_of(rho_of(v[it]));
     }
+
+    // ---- 1b. tile nodes: populations into registers, psi into LDS --------
+    const int lz = t % TZ, lrb = t / TZ;
+    C f[NPT][kQ];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int lr = lrb + k * RSTEP;
+        const int gz = wrap_z(z0 + lz, nz, big);
+        const int gr = mirror_row(r0 + lr, nr);
+        const unsigned node = (unsigned)(gr * nz + gz);
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) f[k][i] = C(buf_load(fin, node * (unsigned)sizeof(S), i * plane_bytes, S()));
+    }
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) s_psi[(lrb + k * RSTEP + 6) * PZ + lz + 6] = psi_of(rho_of(f[k]));
     __syncthreads();
 
     // ---- 2. isotropic d_r psi on the 4-node halo -------------------------
@@ -221,7 +268,7 @@ __global__ __launch_bounds__(256) void axi_tile_kernel(const StepArgs a) {
                         C(1.0 / 12.0);
             }
             const C dzr = (-d1[4] + C(8) * d1[3] - C(8) * d1[1] + d1[0]) * C(1.0 / 12.0);
-            const C inv_r = C(1) / rr;
+            const C inv_r = dev_rcp(rr);
             const C pre = -g18 * psi;
             Fz += pre * dzr * inv_r;
             Fr += pre * (drr * inv_r - dr1 * inv_r * inv_r);
@@ -229,68 +276,100 @@ __global__ __launch_bounds__(256) void axi_tile_kernel(const StepArgs a) {
         Fz += rho * gz_acc;
     };
 
+    // velocity at window node (uy, ux) of a row outside the tile's real
+    // rows: ghost rows take the value of their mirror row (u_r odd at the
+    // axis, even at the wall), computed again here from reloaded populations
+    auto ghost_velocity = [&](int uy, int ux) {
+        const int y = r0 - 2 + uy;
+        int ys = y;
+        C sgn = C(1);
+        if (y < 0) {
+            ys = -1 - y;
+            sgn = C(-1);
+        } else if (y >= nr) {
+            ys = 2 * nr - 1 - y;
+        }
+        const int uys = ys - (r0 - 2);
+        const int o = uy * UZ + ux;
+        if (ys < 0 || ys >= nr || uys < 0 || uys >= UR) {  // no real node reads this entry
+            s_uz[o] = C(0);
+            s_ur[o] = C(0);
+            return;
+        }
+        const int gz = wrap_z(z0 - 2 + ux, nz, big);
+        const unsigned node = (unsigned)(ys * nz + gz);
+        C v[kQ];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) v[i] = C(buf_load(fin, node * (unsigned)sizeof(S), i * plane_bytes, S()));
+        const C rho = rho_of(v);
+        const C jz = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
+        const C jr = (v[2] - v[4]) + (v[5] - v[8]) + (v[6] - v[7]);
+        C Fz, Fr;
+        force_at(uys, ux, rho, C(ys) + C(0.5), Fz, Fr);
+        const C inv_rho = dev_rcp(rho);
+        s_uz[o] = (jz + C(0.5) * Fz) * inv_rho;
+        s_ur[o] = sgn * ((jr + C(0.5) * Fr) * inv_rho);
+    };
+
     C Fz_t[NPT], Fr_t[NPT];
-    // 3a. tile nodes whose row is real: density and momentum from registers
+    // 3a. tile nodes; rows of real nodes use the populations in registers
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int lr = lrb + k * RSTEP;
         const int gr = r0 + lr;
+        Fz_t[k] = C(0);
+        Fr_t[k] = C(0);
         if (gr < nr) {
-            C rho = P::kShift ? rho_ref : C(0), jz = C(0), jr = C(0);
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) rho += f[k][i];
-            jz = (f[k][1] - f[k][3]) + (f[k][5] - f[k][6]) + (f[k][8] - f[k][7]);
-            jr = (f[k][2] - f[k][4]) + (f[k][5] - f[k][8]) + (f[k][6] - f[k][7]);
+            const C rho = rho_of(f[k]);
+            const C jz = (f[k][1] - f[k][3]) + (f[k][5] - f[k][6]) + (f[k][8] - f[k][7]);
+            const C jr = (f[k][2] - f[k][4]) + (f[k][5] - f[k][8]) + (f[k][6] - f[k][7]);
             C Fz, Fr;
             force_at(lr + 2, lz + 2, rho, C(gr) + C(0.5), Fz, Fr);
             Fz_t[k] = Fz;
             Fr_t[k] = Fr;
-            const C inv_rho = C(1) / rho;
+            const C inv_rho = dev_rcp(rho);
             s_uz[(lr + 2) * UZ + lz + 2] = (jz + C(0.5) * Fz) * inv_rho;
             s_ur[(lr + 2) * UZ + lz + 2] = (jr + C(0.5) * Fr) * inv_rho;
         } else {
-            Fz_t[k] = C(0);
-            Fr_t[k] = C(0);
+            ghost_velocity(lr + 2, lz + 2);
         }
     }
-    // 3b. every other velocity-window node: ghost rows take the value of
-    // their mirror row (u_r odd at the axis), computed again here
+    // 3b. the 2-node ring of the velocity window
     {
-        constexpr int NW = UR * UZ;
-        for (int idx = t; idx < NW; idx += NT) {
-            const int uy = idx / UZ, ux = idx - uy * UZ;
+        constexpr int NB = 4 * UZ;   // 2 rows below and 2 above the tile
+        constexpr int NS = 4 * TR;   // 2 columns left and 2 right
+        for (int idx = t; idx < NB + NS; idx += NT) {
+            int uy, ux;
+            if (idx < NB) {
+                const int b = idx / UZ;
+                ux = idx - b * UZ;
+                uy = b < 2 ? b : TR + b;
+            } else {
+                const int j = idx - NB;
+                const int side = j / (2 * TR);
+                const int jj = j - side * 2 * TR;
+                uy = 2 + (jj >> 1);
+                ux = (side ? TZ + 2 : 0) + (jj & 1);
+            }
             const int y = r0 - 2 + uy;
-            const bool in_tile = (uy >= 2 && uy < TR + 2 && ux >= 2 && ux < TZ + 2);
-            if (in_tile && y < nr) continue;  // done in 3a
-            int ys = y;
-            C sgn = C(1);
-            if (y < 0) {
-                ys = -1 - y;
-                sgn = C(-1);
-            } else if (y >= nr) {
-                ys = 2 * nr - 1 - y;
-            }
-            const int uys = ys - (r0 - 2);
-            if (ys < 0 || ys >= nr || uys < 0 || uys >= UR) {  // no real node reads this entry
-                s_uz[idx] = C(0);
-                s_ur[idx] = C(0);
-                continue;
-            }
-            const int gz = wrap_z(z0 - 2 + ux, nz, big);
-            const S* p = fin + (long long)ys * nz + gz;
-            C v[kQ];
+            if (y >= 0 && y < nr) {
+                // real row: same arithmetic as the ghost path with ys = y
+                const int gz = wrap_z(z0 - 2 + ux, nz, big);
+                const unsigned node = (unsigned)(y * nz + gz);
+                C v[kQ];
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) v[i] = C(p[i * n]);
-            C rho = P::kShift ? rho_ref : C(0);
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) rho += v[i];
-            const C jz = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
-            const C jr = (v[2] - v[4]) + (v[5] - v[8]) + (v[6] - v[7]);
-            C Fz, Fr;
-            force_at(uys, ux, rho, C(ys) + C(0.5), Fz, Fr);
-            const C inv_rho = C(1) / rho;
-            s_uz[idx] = (jz + C(0.5) * Fz) * inv_rho;
-            s_ur[idx] = sgn * ((jr + C(0.5) * Fr) * inv_rho);
+                for (int i = 0; i < kQ; ++i) v[i] = C(buf_load(fin, node * (unsigned)sizeof(S), i * plane_bytes, S()));
+                const C rho = rho_of(v);
+                const C jz = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
+                const C jr = (v[2] - v[4]) + (v[5] - v[8]) + (v[6] - v[7]);
+                C Fz, Fr;
+                force_at(uy, ux, rho, C(y) + C(0.5), Fz, Fr);
+                const C inv_rho = dev_rcp(rho);
+                s_uz[uy * UZ + ux] = (jz + C(0.5) * Fz) * inv_rho;
+                s_ur[uy * UZ + ux] = (jr + C(0.5) * Fr) * inv_rho;
+            } else {
+                ghost_velocity(uy, ux);
+            }
         }
     }
     __syncthreads();
@@ -307,9 +386,7 @@ __global__ __launch_bounds__(256) void axi_tile_kernel(const StepArgs a) {
         const bool valid = gz < nz && gr < nr;
         if (!valid) continue;
         const int uy = lr + 2, ux = lz + 2;
-        C rho = P::kShift ? rho_ref : C(0);
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) rho += f[k][i];
+        const C rho = rho_of(f[k]);
         const C jz = (f[k][1] - f[k][3]) + (f[k][5] - f[k][6]) + (f[k][8] - f[k][7]);
         const C jr = (f[k][2] - f[k][4]) + (f[k][5] - f[k][8]) + (f[k][6] - f[k][7]);
         const C uz = s_uz[uy * UZ + ux], ur = s_ur[uy * UZ + ux];
@@ -332,17 +409,17 @@ __global__ __launch_bounds__(256) void axi_tile_kernel(const StepArgs a) {
                 const C druz = d_iso<true>(s_uz, uy, ux, UZ);
                 const C dzur = d_iso<false>(s_ur, uy, ux, UZ);
                 const C drur = d_iso<true>(s_ur, uy, ux, UZ);
-                const C inv_r = C(1) / rr;
+                const C inv_r = dev_rcp(rr);
                 const C mu = rho * mu_fac;
                 hz = (mu * (druz + dzur) - rho * ur * uz) * inv_r;
                 hr = (C(2) * mu * (drur - ur * inv_r) - rho * ur * ur) * inv_r;
                 mass = -rho * ur * inv_r;
             }
-            const C inv_rho = C(1) / rho;
+            const C inv_rho = dev_rcp(rho);
             const C qz = (jz + tau * Fz) * inv_rho;
             const C qr = (jr + tau * Fr) * inv_rho;
             const C qq = C(1.5) * (qz * qz + qr * qr);
-            S* __restrict__ fout = static_cast<S*>(a.fout);
+            const __amdgpu_buffer_rsrc_t fout = pop_rsrc(a.fout, a.state_bytes);
 #pragma unroll
             for (int i = 0; i < kQ; ++i) {
                 const C w = C(weight(i));
@@ -369,7 +446,7 @@ __global__ __launch_bounds__(256) void axi_tile_kernel(const StepArgs a) {
                     }
                 }
                 tz = tz < 0 ? tz + nz : (tz >= nz ? tz - nz : tz);
-                fout[(long long)d * n + (long long)trr * nz + tz] = S(fs);
+                buf_store(fout, (unsigned)(trr * nz + tz) * (unsigned)sizeof(S), d * plane_bytes, S(fs));
             }
         }
     }
