@@ -1,0 +1,89 @@
+/*
+ * lbm_axi adjoint — reverse-mode derivative of the axisymmetric Shan–Chen
+ * step and the interface-radius loss, FP64, on one MI355X.
+ *
+ * The forward step is the method of Srivastava et al. (arXiv:1310.1871,
+ * Sec. II; see lbm_axi.h).  These entry points differentiate it by hand:
+ * the vector-Jacobian product of one step with respect to the state and to
+ * (G, tau), the derivative of the initial equilibrium with respect to the
+ * initial density, and the ray-integral interface radius used as a shape
+ * observable (a reading: the paper fixes no interface-shape observable; its
+ * drop test measures the radial intercept A(t), Sec. IV.B).
+ *
+ * All arrays are FP64 device arrays unless the name starts with h_; states
+ * and adjoints are [9][nr][nz] (the library's population layout), fields
+ * [nr][nz].  The caller owns every buffer and the stream; calls are
+ * asynchronous on hip_stream.  Return codes are the LBM_AXI_* codes of
+ * lbm_axi.h.
+ */
+#ifndef LBM_AXI_ADJOINT_H
+#define LBM_AXI_ADJOINT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lbm_axi.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Bytes of FP64 scratch lbm_axi_adjoint_step needs for an nz x nr grid
+ * (recomputed forward fields and adjoint fields); 0 if the size is
+ * invalid. */
+size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr);
+
+/* One reverse step.  With f' = step(f; G, tau) (post-streaming states,
+ * lbm_axi_step's update), writes d_lam = (df'/df)^T d_lam_next and, if
+ * d_grad_acc is not NULL, adds <d_lam_next, df'/dG> and
+ * <d_lam_next, df'/dtau> to d_grad_acc[0] and d_grad_acc[1].  p must have
+ * precision LBM_AXI_FP64 (LBM_AXI_EUNSUP otherwise).  d_lam must not alias
+ * d_lam_next or d_f.  d_ws: at least lbm_axi_adjoint_workspace_bytes. */
+int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const double* d_lam_next, double* d_lam,
+                         double* d_grad_acc, void* d_ws, size_t ws_bytes, void* hip_stream);
+
+/* Adjoint of the initial equilibrium f_i = f^eq_i(rho0, u0) (appendix,
+ * Eq. e_distribution): d_rho0_bar = sum_i d_lam0_i df^eq_i/drho0.
+ * d_uz0 / d_ur0 may be NULL (zero initial velocity). */
+int lbm_axi_init_vjp(const double* d_lam0, const double* d_uz0, const double* d_ur0, int32_t nz, int32_t nr,
+                     double* d_rho0_bar, void* hip_stream);
+
+/* rho = sum_i f_i of a state (Eq. hydro_var). */
+int lbm_axi_density(const double* d_f, int32_t nz, int32_t nr, double* d_rho, void* hip_stream);
+
+/* Host-side construction of the ray-integral interface radius
+ *   r(theta_m) = sum_k ds * phi(zc + s_k cos theta_m, s_k sin theta_m),
+ *   s_k = (k + 1/2) ds, k < floor(s_max / ds),
+ * with phi the bilinear interpolant of node values (rows mirrored below row
+ * 0, clamped above the last row, z periodic), as a sparse matrix in host
+ * arrays: ray-major CSR (h_row_ptr[n_rays+1], h_col, h_val) and node-major
+ * CSR (h_node_ptr[n_nodes+1], h_nodes, h_node_row, h_node_val).  Call once
+ * with the array pointers NULL to get *h_nnz and *h_n_nodes, then with
+ * arrays of capacity cap >= nnz (LBM_AXI_ENOMEM otherwise). */
+int lbm_axi_ray_weights(int32_t nz, int32_t nr, double zc, const double* h_thetas, int32_t n_rays, double ds,
+                        double s_max, int32_t cap, int32_t* h_row_ptr, int32_t* h_col, double* h_val,
+                        int32_t* h_node_ptr, int32_t* h_nodes, int32_t* h_node_row, double* h_node_val,
+                        int32_t* h_nnz, int32_t* h_n_nodes);
+
+/* d_out[m] = sum_k val_mk (rho[col_mk] - rho_g) / (rho_l - rho_g) with the
+ * ray-major matrix on the device (fixed-order FP64 reduction). */
+int lbm_axi_ray_forward(const double* d_rho, int32_t n_rows, const int32_t* d_row_ptr, const int32_t* d_col,
+                        const double* d_val, double rho_l, double rho_g, double* d_out, void* hip_stream);
+
+/* Adjoint of lbm_axi_ray_forward applied to rho = sum_i f_i:
+ * d_lam_i(x) += sum_m d_rbar[m] w_mx / (rho_l - rho_g) for every direction
+ * i, with the node-major matrix on the device. */
+int lbm_axi_ray_vjp(const double* d_rbar, int32_t n_nodes, const int32_t* d_node_ptr, const int32_t* d_node_row,
+                    const double* d_node_val, const int32_t* d_nodes, double rho_l, double rho_g, int32_t nz,
+                    int32_t nr, double* d_lam, void* hip_stream);
+
+/* *d_loss += sum_m (d_r[m] - d_target[m])^2 and, if d_rbar is not NULL,
+ * d_rbar[m] = 2 (d_r[m] - d_target[m]) (FP64). */
+int lbm_axi_misfit(const double* d_r, const double* d_target, int32_t m, double* d_loss, double* d_rbar,
+                   void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_AXI_ADJOINT_H */

@@ -1,0 +1,728 @@
+// Hand-written adjoint (vector-Jacobian product) of one time step of the
+// axisymmetric Shan–Chen scheme, FP64.
+//
+// Forward step (Sec. II): f* = C(f; G, tau), f_next = S(f*), with C the
+// collision with all its force and source terms and S the push streaming
+// with the boundary rules of Sec. II.E.  Given lam_next = dL/df_next the
+// kernels below produce lam = (df_next/df)^T lam_next and accumulate
+// dL/dG and dL/dtau.
+//
+// The reverse pass follows the forward data flow backwards:
+//   1. forward intermediates at the current state are recomputed into
+//      FP64 fields (rho, j, psi, d_r psi on the ghost-extended rows, d_rr,
+//      the 1D d_r and d_zr, force, u, u^eq, velocity derivatives);
+//   2. nu = S^T lam_next is gathered (S is a permutation);
+//   3. the collision, equilibrium and source terms are reversed node by
+//      node;
+//   4. every stencil is transposed into a gather: the adjoint of a ghost
+//      (mirrored) value is added back onto the real node it mirrors, with
+//      the same parity sign the forward extension used;
+//   5. psi-bar becomes rho-bar through psi'(rho) = exp(-rho/rho0), and
+//      lam_i = f-bar_i + rho-bar + c_i . j-bar.
+// Every kernel is one thread per node; no atomics, so results are
+// deterministic.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <map>
+#include <vector>
+
+#include "../../include/lbm_axi.h"
+#include "../../include/lbm_axi_adjoint.h"
+#include "lattice.hpp"
+
+namespace {
+
+constexpr int NGA = 6;  // ghost rows kept on extended adjoint fields
+
+struct AdjArgs {
+    int nz, nr;
+    long long n;    // nz * nr
+    long long ne;   // nz * (nr + 2 NGA)
+    double G, tau, rho0, gz;
+    int wall, axisym;
+    const double* f;         // [9][n] state f^t
+    const double* lam_next;  // [9][n]
+    double* lam;             // [9][n]
+    double* w;               // field workspace
+};
+
+// field slots inside the workspace (each n doubles)
+enum Slot {
+    S_RHO, S_JZ, S_JR, S_PSI, S_DRR, S_D1, S_DZR, S_FZ, S_FR, S_SCZ, S_SCR, S_UZ, S_UR, S_QZ, S_QR,
+    S_DRUZ, S_DZUR, S_DRUR,
+    // adjoints
+    S_RHOB, S_JZB, S_JRB, S_UZB_H, S_URB_H, S_FZB, S_FRB, S_DRUZB, S_DZURB, S_DRURB,
+    S_PSIB_LOC, S_DZRB, S_DRRB, S_DRB_REAL, S_D1B, S_FSCZB, S_FSCRB, S_GB, S_TAUB,
+    S_NSLOT
+};
+// extended slots (ne doubles each), after the plain ones
+enum SlotE { E_PSI, E_DR, E_UZ, E_UR, E_DRB, E_NSLOT };
+// after the extended slots: the partial f-bar, a population-sized field
+__host__ __device__ inline size_t slot_off(int s, long long n) { return (size_t)s * n; }
+__host__ __device__ inline size_t eslot_off(int s, long long n, long long ne) { return (size_t)S_NSLOT * n + (size_t)s * ne; }
+__host__ __device__ inline size_t fbar_off(long long n, long long ne) { return (size_t)S_NSLOT * n + (size_t)E_NSLOT * ne; }
+
+__device__ __forceinline__ int wrapz(int z, int nz) {
+    int w = z % nz;
+    return w < 0 ? w + nz : w;
+}
+__device__ __forceinline__ int mirror_src(int y, int nr, double& sgn, double axis_sign) {
+    sgn = 1.0;
+    if (y < 0) {
+        sgn = axis_sign;
+        return -1 - y;
+    }
+    if (y >= nr) return 2 * nr - 1 - y;
+    return y;
+}
+// extended-field index of row y (-NGA <= y < nr + NGA), column z
+__device__ __forceinline__ long long eidx(int y, int z, int nz) { return (long long)(y + NGA) * nz + z; }
+
+#define NODE_LOOP(a)                                                 \
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; \
+    if (x >= (a).n) return;                                          \
+    const int r = (int)(x / (a).nz), z = (int)(x - (long long)r * (a).nz);
+
+// isotropic first derivative at (z, y) of an extended field (Sec. II.D)
+__device__ double d_iso_e(const double* E, int z, int y, int nz, bool along_r) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 1; i < lbm::kQ; ++i) {
+        const int c = along_r ? lbm::cr(i) : lbm::cz(i);
+        if (c == 0) continue;
+        const double t = 8.0 * E[eidx(y + lbm::cr(i), wrapz(z + lbm::cz(i), nz), nz)] -
+                         E[eidx(y + 2 * lbm::cr(i), wrapz(z + 2 * lbm::cz(i), nz), nz)];
+        s += c * t;
+    }
+    return s / 36.0;
+}
+
+// ------------------------------------------------------------ forward ----
+
+__global__ void fwd_moments(AdjArgs a) {
+    NODE_LOOP(a)
+    double* w = a.w;
+    const long long n = a.n;
+    double rho = 0, jz = 0, jr = 0;
+#pragma unroll
+    for (int i = 0; i < lbm::kQ; ++i) {
+        const double fi = a.f[i * n + x];
+        rho += fi;
+        jz += lbm::cz(i) * fi;
+        jr += lbm::cr(i) * fi;
+    }
+    w[slot_off(S_RHO, n) + x] = rho;
+    w[slot_off(S_JZ, n) + x] = jz;
+    w[slot_off(S_JR, n) + x] = jr;
+    w[slot_off(S_PSI, n) + x] = a.rho0 * (1.0 - exp(-rho / a.rho0));
+}
+
+// extended copy of a real-row field with mirror parity at the axis and an
+// even mirror at the wall
+__global__ void fwd_extend(AdjArgs a, int src_slot, int dst_eslot, double axis_sign) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.ne) return;
+    const int y = (int)(e / a.nz) - NGA, z = (int)(e - (long long)(y + NGA) * a.nz);
+    double sgn;
+    const int ys = mirror_src(y, a.nr, sgn, axis_sign);
+    a.w[eslot_off(dst_eslot, a.n, a.ne) + e] = sgn * a.w[slot_off(src_slot, a.n) + (long long)ys * a.nz + z];
+}
+
+// isotropic d_r psi on extended rows -4 .. nr+3 (zero elsewhere)
+__global__ void fwd_dr(AdjArgs a) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.ne) return;
+    const int y = (int)(e / a.nz) - NGA, z = (int)(e - (long long)(y + NGA) * a.nz);
+    const double* psiE = a.w + eslot_off(E_PSI, a.n, a.ne);
+    double v = 0.0;
+    if (y >= -4 && y < a.nr + 4) v = d_iso_e(psiE, z, y, a.nz, true);
+    a.w[eslot_off(E_DR, a.n, a.ne) + e] = v;
+}
+
+__global__ void fwd_second(AdjArgs a) {
+    NODE_LOOP(a)
+    const double* psiE = a.w + eslot_off(E_PSI, a.n, a.ne);
+    const double* drE = a.w + eslot_off(E_DR, a.n, a.ne);
+    a.w[slot_off(S_DRR, a.n) + x] = d_iso_e(drE, z, r, a.nz, true);
+    a.w[slot_off(S_D1, a.n) + x] = (-psiE[eidx(r + 2, z, a.nz)] + 8.0 * psiE[eidx(r + 1, z, a.nz)] -
+                                    8.0 * psiE[eidx(r - 1, z, a.nz)] + psiE[eidx(r - 2, z, a.nz)]) / 12.0;
+}
+
+__global__ void fwd_force(AdjArgs a) {
+    NODE_LOOP(a)
+    double* w = a.w;
+    const long long n = a.n;
+    const int nz = a.nz;
+    const double* d1 = w + slot_off(S_D1, n) + (long long)r * nz;
+    const double dzr = (-d1[wrapz(z + 2, nz)] + 8.0 * d1[wrapz(z + 1, nz)] - 8.0 * d1[wrapz(z - 1, nz)] +
+                        d1[wrapz(z - 2, nz)]) / 12.0;
+    w[slot_off(S_DZR, n) + x] = dzr;
+    const double* psiE = w + eslot_off(E_PSI, n, a.ne);
+    double sz = 0, sr = 0;
+#pragma unroll
+    for (int i = 1; i < lbm::kQ; ++i) {
+        const double ps = psiE[eidx(r + lbm::cr(i), wrapz(z + lbm::cz(i), nz), nz)];
+        sz += lbm::weight(i) * ps * lbm::cz(i);
+        sr += lbm::weight(i) * ps * lbm::cr(i);
+    }
+    const double psi = w[slot_off(S_PSI, n) + x], rho = w[slot_off(S_RHO, n) + x];
+    w[slot_off(S_SCZ, n) + x] = sz;
+    w[slot_off(S_SCR, n) + x] = sr;
+    double Fz = -a.G * psi * sz, Fr = -a.G * psi * sr;
+    if (a.axisym) {
+        const double rr = r + 0.5;
+        const double dr1 = w[eslot_off(E_DR, n, a.ne) + eidx(r, z, nz)];
+        const double drr = w[slot_off(S_DRR, n) + x];
+        Fz += -(a.G / 18.0) * psi * dzr / rr;
+        Fr += -(a.G / 18.0) * psi * (drr / rr - dr1 / (rr * rr));
+    }
+    Fz += rho * a.gz;
+    w[slot_off(S_FZ, n) + x] = Fz;
+    w[slot_off(S_FR, n) + x] = Fr;
+    const double jz = w[slot_off(S_JZ, n) + x], jr = w[slot_off(S_JR, n) + x];
+    w[slot_off(S_UZ, n) + x] = (jz + 0.5 * Fz) / rho;
+    w[slot_off(S_UR, n) + x] = (jr + 0.5 * Fr) / rho;
+    w[slot_off(S_QZ, n) + x] = (jz + a.tau * Fz) / rho;
+    w[slot_off(S_QR, n) + x] = (jr + a.tau * Fr) / rho;
+}
+
+__global__ void fwd_velocity_gradients(AdjArgs a) {
+    NODE_LOOP(a)
+    const double* uzE = a.w + eslot_off(E_UZ, a.n, a.ne);
+    const double* urE = a.w + eslot_off(E_UR, a.n, a.ne);
+    a.w[slot_off(S_DRUZ, a.n) + x] = d_iso_e(uzE, z, r, a.nz, true);
+    a.w[slot_off(S_DZUR, a.n) + x] = d_iso_e(urE, z, r, a.nz, false);
+    a.w[slot_off(S_DRUR, a.n) + x] = d_iso_e(urE, z, r, a.nz, true);
+}
+
+// ------------------------------------------------------------ reverse ----
+
+// push target of (node (z, r), direction i) under the boundary rules
+__device__ __forceinline__ void push_target(int z, int r, int i, int nz, int nr, int wall, int& tz, int& tr,
+                                            int& d) {
+    tz = z + lbm::cz(i);
+    tr = r + lbm::cr(i);
+    d = i;
+    if (tr < 0) {
+        tr = 0;
+        d = lbm::mirror_r(i);
+    } else if (tr >= nr) {
+        if (wall == 0) {
+            tz = z;
+            tr = r;
+            d = lbm::opposite(i);
+        } else {
+            tr = nr - 1;
+            d = lbm::mirror_r(i);
+        }
+    }
+    tz = wrapz(tz, nz);
+}
+
+// steps 2-3: streaming transpose, BGK / equilibrium / source reversed
+__global__ void rev_collision(AdjArgs a) {
+    NODE_LOOP(a)
+    double* w = a.w;
+    const long long n = a.n;
+    const double tau = a.tau, inv_tau = 1.0 / tau;
+    const double rho = w[slot_off(S_RHO, n) + x];
+    const double qz = w[slot_off(S_QZ, n) + x], qr = w[slot_off(S_QR, n) + x];
+    const double uz = w[slot_off(S_UZ, n) + x], ur = w[slot_off(S_UR, n) + x];
+    const double rr = r + 0.5;
+    double* fbar = w + fbar_off(n, a.ne);
+
+    double rhob = 0, qzb = 0, qrb = 0, taub = 0, massb = 0, hzb = 0, hrb = 0;
+    const double qq = 1.5 * (qz * qz + qr * qr);
+#pragma unroll
+    for (int i = 0; i < lbm::kQ; ++i) {
+        int tz, tr, d;
+        push_target(z, r, i, a.nz, a.nr, a.wall, tz, tr, d);
+        const double nu = a.lam_next[d * n + (long long)tr * a.nz + tz];
+        const double wi = lbm::weight(i);
+        const double cu = lbm::cz(i) * qz + lbm::cr(i) * qr;
+        const double poly = 3.0 * cu + 4.5 * cu * cu - qq;
+        const double feq = wi * rho * (1.0 + poly);
+        const double fi = a.f[i * n + x];
+        fbar[i * n + x] = nu * (1.0 - inv_tau);
+        taub += nu * (fi - feq) * inv_tau * inv_tau;
+        const double feqb = nu * inv_tau;
+        rhob += feqb * wi * (1.0 + poly);
+        const double dpoly = wi * rho * feqb * (3.0 + 9.0 * cu);  // d feq / d cu
+        qzb += dpoly * lbm::cz(i) - feqb * wi * rho * 3.0 * qz;
+        qrb += dpoly * lbm::cr(i) - feqb * wi * rho * 3.0 * qr;
+        massb += wi * nu;
+        hzb += 3.0 * wi * lbm::cz(i) * nu;
+        hrb += 3.0 * wi * lbm::cr(i) * nu;
+    }
+    double uzb = 0, urb = 0, druzb = 0, dzurb = 0, drurb = 0;
+    if (a.axisym) {
+        const double mu = rho * (tau - 0.5) / 3.0;
+        const double druz = w[slot_off(S_DRUZ, n) + x], dzur = w[slot_off(S_DZUR, n) + x],
+                     drur = w[slot_off(S_DRUR, n) + x];
+        // mass = -rho u_r / r
+        rhob += -massb * ur / rr;
+        urb += -massb * rho / rr;
+        // H_z = (mu (d_r u_z + d_z u_r) - rho u_r u_z) / r
+        double mub = hzb * (druz + dzur) / rr;
+        druzb += hzb * mu / rr;
+        dzurb += hzb * mu / rr;
+        rhob += -hzb * ur * uz / rr;
+        urb += -hzb * rho * uz / rr;
+        uzb += -hzb * rho * ur / rr;
+        // H_r = (2 mu (d_r u_r - u_r / r) - rho u_r^2) / r
+        mub += hrb * 2.0 * (drur - ur / rr) / rr;
+        drurb += hrb * 2.0 * mu / rr;
+        urb += hrb * (-2.0 * mu / (rr * rr) - 2.0 * rho * ur / rr);
+        rhob += -hrb * ur * ur / rr;
+        // mu = rho (tau - 1/2) / 3
+        rhob += mub * (tau - 0.5) / 3.0;
+        taub += mub * rho / 3.0;
+    }
+    // u^eq = (j + tau F) / rho
+    const double Fz = w[slot_off(S_FZ, n) + x], Fr = w[slot_off(S_FR, n) + x];
+    const double jzb = qzb / rho, jrb = qrb / rho;
+    const double Fzb = tau * qzb / rho, Frb = tau * qrb / rho;
+    taub += (qzb * Fz + qrb * Fr) / rho;
+    rhob += -(qzb * qz + qrb * qr) / rho;
+    w[slot_off(S_RHOB, n) + x] = rhob;
+    w[slot_off(S_JZB, n) + x] = jzb;
+    w[slot_off(S_JRB, n) + x] = jrb;
+    w[slot_off(S_FZB, n) + x] = Fzb;
+    w[slot_off(S_FRB, n) + x] = Frb;
+    w[slot_off(S_UZB_H, n) + x] = uzb;
+    w[slot_off(S_URB_H, n) + x] = urb;
+    w[slot_off(S_DRUZB, n) + x] = druzb;
+    w[slot_off(S_DZURB, n) + x] = dzurb;
+    w[slot_off(S_DRURB, n) + x] = drurb;
+    w[slot_off(S_TAUB, n) + x] = taub;
+}
+
+// transposed isotropic stencil: sum over taps o of coef(o) * src(e - o),
+// src living on real rows of a plain field
+__device__ double iso_transpose_real(const double* src, int z, int e, int nz, int nr, bool along_r) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 1; i < lbm::kQ; ++i) {
+        const int c = along_r ? lbm::cr(i) : lbm::cz(i);
+        if (c == 0) continue;
+        const int y1 = e - lbm::cr(i), y2 = e - 2 * lbm::cr(i);
+        if (y1 >= 0 && y1 < nr) s += 8.0 * c * src[(long long)y1 * nz + wrapz(z - lbm::cz(i), nz)];
+        if (y2 >= 0 && y2 < nr) s -= c * src[(long long)y2 * nz + wrapz(z - 2 * lbm::cz(i), nz)];
+    }
+    return s / 36.0;
+}
+
+// step 4 for the velocities, then u = (j + F/2)/rho and the force reversed
+__global__ void rev_velocity_force(AdjArgs a) {
+    NODE_LOOP(a)
+    double* w = a.w;
+    const long long n = a.n;
+    const int nz = a.nz, nr = a.nr;
+    double uzb = w[slot_off(S_UZB_H, n) + x], urb = w[slot_off(S_URB_H, n) + x];
+    if (a.axisym) {
+        // images of row r in the extended velocity fields (reach 2)
+        const double* druzb = w + slot_off(S_DRUZB, n);
+        const double* dzurb = w + slot_off(S_DZURB, n);
+        const double* drurb = w + slot_off(S_DRURB, n);
+        int img[3];
+        double sz[3], sr[3];
+        int ni = 0;
+        img[ni] = r; sz[ni] = 1.0; sr[ni] = 1.0; ++ni;
+        if (r <= 1) { img[ni] = -1 - r; sz[ni] = 1.0; sr[ni] = -1.0; ++ni; }
+        if (r >= nr - 2) { img[ni] = 2 * nr - 1 - r; sz[ni] = 1.0; sr[ni] = 1.0; ++ni; }
+        for (int k = 0; k < ni; ++k) {
+            const int e = img[k];
+            uzb += sz[k] * iso_transpose_real(druzb, z, e, nz, nr, true);
+            urb += sr[k] * (iso_transpose_real(dzurb, z, e, nz, nr, false) + iso_transpose_real(drurb, z, e, nz, nr, true));
+        }
+    }
+    const double rho = w[slot_off(S_RHO, n) + x];
+    const double uz = w[slot_off(S_UZ, n) + x], ur = w[slot_off(S_UR, n) + x];
+    double jzb = w[slot_off(S_JZB, n) + x] + uzb / rho;
+    double jrb = w[slot_off(S_JRB, n) + x] + urb / rho;
+    double Fzb = w[slot_off(S_FZB, n) + x] + 0.5 * uzb / rho;
+    double Frb = w[slot_off(S_FRB, n) + x] + 0.5 * urb / rho;
+    double rhob = w[slot_off(S_RHOB, n) + x] - (uzb * uz + urb * ur) / rho;
+    // F = F^SC + F^sym + rho g z^
+    rhob += Fzb * a.gz;
+    const double psi = w[slot_off(S_PSI, n) + x];
+    const double sz = w[slot_off(S_SCZ, n) + x], sr = w[slot_off(S_SCR, n) + x];
+    double Gb = -psi * (Fzb * sz + Frb * sr);
+    double psib = -a.G * (Fzb * sz + Frb * sr);
+    double dzrb = 0, drrb = 0, dr1b = 0;
+    if (a.axisym) {
+        const double rr = r + 0.5;
+        const double dzr = w[slot_off(S_DZR, n) + x], drr = w[slot_off(S_DRR, n) + x];
+        const double dr1 = w[eslot_off(E_DR, n, a.ne) + eidx(r, z, nz)];
+        const double g18 = a.G / 18.0;
+        // F^sym_z = -(G/18) psi d_zr / r
+        Gb += Fzb * (-psi * dzr / (18.0 * rr));
+        psib += Fzb * (-g18 * dzr / rr);
+        dzrb = Fzb * (-g18 * psi / rr);
+        // F^sym_r = -(G/18) psi (d_rr / r - d_r / r^2)
+        const double br = drr / rr - dr1 / (rr * rr);
+        Gb += Frb * (-psi * br / 18.0);
+        psib += Frb * (-g18 * br);
+        drrb = Frb * (-g18 * psi / rr);
+        dr1b = Frb * (g18 * psi / (rr * rr));
+    }
+    w[slot_off(S_JZB, n) + x] = jzb;
+    w[slot_off(S_JRB, n) + x] = jrb;
+    w[slot_off(S_RHOB, n) + x] = rhob;
+    w[slot_off(S_FSCZB, n) + x] = Fzb;  // adjoint of F^SC equals that of F
+    w[slot_off(S_FSCRB, n) + x] = Frb;
+    w[slot_off(S_PSIB_LOC, n) + x] = psib;
+    w[slot_off(S_DZRB, n) + x] = dzrb;
+    w[slot_off(S_DRRB, n) + x] = drrb;
+    w[slot_off(S_DRB_REAL, n) + x] = dr1b;
+    w[slot_off(S_GB, n) + x] = Gb;
+}
+
+// d_zr = 1D d_z of the 1D d_r: transpose of the outer z difference
+__global__ void rev_dzr(AdjArgs a) {
+    NODE_LOOP(a)
+    const double* b = a.w + slot_off(S_DZRB, a.n) + (long long)r * a.nz;
+    const int nz = a.nz;
+    // forward: out(z) = (-in(z+2) + 8 in(z+1) - 8 in(z-1) + in(z-2)) / 12
+    a.w[slot_off(S_D1B, a.n) + x] = (-b[wrapz(z - 2, nz)] + 8.0 * b[wrapz(z - 1, nz)] - 8.0 * b[wrapz(z + 1, nz)] +
+                                     b[wrapz(z + 2, nz)]) / 12.0;
+}
+
+// adjoint of d_r psi on extended rows -2 .. nr+1 (the rows d_rr reads):
+// transposed d_rr plus the direct use of d_r on real rows
+__global__ void rev_dr(AdjArgs a) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.ne) return;
+    const int y = (int)(e / a.nz) - NGA, z = (int)(e - (long long)(y + NGA) * a.nz);
+    double v = 0.0;
+    if (y >= -2 && y < a.nr + 2) {
+        v = iso_transpose_real(a.w + slot_off(S_DRRB, a.n), z, y, a.nz, a.nr, true);
+        if (y >= 0 && y < a.nr) v += a.w[slot_off(S_DRB_REAL, a.n) + (long long)y * a.nz + z];
+    }
+    a.w[eslot_off(E_DRB, a.n, a.ne) + e] = v;
+}
+
+// adjoint of extended psi at extended row e, column z (before folding)
+__device__ double psi_ext_adjoint(const AdjArgs& a, int z, int e) {
+    const double* w = a.w;
+    const long long n = a.n;
+    const int nz = a.nz, nr = a.nr;
+    double s = 0.0;
+    // d_r psi = iso_r(psi_ext) on rows -4..nr+3; only rows -2..nr+1 carry adjoint
+    const double* drb = w + eslot_off(E_DRB, n, a.ne);
+#pragma unroll
+    for (int i = 1; i < lbm::kQ; ++i) {
+        const int c = lbm::cr(i);
+        if (c == 0) continue;
+        const int y1 = e - lbm::cr(i), y2 = e - 2 * lbm::cr(i);
+        if (y1 >= -2 && y1 < nr + 2) s += (8.0 * c / 36.0) * drb[eidx(y1, wrapz(z - lbm::cz(i), nz), nz)];
+        if (y2 >= -2 && y2 < nr + 2) s -= (c / 36.0) * drb[eidx(y2, wrapz(z - 2 * lbm::cz(i), nz), nz)];
+    }
+    // 1D d_r psi on real rows: (-p(y+2) + 8 p(y+1) - 8 p(y-1) + p(y-2)) / 12
+    const double* d1b = w + slot_off(S_D1B, n);
+    const int ys[4] = {e - 2, e - 1, e + 1, e + 2};
+    const double cf[4] = {-1.0, 8.0, -8.0, 1.0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (ys[k] >= 0 && ys[k] < nr) s += (cf[k] / 12.0) * d1b[(long long)ys[k] * nz + z];
+    // Shan–Chen force: F^SC(x) = -G psi(x) sum_i W_i psi(x + c_i) c_i
+    const double* fzb = w + slot_off(S_FSCZB, n);
+    const double* frb = w + slot_off(S_FSCRB, n);
+    const double* psi = w + slot_off(S_PSI, n);
+#pragma unroll
+    for (int i = 1; i < lbm::kQ; ++i) {
+        const int ysrc = e - lbm::cr(i);
+        if (ysrc < 0 || ysrc >= nr) continue;
+        const long long xs = (long long)ysrc * nz + wrapz(z - lbm::cz(i), nz);
+        s += -a.G * psi[xs] * lbm::weight(i) * (fzb[xs] * lbm::cz(i) + frb[xs] * lbm::cr(i));
+    }
+    return s;
+}
+
+// step 4 for psi (fold every image of the row), step 5, write lam
+__global__ void rev_psi_final(AdjArgs a) {
+    NODE_LOOP(a)
+    double* w = a.w;
+    const long long n = a.n;
+    const int nr = a.nr;
+    double psib = w[slot_off(S_PSIB_LOC, n) + x] + psi_ext_adjoint(a, z, r);
+    if (r <= 3) psib += psi_ext_adjoint(a, z, -1 - r);            // axis images (rows -4..-1)
+    if (r >= nr - 4) psib += psi_ext_adjoint(a, z, 2 * nr - 1 - r);  // wall images (rows nr..nr+3)
+    const double rho = w[slot_off(S_RHO, n) + x];
+    const double rhob = w[slot_off(S_RHOB, n) + x] + psib * exp(-rho / a.rho0);
+    const double jzb = w[slot_off(S_JZB, n) + x], jrb = w[slot_off(S_JRB, n) + x];
+    const double* fbar = w + fbar_off(n, a.ne);
+#pragma unroll
+    for (int i = 0; i < lbm::kQ; ++i)
+        a.lam[i * n + x] = fbar[i * n + x] + rhob + lbm::cz(i) * jzb + lbm::cr(i) * jrb;
+}
+
+// fixed-order reduction of the per-node dL/dG, dL/dtau into acc[0..1]
+__global__ void rev_reduce(AdjArgs a, double* acc) {
+    __shared__ double s[2][256];
+    const int t = threadIdx.x;
+    double g = 0.0, q = 0.0;
+    for (long long x = t; x < a.n; x += 256) {
+        g += a.w[slot_off(S_GB, a.n) + x];
+        q += a.w[slot_off(S_TAUB, a.n) + x];
+    }
+    s[0][t] = g;
+    s[1][t] = q;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (t < k) {
+            s[0][t] += s[0][t + k];
+            s[1][t] += s[1][t + k];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        acc[0] += s[0][0];
+        acc[1] += s[1][0];
+    }
+}
+
+// initial condition f_i = f^eq_i(rho0, u0): rho0-bar = sum_i lam_i d f^eq_i / d rho
+__global__ void init_vjp_kernel(const double* lam, const double* uz, const double* ur, long long n, double* rho_bar) {
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const double vz = uz ? uz[x] : 0.0, vr = ur ? ur[x] : 0.0;
+    const double qq = 1.5 * (vz * vz + vr * vr);
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < lbm::kQ; ++i) {
+        const double cu = lbm::cz(i) * vz + lbm::cr(i) * vr;
+        s += lam[i * n + x] * lbm::weight(i) * (1.0 + 3.0 * cu + 4.5 * cu * cu - qq);
+    }
+    rho_bar[x] = s;
+}
+
+// density of a state [9][n] (for the loss observable)
+__global__ void density_kernel(const double* f, long long n, double* rho) {
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < lbm::kQ; ++i) s += f[i * n + x];
+    rho[x] = s;
+}
+
+// r_m = sum_k w_mk phi(node_k), phi = (rho - rho_g)/(rho_l - rho_g); one
+// workgroup per probe row, fixed-order reduction
+__global__ void ray_forward_kernel(const double* rho, const int* row_ptr, const int* col, const double* val,
+                                   double rho_l, double rho_g, double* out) {
+    __shared__ double s[256];
+    const int m = blockIdx.x, t = threadIdx.x;
+    double acc = 0.0;
+    for (int k = row_ptr[m] + t; k < row_ptr[m + 1]; k += 256) acc += val[k] * (rho[col[k]] - rho_g);
+    s[t] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) s[t] += s[t + w];
+        __syncthreads();
+    }
+    if (t == 0) out[m] = s[0] / (rho_l - rho_g);
+}
+
+// lam_i(x) += sum_m rbar_m w_mx / (rho_l - rho_g) for every i, from the
+// node-major (transposed) copy of the probe matrix
+__global__ void ray_vjp_kernel(const double* rbar, const int* node_ptr, const int* node_row, const double* node_val,
+                               const int* nodes, int n_nodes, double rho_l, double rho_g, long long n, double* lam) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_nodes) return;
+    double s = 0.0;
+    for (int j = node_ptr[k]; j < node_ptr[k + 1]; ++j) s += rbar[node_row[j]] * node_val[j];
+    s /= (rho_l - rho_g);
+    const long long x = nodes[k];
+#pragma unroll
+    for (int i = 0; i < lbm::kQ; ++i) lam[i * n + x] += s;
+}
+
+// loss += sum_m (r_m - target_m)^2 and rbar_m = 2 (r_m - target_m)
+__global__ void misfit_kernel(const double* r, const double* target, int m, double* loss, double* rbar) {
+    __shared__ double s[256];
+    const int t = threadIdx.x;
+    double acc = 0.0;
+    for (int k = t; k < m; k += 256) {
+        const double d = r[k] - target[k];
+        if (rbar) rbar[k] = 2.0 * d;
+        acc += d * d;
+    }
+    s[t] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) s[t] += s[t + w];
+        __syncthreads();
+    }
+    if (t == 0) *loss += s[0];
+}
+
+inline int nblk(long long n) { return (int)((n + 255) / 256); }
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr) {
+    if (nz < 1 || nr < 6) return 0;
+    const long long n = (long long)nz * nr, ne = (long long)nz * (nr + 2 * NGA);
+    return ((size_t)S_NSLOT * n + (size_t)E_NSLOT * ne + 9 * (size_t)n) * sizeof(double);
+}
+
+int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const double* d_lam_next, double* d_lam,
+                         double* d_grad_acc, void* d_ws, size_t ws_bytes, void* hip_stream) {
+    if (!p || !d_f || !d_lam_next || !d_lam || !d_ws) return LBM_AXI_EINVAL;
+    if (p->nz < 1 || p->nr < 6 || !(p->tau > 0.5) || !(p->psi_rho0 > 0.0)) return LBM_AXI_EINVAL;
+    if (p->wall != 0 && p->wall != 1) return LBM_AXI_EINVAL;
+    if (p->precision != LBM_AXI_FP64) return LBM_AXI_EUNSUP;
+    if (ws_bytes < lbm_axi_adjoint_workspace_bytes(p->nz, p->nr)) return LBM_AXI_ENOMEM;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    AdjArgs a{};
+    a.nz = p->nz;
+    a.nr = p->nr;
+    a.n = (long long)p->nz * p->nr;
+    a.ne = (long long)p->nz * (p->nr + 2 * NGA);
+    a.G = p->G;
+    a.tau = p->tau;
+    a.rho0 = p->psi_rho0;
+    a.gz = p->gz;
+    a.wall = p->wall;
+    a.axisym = p->axisym;
+    a.f = d_f;
+    a.lam_next = d_lam_next;
+    a.lam = d_lam;
+    a.w = static_cast<double*>(d_ws);
+    const dim3 b(256);
+    hipLaunchKernelGGL(fwd_moments, dim3(nblk(a.n)), b, 0, s, a);
+    hipLaunchKernelGGL(fwd_extend, dim3(nblk(a.ne)), b, 0, s, a, (int)S_PSI, (int)E_PSI, 1.0);
+    hipLaunchKernelGGL(fwd_dr, dim3(nblk(a.ne)), b, 0, s, a);
+    hipLaunchKernelGGL(fwd_second, dim3(nblk(a.n)), b, 0, s, a);
+    hipLaunchKernelGGL(fwd_force, dim3(nblk(a.n)), b, 0, s, a);
+    hipLaunchKernelGGL(fwd_extend, dim3(nblk(a.ne)), b, 0, s, a, (int)S_UZ, (int)E_UZ, 1.0);
+    hipLaunchKernelGGL(fwd_extend, dim3(nblk(a.ne)), b, 0, s, a, (int)S_UR, (int)E_UR, -1.0);
+    hipLaunchKernelGGL(fwd_velocity_gradients, dim3(nblk(a.n)), b, 0, s, a);
+    hipLaunchKernelGGL(rev_collision, dim3(nblk(a.n)), b, 0, s, a);
+    hipLaunchKernelGGL(rev_velocity_force, dim3(nblk(a.n)), b, 0, s, a);
+    hipLaunchKernelGGL(rev_dzr, dim3(nblk(a.n)), b, 0, s, a);
+    hipLaunchKernelGGL(rev_dr, dim3(nblk(a.ne)), b, 0, s, a);
+    hipLaunchKernelGGL(rev_psi_final, dim3(nblk(a.n)), b, 0, s, a);
+    if (d_grad_acc) hipLaunchKernelGGL(rev_reduce, dim3(1), b, 0, s, a, d_grad_acc);
+    return hipGetLastError() == hipSuccess ? LBM_AXI_OK : LBM_AXI_EHIP;
+}
+
+int lbm_axi_init_vjp(const double* d_lam0, const double* d_uz0, const double* d_ur0, int32_t nz, int32_t nr,
+                     double* d_rho0_bar, void* hip_stream) {
+    if (!d_lam0 || !d_rho0_bar || nz < 1 || nr < 1) return LBM_AXI_EINVAL;
+    const long long n = (long long)nz * nr;
+    hipLaunchKernelGGL(init_vjp_kernel, dim3(nblk(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), d_lam0,
+                       d_uz0, d_ur0, n, d_rho0_bar);
+    return hipGetLastError() == hipSuccess ? LBM_AXI_OK : LBM_AXI_EHIP;
+}
+
+int lbm_axi_density(const double* d_f, int32_t nz, int32_t nr, double* d_rho, void* hip_stream) {
+    if (!d_f || !d_rho || nz < 1 || nr < 1) return LBM_AXI_EINVAL;
+    const long long n = (long long)nz * nr;
+    hipLaunchKernelGGL(density_kernel, dim3(nblk(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), d_f, n, d_rho);
+    return hipGetLastError() == hipSuccess ? LBM_AXI_OK : LBM_AXI_EHIP;
+}
+
+int lbm_axi_ray_forward(const double* d_rho, int32_t n_rows, const int32_t* d_row_ptr, const int32_t* d_col,
+                        const double* d_val, double rho_l, double rho_g, double* d_out, void* hip_stream) {
+    if (!d_rho || !d_row_ptr || !d_col || !d_val || !d_out || n_rows < 0 || rho_l == rho_g) return LBM_AXI_EINVAL;
+    if (n_rows == 0) return LBM_AXI_OK;
+    hipLaunchKernelGGL(ray_forward_kernel, dim3(n_rows), dim3(256), 0, static_cast<hipStream_t>(hip_stream), d_rho,
+                       d_row_ptr, d_col, d_val, rho_l, rho_g, d_out);
+    return hipGetLastError() == hipSuccess ? LBM_AXI_OK : LBM_AXI_EHIP;
+}
+
+int lbm_axi_ray_vjp(const double* d_rbar, int32_t n_nodes, const int32_t* d_node_ptr, const int32_t* d_node_row,
+                    const double* d_node_val, const int32_t* d_nodes, double rho_l, double rho_g, int32_t nz,
+                    int32_t nr, double* d_lam, void* hip_stream) {
+    if (!d_rbar || !d_node_ptr || !d_node_row || !d_node_val || !d_nodes || !d_lam || n_nodes < 0 || rho_l == rho_g)
+        return LBM_AXI_EINVAL;
+    if (n_nodes == 0) return LBM_AXI_OK;
+    hipLaunchKernelGGL(ray_vjp_kernel, dim3((n_nodes + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
+                       d_rbar, d_node_ptr, d_node_row, d_node_val, d_nodes, n_nodes, rho_l, rho_g,
+                       (long long)nz * nr, d_lam);
+    return hipGetLastError() == hipSuccess ? LBM_AXI_OK : LBM_AXI_EHIP;
+}
+
+int lbm_axi_misfit(const double* d_r, const double* d_target, int32_t m, double* d_loss, double* d_rbar,
+                   void* hip_stream) {
+    if (!d_r || !d_target || !d_loss || m < 0) return LBM_AXI_EINVAL;
+    hipLaunchKernelGGL(misfit_kernel, dim3(1), dim3(256), 0, static_cast<hipStream_t>(hip_stream), d_r, d_target, m,
+                       d_loss, d_rbar);
+    return hipGetLastError() == hipSuccess ? LBM_AXI_OK : LBM_AXI_EHIP;
+}
+
+int lbm_axi_ray_weights(int32_t nz, int32_t nr, double zc, const double* h_thetas, int32_t n_rays, double ds,
+                        double s_max, int32_t cap, int32_t* h_row_ptr, int32_t* h_col, double* h_val,
+                        int32_t* h_node_ptr, int32_t* h_nodes, int32_t* h_node_row, double* h_node_val,
+                        int32_t* h_nnz, int32_t* h_n_nodes) {
+    if (nz < 1 || nr < 1 || n_rays < 0 || !(ds > 0.0) || !h_nnz || !h_n_nodes || (n_rays > 0 && !h_thetas))
+        return LBM_AXI_EINVAL;
+    // per ray: node -> weight of the bilinear interpolants of the samples
+    // s_k = (k + 1/2) ds along the ray from (zc, 0) at angle theta; rows
+    // below row 0 mirror onto the real rows, rows above the last clamp to
+    // it, z is periodic
+    std::vector<std::map<int32_t, double>> rows((size_t)n_rays);
+    const int nk = (int)std::floor(s_max / ds);
+    for (int m = 0; m < n_rays; ++m) {
+        const double ct = std::cos(h_thetas[m]), st = std::sin(h_thetas[m]);
+        for (int k = 0; k < nk; ++k) {
+            const double sk = (k + 0.5) * ds;
+            const double zz = zc + sk * ct, y = sk * st - 0.5;
+            const int j0 = (int)std::floor(y), k0 = (int)std::floor(zz);
+            const double ty = y - j0, tz = zz - k0;
+            for (int dj = 0; dj < 2; ++dj) {
+                const double wy = dj ? ty : 1.0 - ty;
+                int jj = j0 + dj;
+                if (jj < 0) jj = -1 - jj;
+                if (jj > nr - 1) jj = nr - 1;
+                for (int dk = 0; dk < 2; ++dk) {
+                    const double wz = dk ? tz : 1.0 - tz;
+                    const double wgt = ds * wy * wz;
+                    if (wgt == 0.0) continue;
+                    int kk = (k0 + dk) % nz;
+                    if (kk < 0) kk += nz;
+                    rows[m][jj * nz + kk] += wgt;
+                }
+            }
+        }
+    }
+    std::map<int32_t, std::vector<std::pair<int32_t, double>>> by_node;
+    int32_t nnz = 0;
+    for (int m = 0; m < n_rays; ++m) {
+        nnz += (int32_t)rows[m].size();
+        for (const auto& kv : rows[m]) by_node[kv.first].push_back({m, kv.second});
+    }
+    *h_nnz = nnz;
+    *h_n_nodes = (int32_t)by_node.size();
+    if (!h_row_ptr || !h_col || !h_val || !h_node_ptr || !h_nodes || !h_node_row || !h_node_val) return LBM_AXI_OK;
+    if (cap < nnz) return LBM_AXI_ENOMEM;
+    int32_t k = 0;
+    h_row_ptr[0] = 0;
+    for (int m = 0; m < n_rays; ++m) {
+        for (const auto& kv : rows[m]) {
+            h_col[k] = kv.first;
+            h_val[k] = kv.second;
+            ++k;
+        }
+        h_row_ptr[m + 1] = k;
+    }
+    int32_t j = 0, q = 0;
+    h_node_ptr[0] = 0;
+    for (const auto& kv : by_node) {
+        h_nodes[q] = kv.first;
+        for (const auto& e : kv.second) {
+            h_node_row[j] = e.first;
+            h_node_val[j] = e.second;
+            ++j;
+        }
+        h_node_ptr[++q] = j;
+    }
+    return LBM_AXI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,237 @@
+"""GPU adjoint of the FP64 step against the oracle.
+
+Per step: the dot-product identity <lam, J v> = <J^T lam, v> with J v from
+complex-step differentiation of the oracle's step (exp, products and
+quotients are complex-analytic, so the complex step is exact to round-off)
+and J^T lam from the hand-written HIP adjoint; likewise for d/dG and d/dtau.
+End to end: the checkpointed gradient of the interface-shape loss against
+the oracle's complex-step gradient and against central finite differences
+of the GPU loss."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import oracle.diagnostics as D
+from lbm_inputs import (adjoint_coeffs, coexistence_densities, drop_density, drop_density_jacobian,
+                        random_state_fields)
+
+pytestmark = pytest.mark.gpu
+
+H = 1e-20  # complex-step size
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _libs():
+    from paper_1310_1871_amd import adjoint as A
+    from paper_1310_1871_amd import lbm_axi as L
+    return L, A
+
+
+def _state(seed, nz, nr, G):
+    rg, rl = coexistence_densities(G)
+    rho = drop_density(nz, nr, nz / 2.0, 0.35 * nr, rl, rg, 2.0, {2: 0.05 * nr})
+    _, uz, ur = random_state_fields(seed, nz, nr, u_amp=0.01)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = O.make_params(nz, nr, G=G)
+    f = O.equilibrium(p, rho, uz, ur) * (1.0 + 0.005 * rng.uniform(-1, 1, size=(9, nr, nz)))
+    return f, rng
+
+
+CASES = [
+    # nz, nr, G, tau, wall, axisym, gz
+    (48, 24, -5.5, 0.9, 0, 1, 0.0),
+    (48, 24, -5.5, 0.9, 1, 1, 0.0),
+    (48, 24, -5.0, 0.8, 1, 0, 0.0),
+    (37, 13, -4.5, 1.1, 0, 1, 1e-4),
+    (5, 8, -4.5, 0.7, 1, 1, 0.0),
+]
+
+
+@pytest.mark.parametrize("nz,nr,G,tau,wall,axisym,gz", CASES)
+def test_adjoint_step_dot_product(nz, nr, G, tau, wall, axisym, gz):
+    L, A = _libs()
+    _say(f"adjoint dot test nz={nz} nr={nr} G={G} tau={tau} wall={wall} axisym={axisym} gz={gz}")
+    f, rng = _state(nz * 100 + nr, nz, nr, G)
+    v = rng.standard_normal((9, nr, nz))
+    lam = rng.standard_normal((9, nr, nz))
+    # oracle: J v, df'/dG, df'/dtau by complex step
+    pc = O.make_params(nz, nr, G=G, tau=tau, wall=wall, axisym=axisym, gz=gz)
+    Jv = O.run(pc, f + 1j * H * v, 1, complex_step=True).imag / H
+    pG = O.make_params(nz, nr, G=G, tau=tau, wall=wall, axisym=axisym, gz=gz, G_im=H)
+    dG = O.run(pG, f.astype(complex), 1, complex_step=True).imag / H
+    pt = O.make_params(nz, nr, G=G, tau=tau, wall=wall, axisym=axisym, gz=gz, tau_im=H)
+    dT = O.run(pt, f.astype(complex), 1, complex_step=True).imag / H
+    # GPU: J^T lam
+    params = L.make_params(nz, nr, G=G, tau=tau, wall=wall, axisym=axisym, gz=gz)
+    dev = torch.device("cuda")
+    ws = torch.empty(A._lib.lbm_axi_adjoint_workspace_bytes(nz, nr) // 8, dtype=torch.float64, device=dev)
+    fd = torch.from_numpy(f).to(dev)
+    ld = torch.from_numpy(lam).to(dev)
+    out = torch.empty_like(ld)
+    acc = torch.zeros(2, dtype=torch.float64, device=dev)
+    A.adjoint_step(params, fd, ld, out, acc, ws)
+    JTl = out.cpu().numpy()
+    acc = acc.cpu().numpy()
+    lhs, rhs = np.sum(lam * Jv), np.sum(JTl * v)
+    _say(f"  <lam,Jv>={lhs:.15e} <JTlam,v>={rhs:.15e} dG {np.sum(lam * dG):.12e} vs {acc[0]:.12e} "
+         f"dtau {np.sum(lam * dT):.12e} vs {acc[1]:.12e}")
+    assert abs(lhs - rhs) <= 1e-11 * np.sum(np.abs(lam * Jv)), (lhs, rhs)
+    assert abs(np.sum(lam * dG) - acc[0]) <= 1e-11 * np.sum(np.abs(lam * dG)) + 1e-300
+    assert abs(np.sum(lam * dT) - acc[1]) <= 1e-11 * np.sum(np.abs(lam * dT)) + 1e-300
+
+
+def test_adjoint_linearises_the_gpu_step():
+    """The adjoint's forward recomputation linearises the same map the fused
+    step kernel applies: (f(x + e v) - f(x - e v)) / 2e from the GPU step
+    matches J v of the oracle."""
+    L, A = _libs()
+    nz, nr, G, tau = 48, 24, -5.5, 0.9
+    f, rng = _state(3, nz, nr, G)
+    v = rng.standard_normal((9, nr, nz))
+    pc = O.make_params(nz, nr, G=G, tau=tau, wall=1)
+    Jv = O.run(pc, f + 1j * H * v, 1, complex_step=True).imag / H
+    outs = []
+    for sgn in (1, -1):
+        sim = L.AxiLBM(L.make_params(nz, nr, G=G, tau=tau, wall=1), torch.ones((nr, nz), dtype=torch.float64).cuda())
+        st = torch.from_numpy(f + sgn * 1e-6 * v).cuda().reshape(-1).view(torch.uint8).clone()
+        sim.set_state(st)
+        sim.step(1)
+        outs.append(sim.populations().cpu().numpy())
+    fd = (outs[0] - outs[1]) / 2e-6
+    assert np.abs(fd - Jv).max() < 1e-6 * np.abs(Jv).max()
+
+
+def test_probe_matches_oracle_and_its_vjp():
+    L, A = _libs()
+    nz, nr, G = 64, 32, -5.5
+    rg, rl = coexistence_densities(G)
+    rho = drop_density(nz, nr, 32.0, 12.0, rl, rg, 2.0, {2: 1.5, 3: -0.7})
+    th = A.default_thetas(16)
+    probe = A.RayProbe(nz, nr, 32.0, th, rl, rg)
+    W = D.interface_radius_weights(nz, nr, 32.0, th)
+    ref = D.interface_radius(rho, W, rl, rg)
+    p = O.make_params(nz, nr, G=G)
+    f = O.equilibrium(p, rho, 0 * rho, 0 * rho)
+    out = torch.empty(16, dtype=torch.float64, device="cuda")
+    probe.radius_of_state(torch.from_numpy(f).cuda(), out)
+    got = out.cpu().numpy()
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+    assert abs(got[8] - 12.0) < 1.5  # a drop of radius ~12 measures ~12
+    # VJP by the dot-product identity on the linear map
+    rng = np.random.Generator(np.random.PCG64(1))
+    rbar = rng.standard_normal(16)
+    v = rng.standard_normal((9, nr, nz))
+    lam = torch.zeros((9, nr, nz), dtype=torch.float64, device="cuda")
+    probe.add_vjp(torch.from_numpy(rbar).cuda(), lam)
+    lhs = np.sum(lam.cpu().numpy() * v)
+    rv = D.interface_radius(v.sum(0) + rg, W, rl, rg)  # r is affine: the linear part acts on sum_i v_i
+    assert abs(lhs - np.dot(rbar, rv)) < 1e-11 * np.sum(np.abs(rbar * rv))
+
+
+def _c4_small():
+    """Reduced version of the adjoint workload: 128 x 64 drop, 400 steps,
+    samples every 50, checkpoints every 100."""
+    nz, nr, R, G, tau = 128, 64, 24.0, -5.5, 0.8
+    rg, rl = coexistence_densities(G)
+    ls = (2, 3, 4, 5, 6)
+    a_t = adjoint_coeffs(11, R)
+    a_0 = adjoint_coeffs(12, R)
+    return nz, nr, R, G, tau, rg, rl, ls, a_t, a_0
+
+
+def _oracle_loss(nz, nr, G, tau, f0, W, targets, steps, every, rl, rg, G_im=0.0, tau_im=0.0):
+    cs = np.iscomplexobj(f0) or G_im != 0.0 or tau_im != 0.0
+    p = O.make_params(nz, nr, G=G, tau=tau, wall=0, G_im=G_im, tau_im=tau_im)
+    f = f0.astype(complex) if cs else f0
+    loss = 0.0
+    for k in range(steps // every):
+        f = O.run(p, f, every, complex_step=cs)
+        r = D.interface_radius(f.sum(0), W, rl, rg)
+        loss = loss + np.sum((r - targets[k]) ** 2)
+    return loss
+
+
+def test_shape_loss_gradient_vs_oracle_and_fd():
+    L, A = _libs()
+    nz, nr, R, G, tau, rg, rl, ls, a_t, a_0 = _c4_small()
+    steps, every, ck = 400, 50, 100
+    zc = nz / 2.0
+    th = A.default_thetas(16)
+    W = D.interface_radius_weights(nz, nr, zc, th)
+    _say("adjoint end-to-end 128x64, 400 steps: oracle targets")
+    # targets from the oracle run of the target coefficients
+    rho_t = drop_density(nz, nr, zc, R, rl, rg, 2.0, a_t)
+    p = O.make_params(nz, nr, G=G, tau=tau, wall=0)
+    f = O.equilibrium(p, rho_t, 0 * rho_t, 0 * rho_t)
+    targets = []
+    for k in range(steps // every):
+        f = O.run(p, f, every)
+        targets.append(D.interface_radius(f.sum(0), W, rl, rg))
+    targets = np.array(targets)
+    rho0 = drop_density(nz, nr, zc, R, rl, rg, 2.0, a_0)
+    J = drop_density_jacobian(nz, nr, zc, R, rl, rg, 2.0, a_0, ls)
+    # GPU adjoint gradient
+    _say("  GPU forward + adjoint")
+    probe = A.RayProbe(nz, nr, zc, th, rl, rg)
+    tgt = torch.from_numpy(targets).cuda()
+    rho0_t = torch.from_numpy(rho0).cuda().requires_grad_(True)
+    Gt = torch.tensor(G, dtype=torch.float64, device="cuda", requires_grad=True)
+    Tt = torch.tensor(tau, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = A.shape_loss(rho0_t, Gt, Tt, probe, tgt, steps, every, ck)
+    loss.backward()
+    g_rho = rho0_t.grad.cpu().numpy()
+    g_gpu = np.array([np.sum(g_rho * J[k]) for k in range(len(ls))] + [Gt.grad.item(), Tt.grad.item()])
+    _say(f"  loss {loss.item():.12e} grad {g_gpu}")
+    # oracle loss value and complex-step gradient
+    f0 = O.equilibrium(p, rho0, 0 * rho0, 0 * rho0)
+    L0 = _oracle_loss(nz, nr, G, tau, f0, W, targets, steps, every, rl, rg)
+    assert abs(loss.item() - L0) <= 1e-9 * abs(L0)
+    w9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None]
+    g_or = []
+    for k in range(len(ls)):
+        _say(f"  oracle complex step a_{ls[k]}")
+        g_or.append(_oracle_loss(nz, nr, G, tau, f0 + 1j * H * w9 * J[k], W, targets, steps, every, rl, rg).imag / H)
+    g_or.append(_oracle_loss(nz, nr, G, tau, f0, W, targets, steps, every, rl, rg, G_im=H).imag / H)
+    g_or.append(_oracle_loss(nz, nr, G, tau, f0, W, targets, steps, every, rl, rg, tau_im=H).imag / H)
+    g_or = np.array(g_or)
+    _say(f"  oracle grad {g_or}")
+    assert np.all(np.abs(g_gpu - g_or) <= 1e-6 * np.abs(g_or) + 1e-9 * np.abs(g_or).max()), (g_gpu, g_or)
+    # central finite differences of the GPU loss (h = 1e-6)
+    h = 1e-6
+    fd = []
+    with torch.no_grad():
+        for k in range(len(ls)):
+            lp = A.shape_loss(torch.from_numpy(rho0 + h * J[k]).cuda(), G, tau, probe, tgt, steps, every, ck).item()
+            lm = A.shape_loss(torch.from_numpy(rho0 - h * J[k]).cuda(), G, tau, probe, tgt, steps, every, ck).item()
+            fd.append((lp - lm) / (2 * h))
+        r0 = torch.from_numpy(rho0).cuda()
+        fd.append((A.shape_loss(r0, G + h, tau, probe, tgt, steps, every, ck).item() -
+                   A.shape_loss(r0, G - h, tau, probe, tgt, steps, every, ck).item()) / (2 * h))
+        fd.append((A.shape_loss(r0, G, tau + h, probe, tgt, steps, every, ck).item() -
+                   A.shape_loss(r0, G, tau - h, probe, tgt, steps, every, ck).item()) / (2 * h))
+    fd = np.array(fd)
+    _say(f"  FD grad {fd}")
+    assert np.all(np.abs(g_gpu - fd) <= 1e-5 * np.abs(fd) + 1e-7 * np.abs(fd).max()), (g_gpu, fd)
+
+
+def test_checkpointing_is_exact():
+    """Recomputing segments from checkpoints reproduces the gradient of the
+    no-recomputation run bit for bit (the step kernel is deterministic)."""
+    L, A = _libs()
+    nz, nr, R, G, tau, rg, rl, ls, a_t, a_0 = _c4_small()
+    steps, every = 200, 50
+    th = A.default_thetas(8)
+    probe = A.RayProbe(nz, nr, nz / 2.0, th, rl, rg)
+    rho0 = torch.from_numpy(drop_density(nz, nr, nz / 2.0, R, rl, rg, 2.0, a_0)).cuda()
+    tgt = A.radius_history(torch.from_numpy(drop_density(nz, nr, nz / 2.0, R, rl, rg, 2.0, a_t)).cuda(), G, tau,
+                           probe, steps, every)
+    grads = []
+    for ck in (50, 200):
+        r0 = rho0.clone().requires_grad_(True)
+        A.shape_loss(r0, G, tau, probe, tgt, steps, every, ck).backward()
+        grads.append(r0.grad.clone())
+    assert torch.equal(grads[0], grads[1])
