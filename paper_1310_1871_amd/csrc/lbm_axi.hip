@@ -12,36 +12,13 @@
 #include <string>
 
 #include "../../include/lbm_axi.h"
+#include "common.hpp"
 #include "lattice.hpp"
 #include "step_kernel.hpp"
 
 namespace {
 
-thread_local std::string g_last_error;
-
-int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-int fail(int code, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return code;
-}
-
-int hip_fail(hipError_t e, const char* what) {
-    return fail(LBM_AXI_EHIP, "%s: %s", what, hipGetErrorString(e));
-}
-
-#define HIP_TRY(expr, what)                      \
-    do {                                         \
-        hipError_t e_ = (expr);                  \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
-    } while (0)
-
-constexpr size_t kAlign = 256;
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+using namespace lbm_host;
 
 // tile shape and workgroup size of the fused kernel per precision (chosen
 // by timing on MI355X: 4096 x 512 thread workload)
@@ -51,8 +28,6 @@ constexpr int kTZ32 = 128, kTR32 = 16, kNT32 = 512;
 int tile_z(int precision) { return precision == LBM_AXI_FP64 ? kTZ64 : kTZ32; }
 int tile_r(int precision) { return precision == LBM_AXI_FP64 ? kTR64 : kTR32; }
 
-size_t storage_size(int precision) { return precision == LBM_AXI_FP64 ? sizeof(double) : sizeof(float); }
-
 struct Layout {
     size_t state_bytes;   // one population buffer
     size_t off_b;         // second buffer
@@ -61,26 +36,6 @@ struct Layout {
     size_t total;
     int tiles_z, tiles_r, nblocks;
 };
-
-int check_params(const lbm_axi_params* p) {
-    if (!p) return fail(LBM_AXI_EINVAL, "params is NULL");
-    if (p->nz < 1) return fail(LBM_AXI_EINVAL, "nz must be >= 1 (got %d)", p->nz);
-    if (p->nr < 6) return fail(LBM_AXI_EINVAL, "nr must be >= 6 for the derivative stencils (got %d)", p->nr);
-    if (9.0 * (double)p->nz * (double)p->nr * (p->precision == LBM_AXI_FP64 ? 8.0 : 4.0) >= 4294967296.0)
-        return fail(LBM_AXI_EINVAL, "grid too large: the population state must stay below 4 GiB");
-    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_AXI_EINVAL, "tau must be > 1/2 (got %g)", p->tau);
-    if (!std::isfinite(p->G)) return fail(LBM_AXI_EINVAL, "G must be finite");
-    if (!(p->psi_rho0 > 0.0) || !std::isfinite(p->psi_rho0)) return fail(LBM_AXI_EINVAL, "psi_rho0 must be > 0");
-    if (!std::isfinite(p->gz)) return fail(LBM_AXI_EINVAL, "gz must be finite");
-    if (p->wall != LBM_AXI_WALL_NOSLIP && p->wall != LBM_AXI_WALL_FREESLIP)
-        return fail(LBM_AXI_EINVAL, "wall must be 0 (no-slip) or 1 (free-slip)");
-    if (p->axisym != 0 && p->axisym != 1) return fail(LBM_AXI_EINVAL, "axisym must be 0 or 1");
-    if (p->precision != LBM_AXI_FP64 && p->precision != LBM_AXI_FP32_SHIFTED)
-        return fail(LBM_AXI_EINVAL, "precision must be 0 (FP64) or 1 (FP32 shifted)");
-    if (p->flags != 0) return fail(LBM_AXI_EUNSUP, "flags must be 0");
-    if (!std::isfinite(p->rho_ref)) return fail(LBM_AXI_EINVAL, "rho_ref must be finite");
-    return LBM_AXI_OK;
-}
 
 Layout layout_of(const lbm_axi_params* p) {
     Layout L{};
@@ -94,26 +49,6 @@ Layout layout_of(const lbm_axi_params* p) {
     L.off_red = L.off_partials + align_up((size_t)L.nblocks * 4 * sizeof(double));
     L.total = L.off_red + align_up(4 * sizeof(double));
     return L;
-}
-
-// f_i = f^eq_i(rho, u) with u^eq = u (initial state, no force shift)
-template <class P>
-__global__ void init_equilibrium_kernel(typename P::S* f, const double* rho, const double* uz,
-                                        const double* ur, long long n, double rho_ref) {
-    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n) return;
-    const double r = rho[x];
-    const double vz = uz ? uz[x] : 0.0;
-    const double vr = ur ? ur[x] : 0.0;
-    const double qq = 1.5 * (vz * vz + vr * vr);
-#pragma unroll
-    for (int i = 0; i < lbm::kQ; ++i) {
-        const double cu = lbm::cz(i) * vz + lbm::cr(i) * vr;
-        const double poly = 3.0 * cu + 4.5 * cu * cu - qq;
-        const double w = lbm::weight(i);
-        double v = P::kShift ? w * ((r - rho_ref) + r * poly) : w * r * (1.0 + poly);
-        f[(long long)i * n + x] = typename P::S(v);
-    }
 }
 
 // fixed-order sum of the per-block partials into out[4]
@@ -309,6 +244,6 @@ int lbm_axi_set_coupling(lbm_axi_t h, double G, double tau) {
 
 void lbm_axi_destroy(lbm_axi_t h) { delete h; }
 
-const char* lbm_axi_last_error(void) { return g_last_error.c_str(); }
+const char* lbm_axi_last_error(void) { return lbm_host::g_last_error.c_str(); }
 
 }  // extern "C"

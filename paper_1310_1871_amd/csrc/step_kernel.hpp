@@ -138,8 +138,11 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
 }
 
+// One TZ x TR tile of one lattice: the whole step (or the moments) for the
+// tile's nodes.  `tile` = tz * tiles_r + tr; `slot` indexes the per-block
+// partial sums of the moments mode.
 template <class P, int TZ, int TR, int NT, bool kMoments>
-__global__ __launch_bounds__(NT) void axi_tile_kernel(const StepArgs a) {
+__device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, const int slot) {
     using S = typename P::S;
     using C = typename P::C;
     constexpr int PZ = TZ + 12, PR = TR + 12;  // psi window (halo 6)
@@ -161,7 +164,6 @@ __global__ __launch_bounds__(NT) void axi_tile_kernel(const StepArgs a) {
     const int nz = a.nz, nr = a.nr;
     const bool big = a.big_nz != 0;
     const int t = threadIdx.x;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int tzi = tile / a.tiles_r;
     const int z0 = tzi * TZ, r0 = (tile - tzi * a.tiles_r) * TR;
     const C rho0 = C(a.rho0);
@@ -466,9 +468,38 @@ __global__ __launch_bounds__(NT) void axi_tile_kernel(const StepArgs a) {
                 double v = 0.0;
 #pragma unroll
                 for (int w = 0; w < NT / 64; ++w) v += s_red[t][w];
-                a.partials[(long long)blockIdx.x * 4 + t] = v;
+                a.partials[(long long)slot * 4 + t] = v;
             }
         }
+    }
+}
+
+template <class P, int TZ, int TR, int NT, bool kMoments>
+__global__ __launch_bounds__(NT) void axi_tile_kernel(const StepArgs a) {
+    tile_body<P, TZ, TR, NT, kMoments>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x);
+}
+
+// Batched ensemble: many independent lattices (each with its own size,
+// parameters and buffers) advanced by one persistent launch.  Work item k is
+// (instance, tile); workgroups stride over the work list, so one launch
+// covers every instance whatever their sizes.  `parity` selects which of an
+// instance's two buffers is read.
+struct BatchInstance {
+    StepArgs args[2];  // [parity]: fin/fout swapped
+};
+
+template <class P, int TZ, int TR, int NT>
+__global__ __launch_bounds__(NT) void axi_batch_kernel(const BatchInstance* __restrict__ insts,
+                                                      const int2* __restrict__ items, int n_items, int parity) {
+    for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
+        // the work item is uniform over the workgroup: keep it (and the
+        // instance arguments it selects) in scalar registers
+        const int2 w = items[k];
+        const int inst = __builtin_amdgcn_readfirstlane(w.x);
+        const int tile = __builtin_amdgcn_readfirstlane(w.y);
+        const StepArgs a = insts[inst].args[parity];
+        tile_body<P, TZ, TR, NT, false>(a, tile, 0);
+        __syncthreads();  // the next item reuses the LDS windows
     }
 }
 
