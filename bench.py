@@ -7,9 +7,12 @@ G; tau does not change the work per node).  Synthetic, seeded inputs resident
 in HBM before the timed region.
 
 One step = one launch of the fused kernel over all 2,097,152 nodes.  Prints
-one JSON line: FP64 MLUPS as ``value``, the FP32-shifted-storage MLUPS, the
-HBM roofline of the dominant (FP64 step) kernel and the CPU oracle timed on
-the host cores over a bounded sample of the same workload.
+one JSON line: FP64 MLUPS as ``value``, the FP32-shifted-storage MLUPS (shift
+rho_ref = gas density), the HBM roofline of the dominant (FP64 step) kernel,
+the adjoint's (forward + backward) / forward time on the 256 x 128 drop, the
+batched ensemble's aggregate MLUPS (256 instances, persistent graph-replayed
+launch vs one launch per instance) and the CPU oracle timed on the host cores
+over a bounded sample of the 4096 x 512 workload.
 """
 import argparse
 import hashlib
@@ -89,7 +92,75 @@ def copy_calibration():
     torch.cuda.synchronize()
 
 
-def cpu_baseline(rho, budget_s=15.0):
+def adjoint_ratio():
+    """(forward + backward) / forward time of the checkpointed adjoint on the
+    adjoint workload: 256 x 128 drop (R = 40), 2000 steps, interface radius
+    sampled every 50 steps on 16 rays, checkpoints every 100 steps,
+    gradients for a_2..a_6 (through rho0), G and tau."""
+    import numpy as np
+    import torch
+    from lbm_inputs import adjoint_coeffs, coexistence_densities, drop_density
+    from paper_1310_1871_amd import adjoint as A
+    nz, nr, R, Gc, tauc, steps, every, ck = 256, 128, 40.0, -5.5, 0.8, 2000, 50, 100
+    rg, rl = coexistence_densities(Gc)
+    probe = A.RayProbe(nz, nr, nz / 2.0, A.default_thetas(16), rl, rg)
+    rho_t = torch.from_numpy(drop_density(nz, nr, nz / 2.0, R, rl, rg, 2.0, adjoint_coeffs(11, R))).cuda()
+    target = A.radius_history(rho_t, Gc, tauc, probe, steps, every)
+    rho0 = torch.from_numpy(drop_density(nz, nr, nz / 2.0, R, rl, rg, 2.0, adjoint_coeffs(12, R))).cuda()
+    times = {}
+    for rep in range(2):  # the first repetition warms up
+        r0 = rho0.clone().requires_grad_(True)
+        G = torch.tensor(Gc, dtype=torch.float64, device="cuda", requires_grad=True)
+        tau = torch.tensor(tauc, dtype=torch.float64, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = A.shape_loss(r0, G, tau, probe, target, steps, every, ck)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times = {"fwd_s": t1 - t0, "bwd_s": t2 - t1, "loss": float(loss.item()),
+                 "dL_dG": float(G.grad.item()), "dL_dtau": float(tau.grad.item())}
+    times["fwd_bwd_over_fwd"] = round((times["fwd_s"] + times["bwd_s"]) / times["fwd_s"], 3)
+    times["workload"] = "drop 256x128 R=40, 2000 steps, 16 rays every 50 steps, checkpoint every 100, FP64"
+    return times
+
+
+def batch_throughput(steps=200):
+    """Batched ensemble: 256 seeded drops/threads of sizes 64x32 .. 512x256,
+    FP32 shifted storage; aggregate MLUPS of the autotuned persistent launch
+    (graph replay) and of one launch per instance per step."""
+    import torch
+    from lbm_inputs import ensemble
+    from paper_1310_1871_amd import batch as B
+    from paper_1310_1871_amd import lbm_axi as L
+    cases = ensemble()
+    params = [L.make_params(c.nz, c.nr, G=c.G, tau=c.tau, wall=c.wall, precision=L.FP32_SHIFTED, rho_ref=c.rho_g)
+              for c in cases]
+    b = B.AxiBatch(params, [torch.from_numpy(c.rho).cuda() for c in cases])
+    choice, _ = b.autotune(steps_per_trial=4)
+    nodes = b.nodes()
+    out = {"instances": len(cases), "nodes": nodes, "schedule": {"config": b.configs()[choice[0]],
+                                                                  "grid_per_cu": choice[1], "order": choice[2]}}
+    for name, fn in (("persistent_graph", b.step), ("per_instance_launches", b.step_per_instance)):
+        fn(20)
+        b.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(b.stream)
+        fn(steps)
+        e1.record(b.stream)
+        b.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[name] = {"ms_per_step": round(ms, 5), "MLUPS": round(nodes / (ms * 1e-3) / 1e6, 1)}
+    out["speedup_persistent_vs_per_instance"] = round(out["per_instance_launches"]["ms_per_step"] /
+                                                      out["persistent_graph"]["ms_per_step"], 3)
+    b.close()
+    return out
+
+
+def cpu_baseline(rho, budget_s=20.0):
     """The oracle as it stands, on the host cores, over whole steps of the
     same 4096 x 512 workload until about budget_s seconds have elapsed."""
     import ctypes
@@ -120,6 +191,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
     ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--skip-adjoint", action="store_true")
+    ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain copy kernel of known size (for counter calibration)")
     args = ap.parse_args()
@@ -158,16 +231,22 @@ def main():
     }
     if not args.skip_fp32:
         print(f"bench: thread {NZ}x{NR} FP32-shifted storage", file=sys.stderr, flush=True)
-        ms32, diag32 = time_gpu(1, rho, rl, args.steps, args.warmup)
+        ms32, diag32 = time_gpu(1, rho, rg, args.steps, args.warmup)
         mlups32 = lups / (ms32 * 1e-3) / 1e6
         ach32 = BYTES_PER_LU["f32"] * lups / (ms32 * 1e-3) / 1e9
         out["fp32_storage"] = {"value": round(mlups32, 2), "unit": "MLUPS", "ms_per_step": round(ms32, 6),
-                               "speedup_vs_f64": round(ms64 / ms32, 3), "rho_ref": round(rl, 5),
+                               "speedup_vs_f64": round(ms64 / ms32, 3), "rho_ref": round(rg, 5),
                                "roofline": {"bound": "hbm", "achieved": round(ach32, 1), "peak": HBM_PEAK_GBS,
                                             "unit": "GB/s", "frac": round(ach32 / HBM_PEAK_GBS, 4),
                                             "traffic": measured_traffic("f32")},
                                "mass_3d_rel_diff_vs_f64": abs(diag32[0] - diag64[0]) / diag64[0]}
     out["adjoint"] = None
+    if not args.skip_adjoint:
+        print("bench: adjoint (fwd+bwd)/fwd on the 256x128 drop", file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_ratio()
+    if not args.skip_batch:
+        print("bench: batched ensemble of 256 instances", file=sys.stderr, flush=True)
+        out["batch"] = batch_throughput()
     if args.copy_calibration:
         copy_calibration()
     if not args.skip_cpu:

@@ -388,7 +388,10 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         const bool valid = gz < nz && gr < nr;
         if (!valid) continue;
         const int uy = lr + 2, ux = lz + 2;
-        const C rho = rho_of(f[k]);
+        C sig = C(0);  // sum of the stored values: rho - rho_ref when shifted
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) sig += f[k][i];
+        const C rho = P::kShift ? sig + rho_ref : sig;
         const C jz = (f[k][1] - f[k][3]) + (f[k][5] - f[k][6]) + (f[k][8] - f[k][7]);
         const C jr = (f[k][2] - f[k][4]) + (f[k][5] - f[k][8]) + (f[k][6] - f[k][7]);
         const C uz = s_uz[uy * UZ + ux], ur = s_ur[uy * UZ + ux];
@@ -422,15 +425,31 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             const C qr = (jr + tau * Fr) * inv_rho;
             const C qq = C(1.5) * (qz * qz + qr * qr);
             const __amdgpu_buffer_rsrc_t fout = pop_rsrc(a.fout, a.state_bytes);
+            // FP32 weights sum to 1 + 7.45e-9, which would bias the mass of
+            // f^eq (and of h) by that fraction at every collision; in FP32 the
+            // rest direction is therefore taken last, as the remainder that
+            // makes sum_i f^eq_i = rho and sum_i h_i = -rho u_r / r hold
+            // (both hold exactly for the paper's weights)
+            constexpr bool kRem = sizeof(C) == 4;
+            C feq_acc = C(0), h_acc = C(0);
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) {
+            for (int ii = 0; ii < kQ; ++ii) {
+                const int i = kRem ? (ii + 1) % kQ : ii;
                 const C w = C(weight(i));
-                const C cu = C(cz(i)) * qz + C(cr(i)) * qr;
-                const C poly = C(3) * cu + C(4.5) * cu * cu - qq;
-                // f^eq(rho, u^eq) (Eq. e_distribution with u^eq throughout);
-                // in shifted storage, f^eq - W rho_ref
-                const C feq = P::kShift ? w * ((rho - rho_ref) + rho * poly) : w * rho * (C(1) + poly);
-                const C hi = w * (mass + C(3) * (C(cz(i)) * hz + C(cr(i)) * hr));
+                C feq, hi;
+                if (kRem && i == 0) {
+                    feq = sig - feq_acc;
+                    hi = mass - h_acc;
+                } else {
+                    const C cu = C(cz(i)) * qz + C(cr(i)) * qr;
+                    const C poly = C(3) * cu + C(4.5) * cu * cu - qq;
+                    // f^eq(rho, u^eq) (Eq. e_distribution with u^eq
+                    // throughout); in shifted storage, f^eq - W rho_ref
+                    feq = P::kShift ? w * (sig + rho * poly) : w * rho * (C(1) + poly);
+                    hi = w * (mass + C(3) * (C(cz(i)) * hz + C(cr(i)) * hr));
+                    feq_acc += feq;
+                    h_acc += hi;
+                }
                 const C fs = f[k][i] - (f[k][i] - feq) * inv_tau + hi;
                 // push to the neighbour with the pre-streaming boundary rules
                 int tz = gz + cz(i), trr = gr + cr(i), d = i;

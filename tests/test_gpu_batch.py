@@ -121,10 +121,14 @@ def test_schedules_agree_and_autotune_restores_state():
     for sched in [(1, 3, 1), (1, 4, 2)]:
         for x, y in zip(outs[(1, 1, 0)], outs[sched]):
             assert torch.equal(x, y)
-    # other tile shapes are other compiled kernels: FP32 rounding may differ
+    # other tile shapes are other compiled kernels whose FP32 rounding
+    # differs (contraction into FMAs, order of sums): after 20 steps the
+    # populations agree to a few ulp of the stored magnitudes (~1e-7 each
+    # step), far below any indexing or boundary mistake (>= 1e-3)
     for sched in [(2, 2, 1), (3, 4, 0)]:
-        for x, y in zip(outs[(1, 1, 0)], outs[sched]):
-            assert torch.allclose(x, y, rtol=1e-5, atol=1e-7)
+        diff = max(float((x - y).abs().max()) for x, y in zip(outs[(1, 1, 0)], outs[sched]))
+        _say(f"schedule {sched} vs (1, 1, 0): max |d f| = {diff:.3e}")
+        assert diff < 1e-5
     b.close()
 
 
