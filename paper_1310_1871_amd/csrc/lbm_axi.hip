@@ -22,8 +22,8 @@ using namespace lbm_host;
 
 // tile shape and workgroup size of the fused kernel per precision (chosen
 // by timing on MI355X: 4096 x 512 thread workload)
-constexpr int kTZ64 = 64, kTR64 = 32, kNT64 = 512;
-constexpr int kTZ32 = 128, kTR32 = 16, kNT32 = 512;
+constexpr int kTZ64 = 64, kTR64 = 32, kNT64 = 1024;
+constexpr int kTZ32 = 64, kTR32 = 32, kNT32 = 512;
 
 int tile_z(int precision) { return precision == LBM_AXI_FP64 ? kTZ64 : kTZ32; }
 int tile_r(int precision) { return precision == LBM_AXI_FP64 ? kTR64 : kTR32; }

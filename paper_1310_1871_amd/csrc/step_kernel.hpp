@@ -153,14 +153,18 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     constexpr int NPT = TZ * TR / NT;          // tile nodes per thread
     static_assert(NPT * NT == TZ * TR, "tile must be a multiple of the workgroup");
 
+    constexpr int NB = 4 * UZ;  // velocity ring: 2 rows below and 2 above the tile
+    constexpr int NS = 4 * TR;  // and 2 columns left and 2 right
+    constexpr int NU = NB + NS;
+
     __shared__ C s_psi[PR * PZ];
     __shared__ C s_dr[DR * DZ];
     __shared__ C s_uz[UR * UZ];
     __shared__ C s_ur[UR * UZ];
+    __shared__ C s_mom[3][NU];  // rho, j_z, j_r of the velocity-ring nodes
 
     const __amdgpu_buffer_rsrc_t fin = pop_rsrc(a.fin, a.state_bytes);
     const unsigned plane_bytes = (unsigned)a.plane * (unsigned)sizeof(S);
-    const long long n = a.plane;
     const int nz = a.nz, nr = a.nr;
     const bool big = a.big_nz != 0;
     const int t = threadIdx.x;
@@ -178,15 +182,32 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         for (int i = 0; i < kQ; ++i) s += v[i];
         return P::kShift ? s + rho_ref : s;
     };
+    auto jz_of = [](const C* v) { return (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]); };
+    auto jr_of = [](const C* v) { return (v[2] - v[4]) + (v[5] - v[8]) + (v[6] - v[7]); };
 
-    // ---- 1a. psi on the 6-node halo ring (loads issued before use) -------
+    // index of velocity-window node (uy, ux) in the compact ring arrays
+    // (the node must lie outside the tile)
+    auto ring_index = [](int uy, int ux) {
+        if (uy < 2) return uy * UZ + ux;
+        if (uy >= TR + 2) return (uy - TR) * UZ + ux;
+        const int side = ux < 2 ? 0 : 1;
+        return NB + side * 2 * TR + (uy - 2) * 2 + (side ? ux - TZ - 2 : ux);
+    };
+
+    // ---- 1. populations of the psi window (tile + 6-node ring) -----------
+    // Every load is issued before any is used.  Ring nodes give psi and,
+    // on the 2-node velocity ring, rho and j; tile nodes keep their
+    // populations in registers until the collision.  Rows outside the
+    // lattice read their mirror row (psi is even at the axis and the wall).
+    constexpr int NBAND = 12 * PZ;  // 6 rows below and 6 above the tile
+    constexpr int NSIDE = 12 * TR;  // 6 columns left and 6 right
+    constexpr int NRING = NBAND + NSIDE;
+    constexpr int NIT = (NRING + NT - 1) / NT;
+    const int lz = t % TZ, lrb = t / TZ;
+    C f[NPT][kQ];
     {
-        constexpr int NBAND = 12 * PZ;  // 6 rows below and 6 above the tile
-        constexpr int NSIDE = 12 * TR;  // 6 columns left and 6 right
-        constexpr int NRING = NBAND + NSIDE;
-        constexpr int NIT = (NRING + NT - 1) / NT;
         C v[NIT][kQ];
-        int slot[NIT];
+        int hrz[NIT];
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int idx = t + it * NT;
@@ -203,7 +224,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
                 hz = (side ? TZ + 6 : 0) + (jj - (jj / 6) * 6);
             }
             const bool live = idx < NRING;
-            slot[it] = live ? hr * PZ + hz : -1;
+            hrz[it] = live ? (hr << 16) | hz : -1;
             const int gz = wrap_z(z0 - 6 + hz, nz, big);
             const int gr = mirror_row(r0 - 6 + (live ? hr : 6), nr);
             const unsigned node = (unsigned)(gr * nz + gz);
@@ -211,21 +232,28 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             for (int i = 0; i < kQ; ++i) v[it][i] = live ? C(buf_load(fin, node * (unsigned)sizeof(S), i * plane_bytes, S())) : C(0);
         }
 #pragma unroll
-        for (int it = 0; it < NIT; ++it)
-            if (slot[it] >= 0) s_psi[slot[it]] = psi_of(rho_of(v[it]));
-    }
-
-    // ---- 1b. tile nodes: populations into registers, psi into LDS --------
-    const int lz = t % TZ, lrb = t / TZ;
-    C f[NPT][kQ];
+        for (int k = 0; k < NPT; ++k) {
+            const int lr = lrb + k * RSTEP;
+            const int gz = wrap_z(z0 + lz, nz, big);
+            const int gr = mirror_row(r0 + lr, nr);
+            const unsigned node = (unsigned)(gr * nz + gz);
 #pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-        const int lr = lrb + k * RSTEP;
-        const int gz = wrap_z(z0 + lz, nz, big);
-        const int gr = mirror_row(r0 + lr, nr);
-        const unsigned node = (unsigned)(gr * nz + gz);
+            for (int i = 0; i < kQ; ++i) f[k][i] = C(buf_load(fin, node * (unsigned)sizeof(S), i * plane_bytes, S()));
+        }
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) f[k][i] = C(buf_load(fin, node * (unsigned)sizeof(S), i * plane_bytes, S()));
+        for (int it = 0; it < NIT; ++it) {
+            if (hrz[it] < 0) continue;
+            const int hr = hrz[it] >> 16, hz = hrz[it] & 0xffff;
+            const C rho = rho_of(v[it]);
+            s_psi[hr * PZ + hz] = psi_of(rho);
+            const int uy = hr - 4, ux = hz - 4, gr = r0 - 6 + hr;
+            if (uy >= 0 && uy < UR && ux >= 0 && ux < UZ && gr >= 0 && gr < nr) {
+                const int o = ring_index(uy, ux);
+                s_mom[0][o] = rho;
+                s_mom[1][o] = jz_of(v[it]);
+                s_mom[2][o] = jr_of(v[it]);
+            }
+        }
     }
 #pragma unroll
     for (int k = 0; k < NPT; ++k) s_psi[(lrb + k * RSTEP + 6) * PZ + lz + 6] = psi_of(rho_of(f[k]));
@@ -278,43 +306,8 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         Fz += rho * gz_acc;
     };
 
-    // velocity at window node (uy, ux) of a row outside the tile's real
-    // rows: ghost rows take the value of their mirror row (u_r odd at the
-    // axis, even at the wall), computed again here from reloaded populations
-    auto ghost_velocity = [&](int uy, int ux) {
-        const int y = r0 - 2 + uy;
-        int ys = y;
-        C sgn = C(1);
-        if (y < 0) {
-            ys = -1 - y;
-            sgn = C(-1);
-        } else if (y >= nr) {
-            ys = 2 * nr - 1 - y;
-        }
-        const int uys = ys - (r0 - 2);
-        const int o = uy * UZ + ux;
-        if (ys < 0 || ys >= nr || uys < 0 || uys >= UR) {  // no real node reads this entry
-            s_uz[o] = C(0);
-            s_ur[o] = C(0);
-            return;
-        }
-        const int gz = wrap_z(z0 - 2 + ux, nz, big);
-        const unsigned node = (unsigned)(ys * nz + gz);
-        C v[kQ];
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) v[i] = C(buf_load(fin, node * (unsigned)sizeof(S), i * plane_bytes, S()));
-        const C rho = rho_of(v);
-        const C jz = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
-        const C jr = (v[2] - v[4]) + (v[5] - v[8]) + (v[6] - v[7]);
-        C Fz, Fr;
-        force_at(uys, ux, rho, C(ys) + C(0.5), Fz, Fr);
-        const C inv_rho = dev_rcp(rho);
-        s_uz[o] = (jz + C(0.5) * Fz) * inv_rho;
-        s_ur[o] = sgn * ((jr + C(0.5) * Fr) * inv_rho);
-    };
-
     C Fz_t[NPT], Fr_t[NPT];
-    // 3a. tile nodes; rows of real nodes use the populations in registers
+    // 3a. tile nodes of real rows, from the populations in registers
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int lr = lrb + k * RSTEP;
@@ -323,58 +316,63 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         Fr_t[k] = C(0);
         if (gr < nr) {
             const C rho = rho_of(f[k]);
-            const C jz = (f[k][1] - f[k][3]) + (f[k][5] - f[k][6]) + (f[k][8] - f[k][7]);
-            const C jr = (f[k][2] - f[k][4]) + (f[k][5] - f[k][8]) + (f[k][6] - f[k][7]);
             C Fz, Fr;
             force_at(lr + 2, lz + 2, rho, C(gr) + C(0.5), Fz, Fr);
             Fz_t[k] = Fz;
             Fr_t[k] = Fr;
             const C inv_rho = dev_rcp(rho);
-            s_uz[(lr + 2) * UZ + lz + 2] = (jz + C(0.5) * Fz) * inv_rho;
-            s_ur[(lr + 2) * UZ + lz + 2] = (jr + C(0.5) * Fr) * inv_rho;
-        } else {
-            ghost_velocity(lr + 2, lz + 2);
+            s_uz[(lr + 2) * UZ + lz + 2] = (jz_of(f[k]) + C(0.5) * Fz) * inv_rho;
+            s_ur[(lr + 2) * UZ + lz + 2] = (jr_of(f[k]) + C(0.5) * Fr) * inv_rho;
         }
     }
-    // 3b. the 2-node ring of the velocity window
-    {
-        constexpr int NB = 4 * UZ;   // 2 rows below and 2 above the tile
-        constexpr int NS = 4 * TR;   // 2 columns left and 2 right
-        for (int idx = t; idx < NB + NS; idx += NT) {
-            int uy, ux;
-            if (idx < NB) {
-                const int b = idx / UZ;
-                ux = idx - b * UZ;
-                uy = b < 2 ? b : TR + b;
-            } else {
-                const int j = idx - NB;
-                const int side = j / (2 * TR);
-                const int jj = j - side * 2 * TR;
-                uy = 2 + (jj >> 1);
-                ux = (side ? TZ + 2 : 0) + (jj & 1);
-            }
-            const int y = r0 - 2 + uy;
-            if (y >= 0 && y < nr) {
-                // real row: same arithmetic as the ghost path with ys = y
-                const int gz = wrap_z(z0 - 2 + ux, nz, big);
-                const unsigned node = (unsigned)(y * nz + gz);
-                C v[kQ];
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) v[i] = C(buf_load(fin, node * (unsigned)sizeof(S), i * plane_bytes, S()));
-                const C rho = rho_of(v);
-                const C jz = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
-                const C jr = (v[2] - v[4]) + (v[5] - v[8]) + (v[6] - v[7]);
-                C Fz, Fr;
-                force_at(uy, ux, rho, C(y) + C(0.5), Fz, Fr);
-                const C inv_rho = dev_rcp(rho);
-                s_uz[uy * UZ + ux] = (jz + C(0.5) * Fz) * inv_rho;
-                s_ur[uy * UZ + ux] = (jr + C(0.5) * Fr) * inv_rho;
-            } else {
-                ghost_velocity(uy, ux);
-            }
+    // 3b. velocity-ring nodes of real rows, from rho and j in LDS
+    for (int idx = t; idx < NU; idx += NT) {
+        int uy, ux;
+        if (idx < NB) {
+            const int b = idx / UZ;
+            ux = idx - b * UZ;
+            uy = b < 2 ? b : TR + b;
+        } else {
+            const int j = idx - NB;
+            const int side = j / (2 * TR);
+            const int jj = j - side * 2 * TR;
+            uy = 2 + (jj >> 1);
+            ux = (side ? TZ + 2 : 0) + (jj & 1);
         }
+        const int y = r0 - 2 + uy;
+        if (y < 0 || y >= nr) continue;
+        const C rho = s_mom[0][idx];
+        C Fz, Fr;
+        force_at(uy, ux, rho, C(y) + C(0.5), Fz, Fr);
+        const C inv_rho = dev_rcp(rho);
+        s_uz[uy * UZ + ux] = (s_mom[1][idx] + C(0.5) * Fz) * inv_rho;
+        s_ur[uy * UZ + ux] = (s_mom[2][idx] + C(0.5) * Fr) * inv_rho;
     }
     __syncthreads();
+    // 3c. rows outside the lattice (only in tiles at the axis or the wall):
+    // the velocity of the mirror row, u_r odd at the axis and even at the
+    // wall; entries no real node reads are zeroed
+    const int axis_rows = r0 < 2 ? 2 - r0 : 0;  // velocity-window rows below the axis
+    const int wall_lo = nr - (r0 - 2);           // first velocity-window row beyond the wall
+    if (axis_rows > 0 || wall_lo < UR) {         // uniform over the workgroup
+        for (int idx = t; idx < UR * UZ; idx += NT) {
+            const int uy = idx / UZ, ux = idx - uy * UZ;
+            const bool axis_side = uy < axis_rows;
+            if (!axis_side && uy < wall_lo) continue;
+            const int y = r0 - 2 + uy;
+            const int ys = axis_side ? -1 - y : 2 * nr - 1 - y;
+            const C sgn = axis_side ? C(-1) : C(1);
+            const int uys = ys - (r0 - 2);
+            if (ys < 0 || ys >= nr || uys < 0 || uys >= UR) {
+                s_uz[idx] = C(0);
+                s_ur[idx] = C(0);
+            } else {
+                s_uz[idx] = s_uz[uys * UZ + ux];
+                s_ur[idx] = sgn * s_ur[uys * UZ + ux];
+            }
+        }
+        __syncthreads();
+    }
 
     // ---- 4. collision + streaming (or moments) for the tile nodes --------
     const C tau = C(a.tau);
