@@ -110,6 +110,13 @@ size_t lbm_axi_state_bytes(lbm_axi_t h);
 int lbm_axi_get_state(lbm_axi_t h, void* d_dst);
 int lbm_axi_set_state(lbm_axi_t h, const void* d_src);
 
+/* Record a trajectory segment: with the handle at state f^t, writes
+ * f^t, f^{t+1}, ..., f^{t+n-1} to d_states (n consecutive blocks of
+ * lbm_axi_state_bytes bytes each, the library's layout) and leaves the
+ * handle at f^{t+n-1} (n - 1 steps).  n >= 1.  For checkpointed reverse
+ * sweeps, which need every state of a segment.  Asynchronous. */
+int lbm_axi_record(lbm_axi_t h, int64_t n, void* d_states);
+
 /* Rebind the stream later calls are issued on. */
 int lbm_axi_set_stream(lbm_axi_t h, void* hip_stream);
 

@@ -42,6 +42,16 @@ size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr);
 int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const double* d_lam_next, double* d_lam,
                          double* d_grad_acc, void* d_ws, size_t ws_bytes, void* hip_stream);
 
+/* k reverse steps over a recorded segment (lbm_axi_record, FP64):
+ * d_states holds f^{t0}, ..., f^{t0+k-1} ([k][9][nr][nz]).  On entry d_lam
+ * holds lam^{t0+k} = dL/df^{t0+k}; on return it holds lam^{t0}, the same
+ * values as k calls of lbm_axi_adjoint_step from the last state back to the
+ * first.  d_tmp: scratch of 9 nz nr doubles (not aliasing d_lam).
+ * d_grad_acc (may be NULL) accumulates dL/dG, dL/dtau over the k steps.
+ * k >= 0 (0 leaves d_lam unchanged). */
+int lbm_axi_adjoint_run(const lbm_axi_params* p, const double* d_states, int32_t k, double* d_lam, double* d_tmp,
+                        double* d_grad_acc, void* d_ws, size_t ws_bytes, void* hip_stream);
+
 /* Adjoint of the initial equilibrium f_i = f^eq_i(rho0, u0) (appendix,
  * Eq. e_distribution): d_rho0_bar = sum_i d_lam0_i df^eq_i/drho0.
  * d_uz0 / d_ur0 may be NULL (zero initial velocity). */

@@ -24,6 +24,8 @@ _d = ctypes.c_double
 _sigs = {
     "lbm_axi_adjoint_workspace_bytes": (ctypes.c_size_t, [_i32, _i32]),
     "lbm_axi_adjoint_step": (ctypes.c_int, [ctypes.POINTER(L.Params), _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "lbm_axi_adjoint_run": (ctypes.c_int, [ctypes.POINTER(L.Params), _vp, _i32, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                           _vp]),
     "lbm_axi_init_vjp": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _vp, _vp]),
     "lbm_axi_density": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp]),
     "lbm_axi_ray_weights": (ctypes.c_int, [_i32, _i32, _d, _vp, _i32, _d, _d, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -121,6 +123,12 @@ def adjoint_step(params, f, lam_next, lam, grad_acc, ws):
                                      ws.numel() * ws.element_size(), _s()))
 
 
+def adjoint_run(params, states, k, lam, tmp, grad_acc, ws):
+    """k reverse steps over states[0..k) (lam: lam^{t0+k} in, lam^{t0} out)."""
+    _check(_lib.lbm_axi_adjoint_run(ctypes.byref(params), _p(states), int(k), _p(lam), _p(tmp), _p(grad_acc), _p(ws),
+                                    ws.numel() * ws.element_size(), _s()))
+
+
 class ShapeLoss(torch.autograd.Function):
     """loss = sum_t sum_m (r(theta_m, t) - target[t, m])^2 of a run started
     from f^eq(rho0, 0); differentiable in rho0, G and tau.
@@ -141,12 +149,16 @@ class ShapeLoss(torch.autograd.Function):
         rbar = torch.zeros((nsamp, probe.m), dtype=torch.float64, device=dev)
         r = torch.empty(probe.m, dtype=torch.float64, device=dev)
         ckpts = []
-        for t in range(steps):
+        t = 0
+        while t < steps:
             if t % checkpoint == 0:
                 ckpts.append(_state_view(sim).clone())
-            sim.step(1)
-            if (t + 1) % every == 0:
-                k = (t + 1) // every - 1
+            # advance to the next checkpoint or sample step in one call
+            nxt = min((t // every + 1) * every, (t // checkpoint + 1) * checkpoint, steps)
+            sim.step(nxt - t)
+            t = nxt
+            if t % every == 0:
+                k = t // every - 1
                 probe.radius_of_state(_state_view(sim), r)
                 _check(_lib.lbm_axi_misfit(_p(r), _p(target[k]), probe.m, _p(loss), _p(rbar[k]), _s()))
         sim.close()
@@ -172,21 +184,22 @@ class ShapeLoss(torch.autograd.Function):
         sim = None
         for s in reversed(range(len(ckpts))):
             t0 = s * checkpoint
-            # recompute the states f^t, t0 <= t < t0 + checkpoint
+            # recompute the states f^t, t0 <= t < t0 + checkpoint, in one call
             if sim is None:
                 sim = L.AxiLBM(params, rho0.detach())
-            raw = ckpts[s].reshape(-1).view(torch.uint8)
-            sim.set_state(raw)
-            for j in range(checkpoint):
-                seg_states[j].copy_(_state_view(sim))
-                if j + 1 < checkpoint:
-                    sim.step(1)
-            for j in reversed(range(checkpoint)):
-                t = t0 + j
-                adjoint_step(params, seg_states[j], lam_a, lam_b, grad_acc, ws)
-                if t > 0 and t % every == 0:
-                    probe.add_vjp(scaled_rbar[t // every - 1], lam_b)
-                lam_a, lam_b = lam_b, lam_a
+            sim.set_state(ckpts[s].reshape(-1).view(torch.uint8))
+            sim.record(checkpoint, seg_states)
+            # reverse sweep in runs between sample steps; after lam^t is
+            # formed at a sample step t > 0, its misfit VJP is added
+            hi = checkpoint
+            for j in range(checkpoint - 1, 0, -1):
+                if (t0 + j) % every == 0:
+                    adjoint_run(params, seg_states[j], hi - j, lam_a, lam_b, grad_acc, ws)
+                    probe.add_vjp(scaled_rbar[(t0 + j) // every - 1], lam_a)
+                    hi = j
+            adjoint_run(params, seg_states[0], hi, lam_a, lam_b, grad_acc, ws)
+            if t0 > 0 and t0 % every == 0:
+                probe.add_vjp(scaled_rbar[t0 // every - 1], lam_a)
         if sim is not None:
             sim.close()
         rho_bar = torch.empty((nr, nz), dtype=torch.float64, device=dev)

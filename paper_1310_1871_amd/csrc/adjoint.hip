@@ -34,6 +34,9 @@
 namespace {
 
 constexpr int NGA = 6;  // ghost rows kept on extended adjoint fields
+// workgroup size of the per-node adjoint kernels: one wave, so that small
+// lattices still spread over every compute unit
+constexpr int kAdjBlock = 64;
 
 struct AdjArgs {
     int nz, nr;
@@ -49,8 +52,7 @@ struct AdjArgs {
 
 // field slots inside the workspace (each n doubles)
 enum Slot {
-    S_RHO, S_JZ, S_JR, S_PSI, S_DRR, S_D1, S_DZR, S_FZ, S_FR, S_SCZ, S_SCR, S_UZ, S_UR, S_QZ, S_QR,
-    S_DRUZ, S_DZUR, S_DRUR,
+    S_RHO, S_JZ, S_JR, S_PSI, S_DRR, S_DZR, S_FZ, S_FR, S_SCZ, S_SCR, S_UZ, S_UR, S_QZ, S_QR,
     // adjoints
     S_RHOB, S_JZB, S_JRB, S_UZB_H, S_URB_H, S_FZB, S_FRB, S_DRUZB, S_DZURB, S_DRURB,
     S_PSIB_LOC, S_DZRB, S_DRRB, S_DRB_REAL, S_D1B, S_FSCZB, S_FSCRB, S_GB, S_TAUB,
@@ -62,6 +64,8 @@ enum SlotE { E_PSI, E_DR, E_UZ, E_UR, E_DRB, E_NSLOT };
 __host__ __device__ inline size_t slot_off(int s, long long n) { return (size_t)s * n; }
 __host__ __device__ inline size_t eslot_off(int s, long long n, long long ne) { return (size_t)S_NSLOT * n + (size_t)s * ne; }
 __host__ __device__ inline size_t fbar_off(long long n, long long ne) { return (size_t)S_NSLOT * n + (size_t)E_NSLOT * ne; }
+// after f-bar: per-block partial sums of dL/dG and dL/dtau ([block][2])
+__host__ __device__ inline size_t part_off(long long n, long long ne) { return fbar_off(n, ne) + 9 * (size_t)n; }
 
 __device__ __forceinline__ int wrapz(int z, int nz) {
     int w = z % nz;
@@ -100,10 +104,18 @@ __device__ double d_iso_e(const double* E, int z, int y, int nz, bool along_r) {
 
 // ------------------------------------------------------------ forward ----
 
+// rho, j, psi on the real rows and psi on the extended rows -6 .. nr+5
+// (a ghost row takes the value of its mirror row: psi is even at the axis
+// and at the wall)
 __global__ void fwd_moments(AdjArgs a) {
-    NODE_LOOP(a)
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.ne) return;
+    const int y = (int)(e / a.nz) - NGA, z = (int)(e - (long long)(y + NGA) * a.nz);
+    double sgn;
+    const int ys = mirror_src(y, a.nr, sgn, 1.0);
     double* w = a.w;
     const long long n = a.n;
+    const long long x = (long long)ys * a.nz + z;
     double rho = 0, jz = 0, jr = 0;
 #pragma unroll
     for (int i = 0; i < lbm::kQ; ++i) {
@@ -112,21 +124,14 @@ __global__ void fwd_moments(AdjArgs a) {
         jz += lbm::cz(i) * fi;
         jr += lbm::cr(i) * fi;
     }
-    w[slot_off(S_RHO, n) + x] = rho;
-    w[slot_off(S_JZ, n) + x] = jz;
-    w[slot_off(S_JR, n) + x] = jr;
-    w[slot_off(S_PSI, n) + x] = a.rho0 * (1.0 - exp(-rho / a.rho0));
-}
-
-// extended copy of a real-row field with mirror parity at the axis and an
-// even mirror at the wall
-__global__ void fwd_extend(AdjArgs a, int src_slot, int dst_eslot, double axis_sign) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= a.ne) return;
-    const int y = (int)(e / a.nz) - NGA, z = (int)(e - (long long)(y + NGA) * a.nz);
-    double sgn;
-    const int ys = mirror_src(y, a.nr, sgn, axis_sign);
-    a.w[eslot_off(dst_eslot, a.n, a.ne) + e] = sgn * a.w[slot_off(src_slot, a.n) + (long long)ys * a.nz + z];
+    const double psi = a.rho0 * (1.0 - exp(-rho / a.rho0));
+    if (y == ys) {
+        w[slot_off(S_RHO, n) + x] = rho;
+        w[slot_off(S_JZ, n) + x] = jz;
+        w[slot_off(S_JR, n) + x] = jr;
+        w[slot_off(S_PSI, n) + x] = psi;
+    }
+    w[eslot_off(E_PSI, n, a.ne) + e] = psi;
 }
 
 // isotropic d_r psi on extended rows -4 .. nr+3 (zero elsewhere)
@@ -140,25 +145,29 @@ __global__ void fwd_dr(AdjArgs a) {
     a.w[eslot_off(E_DR, a.n, a.ne) + e] = v;
 }
 
-__global__ void fwd_second(AdjArgs a) {
-    NODE_LOOP(a)
-    const double* psiE = a.w + eslot_off(E_PSI, a.n, a.ne);
-    const double* drE = a.w + eslot_off(E_DR, a.n, a.ne);
-    a.w[slot_off(S_DRR, a.n) + x] = d_iso_e(drE, z, r, a.nz, true);
-    a.w[slot_off(S_D1, a.n) + x] = (-psiE[eidx(r + 2, z, a.nz)] + 8.0 * psiE[eidx(r + 1, z, a.nz)] -
-                                    8.0 * psiE[eidx(r - 1, z, a.nz)] + psiE[eidx(r - 2, z, a.nz)]) / 12.0;
-}
-
+// forces, hydrodynamic and equilibrium velocities on the real rows, and the
+// velocity on the extended rows (a ghost row recomputes its mirror row's
+// value: u_z even, u_r odd at the axis and even at the wall)
 __global__ void fwd_force(AdjArgs a) {
-    NODE_LOOP(a)
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.ne) return;
+    const int y = (int)(e / a.nz) - NGA, z = (int)(e - (long long)(y + NGA) * a.nz);
+    double sgn;
+    const int r = mirror_src(y, a.nr, sgn, -1.0);
     double* w = a.w;
     const long long n = a.n;
     const int nz = a.nz;
-    const double* d1 = w + slot_off(S_D1, n) + (long long)r * nz;
-    const double dzr = (-d1[wrapz(z + 2, nz)] + 8.0 * d1[wrapz(z + 1, nz)] - 8.0 * d1[wrapz(z - 1, nz)] +
-                        d1[wrapz(z - 2, nz)]) / 12.0;
-    w[slot_off(S_DZR, n) + x] = dzr;
+    const long long x = (long long)r * nz + z;
     const double* psiE = w + eslot_off(E_PSI, n, a.ne);
+    const double* drE = w + eslot_off(E_DR, n, a.ne);
+    // 1D fourth-order d_z of the 1D fourth-order d_r (Sec. II.D)
+    auto d1 = [&](int zz) {
+        zz = wrapz(zz, nz);
+        return (-psiE[eidx(r + 2, zz, nz)] + 8.0 * psiE[eidx(r + 1, zz, nz)] - 8.0 * psiE[eidx(r - 1, zz, nz)] +
+                psiE[eidx(r - 2, zz, nz)]) / 12.0;
+    };
+    const double dzr = (-d1(z + 2) + 8.0 * d1(z + 1) - 8.0 * d1(z - 1) + d1(z - 2)) / 12.0;
+    const double drr = d_iso_e(drE, z, r, nz, true);
     double sz = 0, sr = 0;
 #pragma unroll
     for (int i = 1; i < lbm::kQ; ++i) {
@@ -167,33 +176,30 @@ __global__ void fwd_force(AdjArgs a) {
         sr += lbm::weight(i) * ps * lbm::cr(i);
     }
     const double psi = w[slot_off(S_PSI, n) + x], rho = w[slot_off(S_RHO, n) + x];
-    w[slot_off(S_SCZ, n) + x] = sz;
-    w[slot_off(S_SCR, n) + x] = sr;
     double Fz = -a.G * psi * sz, Fr = -a.G * psi * sr;
     if (a.axisym) {
         const double rr = r + 0.5;
-        const double dr1 = w[eslot_off(E_DR, n, a.ne) + eidx(r, z, nz)];
-        const double drr = w[slot_off(S_DRR, n) + x];
+        const double dr1 = drE[eidx(r, z, nz)];
         Fz += -(a.G / 18.0) * psi * dzr / rr;
         Fr += -(a.G / 18.0) * psi * (drr / rr - dr1 / (rr * rr));
     }
     Fz += rho * a.gz;
-    w[slot_off(S_FZ, n) + x] = Fz;
-    w[slot_off(S_FR, n) + x] = Fr;
     const double jz = w[slot_off(S_JZ, n) + x], jr = w[slot_off(S_JR, n) + x];
-    w[slot_off(S_UZ, n) + x] = (jz + 0.5 * Fz) / rho;
-    w[slot_off(S_UR, n) + x] = (jr + 0.5 * Fr) / rho;
-    w[slot_off(S_QZ, n) + x] = (jz + a.tau * Fz) / rho;
-    w[slot_off(S_QR, n) + x] = (jr + a.tau * Fr) / rho;
-}
-
-__global__ void fwd_velocity_gradients(AdjArgs a) {
-    NODE_LOOP(a)
-    const double* uzE = a.w + eslot_off(E_UZ, a.n, a.ne);
-    const double* urE = a.w + eslot_off(E_UR, a.n, a.ne);
-    a.w[slot_off(S_DRUZ, a.n) + x] = d_iso_e(uzE, z, r, a.nz, true);
-    a.w[slot_off(S_DZUR, a.n) + x] = d_iso_e(urE, z, r, a.nz, false);
-    a.w[slot_off(S_DRUR, a.n) + x] = d_iso_e(urE, z, r, a.nz, true);
+    const double uz = (jz + 0.5 * Fz) / rho, ur = (jr + 0.5 * Fr) / rho;
+    if (y == r) {
+        w[slot_off(S_DZR, n) + x] = dzr;
+        w[slot_off(S_DRR, n) + x] = drr;
+        w[slot_off(S_SCZ, n) + x] = sz;
+        w[slot_off(S_SCR, n) + x] = sr;
+        w[slot_off(S_FZ, n) + x] = Fz;
+        w[slot_off(S_FR, n) + x] = Fr;
+        w[slot_off(S_UZ, n) + x] = uz;
+        w[slot_off(S_UR, n) + x] = ur;
+        w[slot_off(S_QZ, n) + x] = (jz + a.tau * Fz) / rho;
+        w[slot_off(S_QR, n) + x] = (jr + a.tau * Fr) / rho;
+    }
+    w[eslot_off(E_UZ, n, a.ne) + e] = uz;
+    w[eslot_off(E_UR, n, a.ne) + e] = sgn * ur;
 }
 
 // ------------------------------------------------------------ reverse ----
@@ -258,8 +264,10 @@ __global__ void rev_collision(AdjArgs a) {
     double uzb = 0, urb = 0, druzb = 0, dzurb = 0, drurb = 0;
     if (a.axisym) {
         const double mu = rho * (tau - 0.5) / 3.0;
-        const double druz = w[slot_off(S_DRUZ, n) + x], dzur = w[slot_off(S_DZUR, n) + x],
-                     drur = w[slot_off(S_DRUR, n) + x];
+        const double* uzE = w + eslot_off(E_UZ, n, a.ne);
+        const double* urE = w + eslot_off(E_UR, n, a.ne);
+        const double druz = d_iso_e(uzE, z, r, a.nz, true), dzur = d_iso_e(urE, z, r, a.nz, false),
+                     drur = d_iso_e(urE, z, r, a.nz, true);
         // mass = -rho u_r / r
         rhob += -massb * ur / rr;
         urb += -massb * rho / rr;
@@ -441,31 +449,57 @@ __device__ double psi_ext_adjoint(const AdjArgs& a, int z, int e) {
 }
 
 // step 4 for psi (fold every image of the row), step 5, write lam
+// Last reverse kernel: lam = f-bar + rho-bar + c . j-bar, and the block's
+// partial sums of the node contributions to dL/dG and dL/dtau (a fixed
+// tree order, so the result does not depend on scheduling).
 __global__ void rev_psi_final(AdjArgs a) {
-    NODE_LOOP(a)
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double* w = a.w;
     const long long n = a.n;
-    const int nr = a.nr;
-    double psib = w[slot_off(S_PSIB_LOC, n) + x] + psi_ext_adjoint(a, z, r);
-    if (r <= 3) psib += psi_ext_adjoint(a, z, -1 - r);            // axis images (rows -4..-1)
-    if (r >= nr - 4) psib += psi_ext_adjoint(a, z, 2 * nr - 1 - r);  // wall images (rows nr..nr+3)
-    const double rho = w[slot_off(S_RHO, n) + x];
-    const double rhob = w[slot_off(S_RHOB, n) + x] + psib * exp(-rho / a.rho0);
-    const double jzb = w[slot_off(S_JZB, n) + x], jrb = w[slot_off(S_JRB, n) + x];
-    const double* fbar = w + fbar_off(n, a.ne);
+    double g = 0.0, q = 0.0;
+    if (x < n) {
+        const int nr = a.nr;
+        const int r = (int)(x / a.nz), z = (int)(x - (long long)r * a.nz);
+        double psib = w[slot_off(S_PSIB_LOC, n) + x] + psi_ext_adjoint(a, z, r);
+        if (r <= 3) psib += psi_ext_adjoint(a, z, -1 - r);            // axis images (rows -4..-1)
+        if (r >= nr - 4) psib += psi_ext_adjoint(a, z, 2 * nr - 1 - r);  // wall images (rows nr..nr+3)
+        const double rho = w[slot_off(S_RHO, n) + x];
+        const double rhob = w[slot_off(S_RHOB, n) + x] + psib * exp(-rho / a.rho0);
+        const double jzb = w[slot_off(S_JZB, n) + x], jrb = w[slot_off(S_JRB, n) + x];
+        const double* fbar = w + fbar_off(n, a.ne);
 #pragma unroll
-    for (int i = 0; i < lbm::kQ; ++i)
-        a.lam[i * n + x] = fbar[i * n + x] + rhob + lbm::cz(i) * jzb + lbm::cr(i) * jrb;
+        for (int i = 0; i < lbm::kQ; ++i)
+            a.lam[i * n + x] = fbar[i * n + x] + rhob + lbm::cz(i) * jzb + lbm::cr(i) * jrb;
+        g = w[slot_off(S_GB, n) + x];
+        q = w[slot_off(S_TAUB, n) + x];
+    }
+    __shared__ double s[2][kAdjBlock];
+    const int t = threadIdx.x;
+    s[0][t] = g;
+    s[1][t] = q;
+    __syncthreads();
+    for (int k = kAdjBlock / 2; k > 0; k >>= 1) {
+        if (t < k) {
+            s[0][t] += s[0][t + k];
+            s[1][t] += s[1][t + k];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        w[part_off(n, a.ne) + 2 * (size_t)blockIdx.x] = s[0][0];
+        w[part_off(n, a.ne) + 2 * (size_t)blockIdx.x + 1] = s[1][0];
+    }
 }
-
-// fixed-order reduction of the per-node dL/dG, dL/dtau into acc[0..1]
-__global__ void rev_reduce(AdjArgs a, double* acc) {
+// acc[0] += dL/dG, acc[1] += dL/dtau of this step: the block partials
+// summed in a fixed order
+__global__ void rev_reduce(AdjArgs a, int nparts, double* acc) {
     __shared__ double s[2][256];
     const int t = threadIdx.x;
+    const double* part = a.w + part_off(a.n, a.ne);
     double g = 0.0, q = 0.0;
-    for (long long x = t; x < a.n; x += 256) {
-        g += a.w[slot_off(S_GB, a.n) + x];
-        q += a.w[slot_off(S_TAUB, a.n) + x];
+    for (int b = t; b < nparts; b += 256) {
+        g += part[2 * (size_t)b];
+        q += part[2 * (size_t)b + 1];
     }
     s[0][t] = g;
     s[1][t] = q;
@@ -567,7 +601,8 @@ extern "C" {
 size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr) {
     if (nz < 1 || nr < 6) return 0;
     const long long n = (long long)nz * nr, ne = (long long)nz * (nr + 2 * NGA);
-    return ((size_t)S_NSLOT * n + (size_t)E_NSLOT * ne + 9 * (size_t)n) * sizeof(double);
+    const size_t nparts = (size_t)((n + kAdjBlock - 1) / kAdjBlock);
+    return ((size_t)S_NSLOT * n + (size_t)E_NSLOT * ne + 9 * (size_t)n + 2 * nparts) * sizeof(double);
 }
 
 int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const double* d_lam_next, double* d_lam,
@@ -593,22 +628,39 @@ int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const doubl
     a.lam_next = d_lam_next;
     a.lam = d_lam;
     a.w = static_cast<double*>(d_ws);
-    const dim3 b(256);
-    hipLaunchKernelGGL(fwd_moments, dim3(nblk(a.n)), b, 0, s, a);
-    hipLaunchKernelGGL(fwd_extend, dim3(nblk(a.ne)), b, 0, s, a, (int)S_PSI, (int)E_PSI, 1.0);
-    hipLaunchKernelGGL(fwd_dr, dim3(nblk(a.ne)), b, 0, s, a);
-    hipLaunchKernelGGL(fwd_second, dim3(nblk(a.n)), b, 0, s, a);
-    hipLaunchKernelGGL(fwd_force, dim3(nblk(a.n)), b, 0, s, a);
-    hipLaunchKernelGGL(fwd_extend, dim3(nblk(a.ne)), b, 0, s, a, (int)S_UZ, (int)E_UZ, 1.0);
-    hipLaunchKernelGGL(fwd_extend, dim3(nblk(a.ne)), b, 0, s, a, (int)S_UR, (int)E_UR, -1.0);
-    hipLaunchKernelGGL(fwd_velocity_gradients, dim3(nblk(a.n)), b, 0, s, a);
-    hipLaunchKernelGGL(rev_collision, dim3(nblk(a.n)), b, 0, s, a);
-    hipLaunchKernelGGL(rev_velocity_force, dim3(nblk(a.n)), b, 0, s, a);
-    hipLaunchKernelGGL(rev_dzr, dim3(nblk(a.n)), b, 0, s, a);
-    hipLaunchKernelGGL(rev_dr, dim3(nblk(a.ne)), b, 0, s, a);
-    hipLaunchKernelGGL(rev_psi_final, dim3(nblk(a.n)), b, 0, s, a);
-    if (d_grad_acc) hipLaunchKernelGGL(rev_reduce, dim3(1), b, 0, s, a, d_grad_acc);
+    const dim3 b(kAdjBlock);
+    const int bn = (int)((a.n + kAdjBlock - 1) / kAdjBlock), be = (int)((a.ne + kAdjBlock - 1) / kAdjBlock);
+    hipLaunchKernelGGL(fwd_moments, dim3(be), b, 0, s, a);
+    hipLaunchKernelGGL(fwd_dr, dim3(be), b, 0, s, a);
+    hipLaunchKernelGGL(fwd_force, dim3(be), b, 0, s, a);
+    hipLaunchKernelGGL(rev_collision, dim3(bn), b, 0, s, a);
+    hipLaunchKernelGGL(rev_velocity_force, dim3(bn), b, 0, s, a);
+    hipLaunchKernelGGL(rev_dzr, dim3(bn), b, 0, s, a);
+    hipLaunchKernelGGL(rev_dr, dim3(be), b, 0, s, a);
+    hipLaunchKernelGGL(rev_psi_final, dim3(bn), b, 0, s, a);
+    if (d_grad_acc) hipLaunchKernelGGL(rev_reduce, dim3(1), dim3(256), 0, s, a, bn, d_grad_acc);
     return hipGetLastError() == hipSuccess ? LBM_AXI_OK : LBM_AXI_EHIP;
+}
+
+int lbm_axi_adjoint_run(const lbm_axi_params* p, const double* d_states, int32_t k, double* d_lam, double* d_tmp,
+                        double* d_grad_acc, void* d_ws, size_t ws_bytes, void* hip_stream) {
+    if (!p || !d_states || !d_lam || !d_tmp || d_tmp == d_lam || k < 0) return LBM_AXI_EINVAL;
+    const size_t n9 = 9 * (size_t)p->nz * (size_t)p->nr;
+    double* cur = d_lam;  // holds lam^{t0+j+1} before step j
+    double* nxt = d_tmp;
+    for (int32_t j = k - 1; j >= 0; --j) {
+        const int rc = lbm_axi_adjoint_step(p, d_states + (size_t)j * n9, cur, nxt, d_grad_acc, d_ws, ws_bytes,
+                                            hip_stream);
+        if (rc != LBM_AXI_OK) return rc;
+        double* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if (cur != d_lam &&
+        hipMemcpyAsync(d_lam, cur, n9 * sizeof(double), hipMemcpyDeviceToDevice, static_cast<hipStream_t>(hip_stream)) !=
+            hipSuccess)
+        return LBM_AXI_EHIP;
+    return LBM_AXI_OK;
 }
 
 int lbm_axi_init_vjp(const double* d_lam0, const double* d_uz0, const double* d_ur0, int32_t nz, int32_t nr,

@@ -22,9 +22,9 @@ struct Config {
     int tz, tr, nt;
 };
 // compiled configurations per precision (index = configuration id)
-constexpr Config kCfg32[] = {{64, 16, 256}, {64, 16, 512}, {128, 16, 512}, {64, 32, 512}};
-constexpr Config kCfg64[] = {{64, 16, 512}, {64, 32, 512}, {64, 32, 1024}};
-constexpr int kNCfg32 = 4, kNCfg64 = 3;
+constexpr Config kCfg32[] = {{64, 16, 256}, {64, 16, 512}, {128, 16, 512}, {64, 32, 512}, {32, 16, 512}};
+constexpr Config kCfg64[] = {{64, 16, 512}, {64, 32, 512}, {64, 32, 1024}, {32, 16, 512}};
+constexpr int kNCfg32 = 5, kNCfg64 = 4;
 
 template <class P, int TZ, int TR, int NT>
 void launch_batch_t(dim3 grid, hipStream_t s, const lbm::BatchInstance* insts, const int2* items, int n, int parity) {
@@ -39,17 +39,20 @@ using BatchFn = void (*)(dim3, hipStream_t, const lbm::BatchInstance*, const int
 using TileFn = void (*)(dim3, hipStream_t, const lbm::StepArgs&);
 
 constexpr BatchFn kBatch32[] = {launch_batch_t<lbm::PrecF32S, 64, 16, 256>, launch_batch_t<lbm::PrecF32S, 64, 16, 512>,
-                                launch_batch_t<lbm::PrecF32S, 128, 16, 512>, launch_batch_t<lbm::PrecF32S, 64, 32, 512>};
+                                launch_batch_t<lbm::PrecF32S, 128, 16, 512>, launch_batch_t<lbm::PrecF32S, 64, 32, 512>,
+                                launch_batch_t<lbm::PrecF32S, 32, 16, 512>};
 constexpr BatchFn kBatch64[] = {launch_batch_t<lbm::PrecF64, 64, 16, 512>, launch_batch_t<lbm::PrecF64, 64, 32, 512>,
-                                launch_batch_t<lbm::PrecF64, 64, 32, 1024>};
+                                launch_batch_t<lbm::PrecF64, 64, 32, 1024>, launch_batch_t<lbm::PrecF64, 32, 16, 512>};
 constexpr TileFn kStep32[] = {launch_tile_t<lbm::PrecF32S, 64, 16, 256, false>, launch_tile_t<lbm::PrecF32S, 64, 16, 512, false>,
-                              launch_tile_t<lbm::PrecF32S, 128, 16, 512, false>, launch_tile_t<lbm::PrecF32S, 64, 32, 512, false>};
+                              launch_tile_t<lbm::PrecF32S, 128, 16, 512, false>, launch_tile_t<lbm::PrecF32S, 64, 32, 512, false>,
+                              launch_tile_t<lbm::PrecF32S, 32, 16, 512, false>};
 constexpr TileFn kStep64[] = {launch_tile_t<lbm::PrecF64, 64, 16, 512, false>, launch_tile_t<lbm::PrecF64, 64, 32, 512, false>,
-                              launch_tile_t<lbm::PrecF64, 64, 32, 1024, false>};
+                              launch_tile_t<lbm::PrecF64, 64, 32, 1024, false>, launch_tile_t<lbm::PrecF64, 32, 16, 512, false>};
 constexpr TileFn kMom32[] = {launch_tile_t<lbm::PrecF32S, 64, 16, 256, true>, launch_tile_t<lbm::PrecF32S, 64, 16, 512, true>,
-                             launch_tile_t<lbm::PrecF32S, 128, 16, 512, true>, launch_tile_t<lbm::PrecF32S, 64, 32, 512, true>};
+                             launch_tile_t<lbm::PrecF32S, 128, 16, 512, true>, launch_tile_t<lbm::PrecF32S, 64, 32, 512, true>,
+                             launch_tile_t<lbm::PrecF32S, 32, 16, 512, true>};
 constexpr TileFn kMom64[] = {launch_tile_t<lbm::PrecF64, 64, 16, 512, true>, launch_tile_t<lbm::PrecF64, 64, 32, 512, true>,
-                             launch_tile_t<lbm::PrecF64, 64, 32, 1024, true>};
+                             launch_tile_t<lbm::PrecF64, 64, 32, 1024, true>, launch_tile_t<lbm::PrecF64, 32, 16, 512, true>};
 
 int tiles_of(const lbm_axi_params& p, const Config& c) {
     return ((p.nz + c.tz - 1) / c.tz) * ((p.nr + c.tr - 1) / c.tr);
@@ -248,7 +251,7 @@ int lbm_axi_batch_create(const lbm_axi_params* ps, int32_t n_inst, const double*
     HIP_TRY(hipGetDevice(&dev), "get device");
     if (hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || b->cus < 1)
         b->cus = 256;
-    b->cfg = b->precision == LBM_AXI_FP64 ? 2 : 3;  // the single-lattice choice until tuned
+    b->cfg = b->precision == LBM_AXI_FP64 ? 3 : 4;  // 32 x 16 tiles, as for a single small lattice, until tuned
     for (int k = 0; k < n_inst; ++k) {
         const long long n = (long long)ps[k].nz * ps[k].nr;
         const int blocks = (int)((n + 255) / 256);

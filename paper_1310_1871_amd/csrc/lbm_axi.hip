@@ -20,13 +20,20 @@ namespace {
 
 using namespace lbm_host;
 
-// tile shape and workgroup size of the fused kernel per precision (chosen
-// by timing on MI355X: 4096 x 512 thread workload)
-constexpr int kTZ64 = 64, kTR64 = 32, kNT64 = 1024;
-constexpr int kTZ32 = 64, kTR32 = 32, kNT32 = 512;
+// Tile shapes of the fused kernel (chosen by timing on MI355X).  Large
+// lattices use 64 x 32 tiles (1024 threads in FP64, 512 in FP32); lattices
+// with fewer than 4 such tiles per compute unit use 32 x 16 tiles (512
+// threads), which keep more compute units busy (256 x 128: 7.5 instead of
+// 15 us per FP64 step).
+struct Shape {
+    int tz, tr;
+};
+constexpr Shape kShape[2] = {{64, 32}, {32, 16}};  // [0] large, [1] small
+constexpr int kNT64 = 1024, kNT32 = 512, kNTSmall = 512;
 
-int tile_z(int precision) { return precision == LBM_AXI_FP64 ? kTZ64 : kTZ32; }
-int tile_r(int precision) { return precision == LBM_AXI_FP64 ? kTR64 : kTR32; }
+int tiles_of(const lbm_axi_params* p, int c) {
+    return ((p->nz + kShape[c].tz - 1) / kShape[c].tz) * ((p->nr + kShape[c].tr - 1) / kShape[c].tr);
+}
 
 struct Layout {
     size_t state_bytes;   // one population buffer
@@ -34,21 +41,36 @@ struct Layout {
     size_t off_partials;  // [max blocks][4] doubles
     size_t off_red;       // [4] doubles
     size_t total;
+    int cfg;              // tile shape in use
     int tiles_z, tiles_r, nblocks;
 };
 
-Layout layout_of(const lbm_axi_params* p) {
+// offsets do not depend on the tile shape (the partials are sized for the
+// shape with more tiles), so the workspace size is a function of p alone
+Layout layout_of(const lbm_axi_params* p, int cfg) {
     Layout L{};
     const size_t n = (size_t)p->nz * p->nr;
     L.state_bytes = 9 * n * storage_size(p->precision);
-    L.tiles_z = (p->nz + tile_z(p->precision) - 1) / tile_z(p->precision);
-    L.tiles_r = (p->nr + tile_r(p->precision) - 1) / tile_r(p->precision);
+    L.cfg = cfg;
+    L.tiles_z = (p->nz + kShape[cfg].tz - 1) / kShape[cfg].tz;
+    L.tiles_r = (p->nr + kShape[cfg].tr - 1) / kShape[cfg].tr;
     L.nblocks = L.tiles_z * L.tiles_r;
+    const int max_blocks = tiles_of(p, 1) > tiles_of(p, 0) ? tiles_of(p, 1) : tiles_of(p, 0);
     L.off_b = align_up(L.state_bytes);
     L.off_partials = L.off_b + align_up(L.state_bytes);
-    L.off_red = L.off_partials + align_up((size_t)L.nblocks * 4 * sizeof(double));
+    L.off_red = L.off_partials + align_up((size_t)max_blocks * 4 * sizeof(double));
     L.total = L.off_red + align_up(4 * sizeof(double));
     return L;
+}
+
+// large tiles when they give at least 4 workgroups per compute unit
+int pick_shape(const lbm_axi_params* p) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+    }
+    return tiles_of(p, 0) >= 4 * cus ? 0 : 1;
 }
 
 // fixed-order sum of the per-block partials into out[4]
@@ -91,7 +113,7 @@ lbm::StepArgs make_args(lbm_axi_ctx* h) {
     a.nz = h->p.nz;
     a.nr = h->p.nr;
     a.tiles_r = h->L.tiles_r;
-    a.big_nz = h->p.nz >= tile_z(h->p.precision) + 6 ? 1 : 0;
+    a.big_nz = h->p.nz >= kShape[h->L.cfg].tz + 6 ? 1 : 0;
     a.wall = h->p.wall;
     a.axisym = h->p.axisym;
     a.G = h->p.G;
@@ -105,12 +127,22 @@ lbm::StepArgs make_args(lbm_axi_ctx* h) {
 template <bool kMoments>
 int launch_tile(lbm_axi_ctx* h, const lbm::StepArgs& a) {
     const dim3 grid(h->L.nblocks);
-    if (h->p.precision == LBM_AXI_FP64)
-        hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, kTZ64, kTR64, kNT64, kMoments>), grid, dim3(kNT64), 0,
-                           h->stream, a);
-    else
-        hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, kTZ32, kTR32, kNT32, kMoments>), grid, dim3(kNT32), 0,
-                           h->stream, a);
+    const bool f64 = h->p.precision == LBM_AXI_FP64;
+    if (h->L.cfg == 0) {
+        if (f64)
+            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, 64, 32, kNT64, kMoments>), grid, dim3(kNT64), 0,
+                               h->stream, a);
+        else
+            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, 64, 32, kNT32, kMoments>), grid, dim3(kNT32), 0,
+                               h->stream, a);
+    } else {
+        if (f64)
+            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, 32, 16, kNTSmall, kMoments>), grid, dim3(kNTSmall),
+                               0, h->stream, a);
+        else
+            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, 32, 16, kNTSmall, kMoments>), grid,
+                               dim3(kNTSmall), 0, h->stream, a);
+    }
     HIP_TRY(hipGetLastError(), "step kernel launch");
     return LBM_AXI_OK;
 }
@@ -121,7 +153,7 @@ extern "C" {
 
 size_t lbm_axi_workspace_bytes(const lbm_axi_params* p) {
     if (check_params(p) != LBM_AXI_OK) return 0;
-    return layout_of(p).total;
+    return layout_of(p, 0).total;
 }
 
 int lbm_axi_create(const lbm_axi_params* p, const double* d_rho0, const double* d_uz0, const double* d_ur0,
@@ -133,7 +165,7 @@ int lbm_axi_create(const lbm_axi_params* p, const double* d_rho0, const double* 
     if (!d_rho0) return fail(LBM_AXI_EINVAL, "d_rho0 is NULL");
     if (!d_workspace) return fail(LBM_AXI_EINVAL, "workspace is NULL");
     if ((uintptr_t)d_workspace % kAlign != 0) return fail(LBM_AXI_EINVAL, "workspace must be 256-byte aligned");
-    const Layout L = layout_of(p);
+    const Layout L = layout_of(p, pick_shape(p));
     if (ws_bytes < L.total)
         return fail(LBM_AXI_ENOMEM, "workspace too small: %zu bytes, need %zu", ws_bytes, L.total);
     auto* h = new (std::nothrow) lbm_axi_ctx{};
@@ -222,6 +254,23 @@ int lbm_axi_set_state(lbm_axi_t h, const void* d_src) {
     if (!d_src) return fail(LBM_AXI_EINVAL, "d_src is NULL");
     HIP_TRY(hipMemcpyAsync(state_ptr(h, h->cur), d_src, h->L.state_bytes, hipMemcpyDeviceToDevice, h->stream),
             "set_state copy");
+    return LBM_AXI_OK;
+}
+
+int lbm_axi_record(lbm_axi_t h, int64_t n, void* d_states) {
+    if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
+    if (!d_states) return fail(LBM_AXI_EINVAL, "d_states is NULL");
+    if (n < 1) return fail(LBM_AXI_EINVAL, "n must be >= 1");
+    char* dst = static_cast<char*>(d_states);
+    for (int64_t j = 0; j < n; ++j) {
+        if (j > 0) {
+            int rc = lbm_axi_step(h, 1);
+            if (rc != LBM_AXI_OK) return rc;
+        }
+        HIP_TRY(hipMemcpyAsync(dst + (size_t)j * h->L.state_bytes, state_ptr(h, h->cur), h->L.state_bytes,
+                               hipMemcpyDeviceToDevice, h->stream),
+                "record copy");
+    }
     return LBM_AXI_OK;
 }
 

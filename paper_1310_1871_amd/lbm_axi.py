@@ -65,6 +65,7 @@ def _load():
         "lbm_axi_state_bytes": (ctypes.c_size_t, [vp]),
         "lbm_axi_get_state": (ctypes.c_int, [vp, vp]),
         "lbm_axi_set_state": (ctypes.c_int, [vp, vp]),
+        "lbm_axi_record": (ctypes.c_int, [vp, ctypes.c_int64, vp]),
         "lbm_axi_set_stream": (ctypes.c_int, [vp, vp]),
         "lbm_axi_set_coupling": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double]),
         "lbm_axi_destroy": (None, [vp]),
@@ -174,17 +175,32 @@ class AxiLBM:
     def state_bytes(self):
         return int(lib.lbm_axi_state_bytes(self._h))
 
-    def get_state(self):
+    def get_state(self, out=None):
+        """Copy of the populations (the library's storage type, [9][nr][nz]);
+        into ``out`` (a contiguous device tensor of state_bytes bytes) if
+        given."""
         self._sync_stream()
-        dst = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
-        check(lib.lbm_axi_get_state(self._h, _ptr(dst)))
-        return dst
+        if out is None:
+            out = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        elif out.numel() * out.element_size() != self.state_bytes() or not out.is_contiguous():
+            raise ValueError("state buffer of the wrong size or not contiguous")
+        check(lib.lbm_axi_get_state(self._h, _ptr(out)))
+        return out
 
     def set_state(self, src):
         if src.numel() * src.element_size() != self.state_bytes() or not src.is_contiguous():
             raise ValueError("state buffer of the wrong size or not contiguous")
         self._sync_stream()
         check(lib.lbm_axi_set_state(self._h, _ptr(src)))
+
+    def record(self, n, out):
+        """Write the states f^t .. f^{t+n-1} into ``out`` (a contiguous
+        device tensor of n * state_bytes bytes) and leave the lattice at
+        f^{t+n-1}."""
+        if n < 1 or out.numel() * out.element_size() != n * self.state_bytes() or not out.is_contiguous():
+            raise ValueError("record buffer of the wrong size or not contiguous")
+        self._sync_stream()
+        check(lib.lbm_axi_record(self._h, int(n), _ptr(out)))
 
     def populations(self):
         """Current populations as a float64 tensor [9, nr, nz] (the shift is

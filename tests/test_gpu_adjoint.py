@@ -275,6 +275,42 @@ def test_shape_loss_gradient_full_adjoint_workload():
     assert np.all(np.abs(g_gpu - fd) <= 1e-6 * np.abs(fd) + 1e-8 * np.abs(fd).max()), (g_gpu, fd)
 
 
+def test_record_and_adjoint_run_match_single_steps():
+    """lbm_axi_record writes the same states as stepping one by one, and
+    lbm_axi_adjoint_run over k recorded states equals k single adjoint
+    steps, bit for bit (same kernels, same order of the G/tau sums)."""
+    L, A = _libs()
+    nz, nr, G, tau, k = 48, 24, -5.5, 0.9, 7
+    _say("record / adjoint_run vs single steps")
+    f, rng = _state(3, nz, nr, G)
+    params = L.make_params(nz, nr, G=G, tau=tau)
+    rho = torch.from_numpy(f.sum(0)).cuda()
+    sim = L.AxiLBM(params, rho)
+    sim.set_state(torch.from_numpy(f).cuda().reshape(-1).view(torch.uint8))
+    rec = torch.empty((k, 9, nr, nz), dtype=torch.float64, device="cuda")
+    sim.record(k, rec)
+    sim.set_state(torch.from_numpy(f).cuda().reshape(-1).view(torch.uint8))
+    for j in range(k):
+        assert torch.equal(rec[j], sim.get_state().view(torch.float64).reshape(9, nr, nz)), j
+        sim.step(1)
+    sim.close()
+    dev = torch.device("cuda")
+    ws = torch.empty(A._lib.lbm_axi_adjoint_workspace_bytes(nz, nr) // 8, dtype=torch.float64, device=dev)
+    lam0 = torch.from_numpy(rng.standard_normal((9, nr, nz))).to(dev)
+    # single steps
+    acc1 = torch.zeros(2, dtype=torch.float64, device=dev)
+    cur, nxt = lam0.clone(), torch.empty_like(lam0)
+    for j in reversed(range(k)):
+        A.adjoint_step(params, rec[j], cur, nxt, acc1, ws)
+        cur, nxt = nxt, cur
+    # one run
+    acc2 = torch.zeros(2, dtype=torch.float64, device=dev)
+    lam = lam0.clone()
+    A.adjoint_run(params, rec[0], k, lam, torch.empty_like(lam), acc2, ws)
+    assert torch.equal(lam, cur)
+    assert torch.equal(acc1, acc2)
+
+
 def test_checkpointing_is_exact():
     """Recomputing segments from checkpoints reproduces the gradient of the
     no-recomputation run bit for bit (the step kernel is deterministic)."""
