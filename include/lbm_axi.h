@@ -44,6 +44,15 @@ extern "C" {
 #define LBM_AXI_FP64 0          /* populations stored and collided in FP64 */
 #define LBM_AXI_FP32_SHIFTED 1  /* FP32 storage of f_i - W_i rho_ref, FP32 collision */
 
+/* flags: force incorporation.  0 (default) is the Shan–Chen velocity shift
+ * of the paper's scheme (Sec. II.A, Eqs. ueq and uhydro).  LBM_AXI_FLAG_GUO
+ * selects the forcing of Guo, Zheng and Shi (Phys. Rev. E 65, 046308, 2002),
+ * the scheme the paper compares against in Sec. IV.A and Table I: f^eq at
+ * the hydrodynamic velocity u = (j + F/2)/rho plus, in the collision,
+ * (1 - 1/(2 tau)) W_i [3 (c_i - u) + 9 (c_i . u) c_i] . F.  Forces, sources
+ * and boundary rules are the same.  The adjoint supports the default only. */
+#define LBM_AXI_FLAG_GUO 4
+
 typedef struct lbm_axi_params {
     int32_t nz;        /* nodes along z (>= 1) */
     int32_t nr;        /* nodes along r (>= 6: reach of the derivative stencils) */
@@ -55,7 +64,7 @@ typedef struct lbm_axi_params {
     int32_t wall;      /* LBM_AXI_WALL_NOSLIP or LBM_AXI_WALL_FREESLIP */
     int32_t axisym;    /* 1: axisymmetric method; 0: plain planar Shan–Chen (test mode) */
     int32_t precision; /* LBM_AXI_FP64 or LBM_AXI_FP32_SHIFTED */
-    int32_t flags;     /* reserved, must be 0 */
+    int32_t flags;     /* 0 or LBM_AXI_FLAG_GUO; other bits are rejected (LBM_AXI_EUNSUP) */
     double rho_ref;    /* shift of the FP32 storage (ignored in FP64) */
 } lbm_axi_params;
 

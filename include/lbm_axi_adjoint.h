@@ -37,7 +37,7 @@ size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr);
  * lbm_axi_step's update), writes d_lam = (df'/df)^T d_lam_next and, if
  * d_grad_acc is not NULL, adds <d_lam_next, df'/dG> and
  * <d_lam_next, df'/dtau> to d_grad_acc[0] and d_grad_acc[1].  p must have
- * precision LBM_AXI_FP64 (LBM_AXI_EUNSUP otherwise).  d_lam must not alias
+ * precision LBM_AXI_FP64 and flags 0 (LBM_AXI_EUNSUP otherwise).  d_lam must not alias
  * d_lam_next or d_f.  d_ws: at least lbm_axi_adjoint_workspace_bytes. */
 int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const double* d_lam_next, double* d_lam,
                          double* d_grad_acc, void* d_ws, size_t ws_bytes, void* hip_stream);

@@ -45,10 +45,13 @@ class Params(ctypes.Structure):
     ]
 
 
+FLAG_GUO = 4  # Guo forcing instead of the velocity shift (see the C source)
+
+
 def make_params(nz, nr, G=-5.5, tau=1.0, psi_rho0=1.0, gz=0.0, wall=WALL_NOSLIP, axisym=1,
-                G_im=0.0, tau_im=0.0):
+                G_im=0.0, tau_im=0.0, flags=0):
     return Params(int(nz), int(nr), float(G), float(G_im), float(tau), float(tau_im),
-                  float(psi_rho0), float(gz), int(wall), int(axisym), 0, 0)
+                  float(psi_rho0), float(gz), int(wall), int(axisym), int(flags), 0)
 
 
 _lib = None

@@ -64,9 +64,19 @@ typedef struct {
     double gz;            /* body acceleration along +z */
     int32_t wall;         /* 0: no-slip (mid-grid bounce-back), 1: free-slip (mid-grid specular) */
     int32_t axisym;       /* 1: axisymmetric terms on, 0: plain 2D Shan–Chen */
-    int32_t flags;        /* reserved */
+    int32_t flags;        /* bit 2 (ORACLE_FLAG_GUO): Guo forcing instead of the velocity shift */
     int32_t pad;
 } or_params;
+
+/* Force incorporation.  Default: the Shan–Chen velocity shift the paper's
+ * scheme uses (Sec. II.A, Eqs. ueq and uhydro).  ORACLE_FLAG_GUO: the scheme
+ * of Guo, Zheng and Shi (Phys. Rev. E 65, 046308, 2002), which the paper
+ * compares against in Sec. IV.A and Table I: f^eq at the hydrodynamic
+ * velocity u = (j + F/2)/rho and a forcing term
+ *   (1 - 1/(2 tau)) W_i [ (c_i - u)/c_s^2 + (c_i . u) c_i / c_s^4 ] . F
+ * added in the collision.  The axisymmetric sources h_i and the forces are
+ * the same in both cases. */
+#define ORACLE_FLAG_GUO 4
 
 /* order of the intermediate fields written by *_fields() */
 enum {
@@ -295,10 +305,16 @@ static void compute_fields(const or_params* p, const num* f, workspace* w) {
             F[FLD_FR][x] = F[FLD_FSCR][x] + F[FLD_FSYMR][x];
 
             /* equilibrium velocity (Eq. ueq) and hydrodynamic velocity (Eq. uhydro) */
-            F[FLD_UEQZ][x] = (F[FLD_JZ][x] + tau * F[FLD_FZ][x]) / rho;
-            F[FLD_UEQR][x] = (F[FLD_JR][x] + tau * F[FLD_FR][x]) / rho;
             F[FLD_UZ][x] = (F[FLD_JZ][x] + 0.5 * F[FLD_FZ][x]) / rho;
             F[FLD_UR][x] = (F[FLD_JR][x] + 0.5 * F[FLD_FR][x]) / rho;
+            if (p->flags & ORACLE_FLAG_GUO) {
+                /* Guo forcing: the equilibrium is taken at the hydrodynamic velocity */
+                F[FLD_UEQZ][x] = F[FLD_UZ][x];
+                F[FLD_UEQR][x] = F[FLD_UR][x];
+            } else {
+                F[FLD_UEQZ][x] = (F[FLD_JZ][x] + tau * F[FLD_FZ][x]) / rho;
+                F[FLD_UEQR][x] = (F[FLD_JR][x] + tau * F[FLD_FR][x]) / rho;
+            }
         }
 
     /* velocity gradients for the viscous source terms.  Reading: the paper
@@ -337,12 +353,22 @@ static void compute_fields(const or_params* p, const num* f, workspace* w) {
              * its discretisation; the explicit node value is used. */
             num uqz = F[FLD_UEQZ][x], uqr = F[FLD_UEQR][x];
             num inv_tau = 1.0 / tau;
+            const int guo = (p->flags & ORACLE_FLAG_GUO) != 0;
+            num Fz = F[FLD_FZ][x], Fr = F[FLD_FR][x];
             for (int i = 0; i < 9; ++i) {
                 num hi = WT[i] * (mass + (CZ[i] * hz + CR[i] * hr) / CS2);
                 w->h[i * n + x] = hi;
                 num fi = f[i * n + x];
                 /* BGK collision plus source (Eq. lbm2d_mod_new) */
-                w->fstar[i * n + x] = fi - (fi - feq(i, rho, uqz, uqr)) * inv_tau + hi;
+                num fs = fi - (fi - feq(i, rho, uqz, uqr)) * inv_tau + hi;
+                if (guo) {
+                    /* forcing term of Guo et al., with u the hydrodynamic velocity */
+                    num cu = CZ[i] * uz + CR[i] * ur;
+                    num gz = (CZ[i] - uz) / CS2 + cu * CZ[i] / (CS2 * CS2);
+                    num gr = (CR[i] - ur) / CS2 + cu * CR[i] / (CS2 * CS2);
+                    fs += (1.0 - 0.5 * inv_tau) * WT[i] * (gz * Fz + gr * Fr);
+                }
+                w->fstar[i * n + x] = fs;
             }
         }
 }
@@ -383,6 +409,7 @@ static void stream(const or_params* p, const num* fstar, num* fout) {
 
 int API(check)(const or_params* p) {
     if (p->nz < 1 || p->nr < NG) return -1;
+    if (p->flags != 0 && p->flags != ORACLE_FLAG_GUO) return -1;
     return 0;
 }
 

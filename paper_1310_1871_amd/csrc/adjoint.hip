@@ -610,7 +610,7 @@ int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const doubl
     if (!p || !d_f || !d_lam_next || !d_lam || !d_ws) return LBM_AXI_EINVAL;
     if (p->nz < 1 || p->nr < 6 || !(p->tau > 0.5) || !(p->psi_rho0 > 0.0)) return LBM_AXI_EINVAL;
     if (p->wall != 0 && p->wall != 1) return LBM_AXI_EINVAL;
-    if (p->precision != LBM_AXI_FP64) return LBM_AXI_EUNSUP;
+    if (p->precision != LBM_AXI_FP64 || p->flags != 0) return LBM_AXI_EUNSUP;
     if (ws_bytes < lbm_axi_adjoint_workspace_bytes(p->nz, p->nr)) return LBM_AXI_ENOMEM;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     AdjArgs a{};

@@ -133,6 +133,7 @@ lbm::StepArgs instance_args(lbm_axi_batch* b, int k, int parity) {
     a.big_nz = p.nz >= c.tz + 6 ? 1 : 0;
     a.wall = p.wall;
     a.axisym = p.axisym;
+    a.guo = (p.flags & LBM_AXI_FLAG_GUO) ? 1 : 0;
     a.G = p.G;
     a.tau = p.tau;
     a.rho0 = p.psi_rho0;

@@ -116,6 +116,7 @@ lbm::StepArgs make_args(lbm_axi_ctx* h) {
     a.big_nz = h->p.nz >= kShape[h->L.cfg].tz + 6 ? 1 : 0;
     a.wall = h->p.wall;
     a.axisym = h->p.axisym;
+    a.guo = (h->p.flags & LBM_AXI_FLAG_GUO) ? 1 : 0;
     a.G = h->p.G;
     a.tau = h->p.tau;
     a.rho0 = h->p.psi_rho0;

@@ -43,6 +43,7 @@ struct StepArgs {
     int big_nz;        // 1 if nz >= TZ + 6: periodic wrap needs one add/sub
     int wall;          // 0 no-slip, 1 free-slip
     int axisym;        // 1 axisymmetric terms on
+    int guo;           // 1: Guo forcing instead of the velocity shift
     double G, tau, rho0, gz, rho_ref;
 };
 
@@ -419,9 +420,14 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
                 mass = -rho * ur * inv_r;
             }
             const C inv_rho = dev_rcp(rho);
-            const C qz = (jz + tau * Fz) * inv_rho;
-            const C qr = (jr + tau * Fr) * inv_rho;
+            const bool guo = a.guo != 0;
+            // equilibrium velocity: shifted by tau F (Eq. ueq), or the
+            // hydrodynamic velocity with Guo forcing
+            const C qz = guo ? uz : (jz + tau * Fz) * inv_rho;
+            const C qr = guo ? ur : (jr + tau * Fr) * inv_rho;
             const C qq = C(1.5) * (qz * qz + qr * qr);
+            const C gpre = C(1) - C(0.5) * inv_tau;  // Guo: (1 - 1/(2 tau))
+            const C uF = uz * Fz + ur * Fr;
             const __amdgpu_buffer_rsrc_t fout = pop_rsrc(a.fout, a.state_bytes);
             // FP32 weights sum to 1 + 7.45e-9, which would bias the mass of
             // f^eq (and of h) by that fraction at every collision; in FP32 the
@@ -436,6 +442,8 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
                 const C w = C(weight(i));
                 C feq, hi;
                 if (kRem && i == 0) {
+                    // the Guo term carries no mass either: its rest part is
+                    // minus the sum of the others
                     feq = sig - feq_acc;
                     hi = mass - h_acc;
                 } else {
@@ -445,6 +453,12 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
                     // throughout); in shifted storage, f^eq - W rho_ref
                     feq = P::kShift ? w * (sig + rho * poly) : w * rho * (C(1) + poly);
                     hi = w * (mass + C(3) * (C(cz(i)) * hz + C(cr(i)) * hr));
+                    if (guo) {
+                        // Guo et al.: W_i [3 (c_i - u) + 9 (c_i . u) c_i] . F
+                        const C cF = C(cz(i)) * Fz + C(cr(i)) * Fr;
+                        const C cuu = C(cz(i)) * uz + C(cr(i)) * ur;
+                        hi += gpre * w * (C(3) * (cF - uF) + C(9) * cuu * cF);
+                    }
                     feq_acc += feq;
                     h_acc += hi;
                 }

@@ -24,6 +24,7 @@ WALL_NOSLIP = 0
 WALL_FREESLIP = 1
 FP64 = 0
 FP32_SHIFTED = 1
+FLAG_GUO = 4  # Guo forcing instead of the velocity shift (include/lbm_axi.h)
 NREDUCE = 4
 
 

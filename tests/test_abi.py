@@ -34,11 +34,13 @@ def test_parameter_validation():
     good = L.make_params(64, 32)
     assert L.workspace_bytes(good) > 2 * 9 * 64 * 32 * 8
     for field, value, msg in [("nz", 0, "nz"), ("nr", 5, "nr"), ("tau", 0.5, "tau"), ("wall", 2, "wall"),
-                              ("axisym", 3, "axisym"), ("precision", 7, "precision"), ("psi_rho0", 0.0, "psi_rho0")]:
+                              ("axisym", 3, "axisym"), ("precision", 7, "precision"), ("psi_rho0", 0.0, "psi_rho0"),
+                              ("flags", 1, "flags"), ("flags", 8, "flags")]:
         p = L.make_params(64, 32)
         setattr(p, field, value)
         assert L.workspace_bytes(p) == 0
         assert msg in L.last_error()
+    assert L.workspace_bytes(L.make_params(64, 32, flags=L.FLAG_GUO)) == L.workspace_bytes(good)
 
 
 def test_fp32_workspace_is_half():

@@ -25,16 +25,16 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def _compare(nz, nr, rho, steps, G=-5.5, tau=1.0, wall=0, axisym=1, gz=0.0, uz=None, ur=None, tol=TOL):
+def _compare(nz, nr, rho, steps, G=-5.5, tau=1.0, wall=0, axisym=1, gz=0.0, uz=None, ur=None, tol=TOL, flags=0):
     L = _lib()
-    _say(f"parity case nz={nz} nr={nr} steps={steps} G={G} tau={tau} wall={wall} axisym={axisym}")
+    _say(f"parity case nz={nz} nr={nr} steps={steps} G={G} tau={tau} wall={wall} axisym={axisym} flags={flags}")
     uz = np.zeros_like(rho) if uz is None else uz
     ur = np.zeros_like(rho) if ur is None else ur
-    sim = L.AxiLBM(L.make_params(nz, nr, G=G, tau=tau, wall=wall, axisym=axisym, gz=gz),
+    sim = L.AxiLBM(L.make_params(nz, nr, G=G, tau=tau, wall=wall, axisym=axisym, gz=gz, flags=flags),
                    torch.from_numpy(rho).cuda(), torch.from_numpy(uz).cuda(), torch.from_numpy(ur).cuda())
     sim.step(steps)
     rg, uzg, urg = (t.cpu().numpy() for t in sim.moments())
-    p = O.make_params(nz, nr, G=G, tau=tau, wall=wall, axisym=axisym, gz=gz)
+    p = O.make_params(nz, nr, G=G, tau=tau, wall=wall, axisym=axisym, gz=gz, flags=flags)
     f = O.run(p, O.equilibrium(p, rho, uz, ur), steps)
     ro, uzo, uro = O.moments(p, f)
     assert np.isfinite(ro).all()
@@ -50,6 +50,21 @@ def test_static_drop_1000_steps(wall, axisym):
     """Static drop 64 x 32 (R = 10, rho 2.0/0.15, G = -5.5, tau = 1)."""
     c = static_drop()
     _compare(c.nz, c.nr, c.rho, 1000, G=c.G, tau=c.tau, wall=wall, axisym=axisym)
+
+
+@pytest.mark.parametrize("wall", [0, 1])
+def test_guo_forcing_static_drop_1000_steps(wall):
+    """The Guo forcing option (the scheme the paper compares against in
+    Sec. IV.A) on the static drop, both walls, against the oracle's."""
+    c = static_drop()
+    _compare(c.nz, c.nr, c.rho, 1000, G=c.G, tau=c.tau, wall=wall, flags=4)
+
+
+def test_guo_forcing_ragged_and_body_force():
+    """Guo forcing on a ragged grid with random fields and a body force."""
+    nz, nr = 100, 37
+    rho, uz, ur = random_state_fields(7337, nz, nr, rho_lo=0.5, rho_hi=1.5, u_amp=0.01)
+    _compare(nz, nr, rho, 200, G=-4.0, tau=0.8, wall=0, gz=1e-5, uz=uz, ur=ur, flags=4)
 
 
 def test_oscillating_drop_shape_1000_steps():
@@ -82,6 +97,18 @@ def test_full_size_thread_fields():
     rg, rl = coexistence_densities(G)
     rho = thread_density(4096, 512, 64.0, rl, rg, 2.0, 0.1, 1)
     _compare(4096, 512, rho, 3, G=G, tau=0.8, wall=1)
+
+
+@pytest.mark.parametrize("wall", [0, 1])
+def test_large_tile_shape_ragged(wall):
+    """A lattice large enough for the 64 x 32 tiles (1105 of them) but not a
+    multiple of them: 4100 x 515 leaves a last tile column 4 wide and a last
+    tile row with 3 real rows, so the ghost rows beyond the wall fill most
+    of its velocity window.  Both wall rules, random smooth fields, 6 steps
+    against the oracle."""
+    nz, nr = 4100, 515
+    rho, uz, ur = random_state_fields(4100515 + wall, nz, nr, rho_lo=0.3, rho_hi=2.0, u_amp=0.01)
+    _compare(nz, nr, rho, 6, G=-5.0, tau=0.9, wall=wall, uz=uz, ur=ur)
 
 
 def test_reduce_and_moments_match_oracle_diagnostics():
