@@ -26,33 +26,33 @@ constexpr Config kCfg32[] = {{64, 16, 256}, {64, 16, 512}, {128, 16, 512}, {64, 
 constexpr Config kCfg64[] = {{64, 16, 512}, {64, 32, 512}, {64, 32, 1024}, {32, 16, 512}};
 constexpr int kNCfg32 = 5, kNCfg64 = 4;
 
-template <class P, int TZ, int TR, int NT>
+template <class P, int TZ, int TR, int NT, int kForce>
 void launch_batch_t(dim3 grid, hipStream_t s, const lbm::BatchInstance* insts, const int2* items, int n, int parity) {
-    hipLaunchKernelGGL((lbm::axi_batch_kernel<P, TZ, TR, NT>), grid, dim3(NT), 0, s, insts, items, n, parity);
+    hipLaunchKernelGGL((lbm::axi_batch_kernel<P, TZ, TR, NT, kForce>), grid, dim3(NT), 0, s, insts, items, n, parity);
 }
-template <class P, int TZ, int TR, int NT, bool kMoments>
+template <class P, int TZ, int TR, int NT, bool kMoments, int kForce>
 void launch_tile_t(dim3 grid, hipStream_t s, const lbm::StepArgs& a) {
-    hipLaunchKernelGGL((lbm::axi_tile_kernel<P, TZ, TR, NT, kMoments>), grid, dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((lbm::axi_tile_kernel<P, TZ, TR, NT, kMoments, kForce>), grid, dim3(NT), 0, s, a);
 }
 
 using BatchFn = void (*)(dim3, hipStream_t, const lbm::BatchInstance*, const int2*, int, int);
 using TileFn = void (*)(dim3, hipStream_t, const lbm::StepArgs&);
 
-constexpr BatchFn kBatch32[] = {launch_batch_t<lbm::PrecF32S, 64, 16, 256>, launch_batch_t<lbm::PrecF32S, 64, 16, 512>,
-                                launch_batch_t<lbm::PrecF32S, 128, 16, 512>, launch_batch_t<lbm::PrecF32S, 64, 32, 512>,
-                                launch_batch_t<lbm::PrecF32S, 32, 16, 512>};
-constexpr BatchFn kBatch64[] = {launch_batch_t<lbm::PrecF64, 64, 16, 512>, launch_batch_t<lbm::PrecF64, 64, 32, 512>,
-                                launch_batch_t<lbm::PrecF64, 64, 32, 1024>, launch_batch_t<lbm::PrecF64, 32, 16, 512>};
-constexpr TileFn kStep32[] = {launch_tile_t<lbm::PrecF32S, 64, 16, 256, false>, launch_tile_t<lbm::PrecF32S, 64, 16, 512, false>,
-                              launch_tile_t<lbm::PrecF32S, 128, 16, 512, false>, launch_tile_t<lbm::PrecF32S, 64, 32, 512, false>,
-                              launch_tile_t<lbm::PrecF32S, 32, 16, 512, false>};
-constexpr TileFn kStep64[] = {launch_tile_t<lbm::PrecF64, 64, 16, 512, false>, launch_tile_t<lbm::PrecF64, 64, 32, 512, false>,
-                              launch_tile_t<lbm::PrecF64, 64, 32, 1024, false>, launch_tile_t<lbm::PrecF64, 32, 16, 512, false>};
-constexpr TileFn kMom32[] = {launch_tile_t<lbm::PrecF32S, 64, 16, 256, true>, launch_tile_t<lbm::PrecF32S, 64, 16, 512, true>,
-                             launch_tile_t<lbm::PrecF32S, 128, 16, 512, true>, launch_tile_t<lbm::PrecF32S, 64, 32, 512, true>,
-                             launch_tile_t<lbm::PrecF32S, 32, 16, 512, true>};
-constexpr TileFn kMom64[] = {launch_tile_t<lbm::PrecF64, 64, 16, 512, true>, launch_tile_t<lbm::PrecF64, 64, 32, 512, true>,
-                             launch_tile_t<lbm::PrecF64, 64, 32, 1024, true>, launch_tile_t<lbm::PrecF64, 32, 16, 512, true>};
+// [f] = forcing: 0 velocity shift everywhere, 1 per-instance choice at run
+// time (some instance uses the Guo option)
+#define LBM_CFG32(F, ...) {F<lbm::PrecF32S, 64, 16, 256, __VA_ARGS__>, F<lbm::PrecF32S, 64, 16, 512, __VA_ARGS__>, \
+                           F<lbm::PrecF32S, 128, 16, 512, __VA_ARGS__>, F<lbm::PrecF32S, 64, 32, 512, __VA_ARGS__>, \
+                           F<lbm::PrecF32S, 32, 16, 512, __VA_ARGS__>}
+#define LBM_CFG64(F, ...) {F<lbm::PrecF64, 64, 16, 512, __VA_ARGS__>, F<lbm::PrecF64, 64, 32, 512, __VA_ARGS__>, \
+                           F<lbm::PrecF64, 64, 32, 1024, __VA_ARGS__>, F<lbm::PrecF64, 32, 16, 512, __VA_ARGS__>}
+constexpr BatchFn kBatch32[2][kNCfg32] = {LBM_CFG32(launch_batch_t, 0), LBM_CFG32(launch_batch_t, 2)};
+constexpr BatchFn kBatch64[2][kNCfg64] = {LBM_CFG64(launch_batch_t, 0), LBM_CFG64(launch_batch_t, 2)};
+constexpr TileFn kStep32[2][kNCfg32] = {LBM_CFG32(launch_tile_t, false, 0), LBM_CFG32(launch_tile_t, false, 2)};
+constexpr TileFn kStep64[2][kNCfg64] = {LBM_CFG64(launch_tile_t, false, 0), LBM_CFG64(launch_tile_t, false, 2)};
+constexpr TileFn kMom32[kNCfg32] = LBM_CFG32(launch_tile_t, true, 0);
+constexpr TileFn kMom64[kNCfg64] = LBM_CFG64(launch_tile_t, true, 0);
+#undef LBM_CFG32
+#undef LBM_CFG64
 
 int tiles_of(const lbm_axi_params& p, const Config& c) {
     return ((p.nz + c.tz - 1) / c.tz) * ((p.nr + c.tr - 1) / c.tr);
@@ -70,6 +70,7 @@ struct lbm_axi_batch {
     int precision = 0;
     int parity = 0;
     int cfg = 0, grid_per_cu = 2, order = 1;
+    int any_guo = 0;  // 1 if some instance uses the Guo forcing option
     int n_items = 0, cus = 256;
     std::vector<lbm::BatchInstance> host_tab;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -191,7 +192,7 @@ int grid_size(lbm_axi_batch* b) {
 }
 
 int launch_once(lbm_axi_batch* b, hipStream_t s, int parity) {
-    const BatchFn fn = b->precision == LBM_AXI_FP64 ? kBatch64[b->cfg] : kBatch32[b->cfg];
+    const BatchFn fn = b->precision == LBM_AXI_FP64 ? kBatch64[b->any_guo][b->cfg] : kBatch32[b->any_guo][b->cfg];
     fn(dim3(grid_size(b)), s, reinterpret_cast<const lbm::BatchInstance*>(b->ws + b->off_tab),
        reinterpret_cast<const int2*>(b->ws + b->off_items), b->n_items, parity);
     HIP_TRY(hipGetLastError(), "batch kernel launch");
@@ -248,6 +249,8 @@ int lbm_axi_batch_create(const lbm_axi_params* ps, int32_t n_inst, const double*
     b->ws = static_cast<char*>(d_workspace);
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->precision = ps[0].precision;
+    for (int k = 0; k < n_inst; ++k)
+        if (ps[k].flags & LBM_AXI_FLAG_GUO) b->any_guo = 1;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev), "get device");
     if (hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || b->cus < 1)
@@ -298,7 +301,7 @@ int lbm_axi_batch_step(lbm_axi_batch_t b, int64_t n) {
 int lbm_axi_batch_step_per_instance(lbm_axi_batch_t b, int64_t n) {
     if (!b) return fail(LBM_AXI_EINVAL, "batch is NULL");
     if (n < 0) return fail(LBM_AXI_EINVAL, "n must be >= 0");
-    const TileFn fn = b->precision == LBM_AXI_FP64 ? kStep64[b->cfg] : kStep32[b->cfg];
+    const TileFn fn = b->precision == LBM_AXI_FP64 ? kStep64[b->any_guo][b->cfg] : kStep32[b->any_guo][b->cfg];
     for (int64_t s = 0; s < n; ++s) {
         for (size_t k = 0; k < b->p.size(); ++k)
             fn(dim3(tiles_of(b->p[k], b->config())), b->stream, b->host_tab[k].args[b->parity]);

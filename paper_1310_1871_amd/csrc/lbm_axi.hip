@@ -125,25 +125,35 @@ lbm::StepArgs make_args(lbm_axi_ctx* h) {
     return a;
 }
 
-template <bool kMoments>
-int launch_tile(lbm_axi_ctx* h, const lbm::StepArgs& a) {
+template <bool kMoments, int kForce>
+void launch_shape(lbm_axi_ctx* h, const lbm::StepArgs& a) {
     const dim3 grid(h->L.nblocks);
     const bool f64 = h->p.precision == LBM_AXI_FP64;
     if (h->L.cfg == 0) {
         if (f64)
-            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, 64, 32, kNT64, kMoments>), grid, dim3(kNT64), 0,
-                               h->stream, a);
-        else
-            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, 64, 32, kNT32, kMoments>), grid, dim3(kNT32), 0,
-                               h->stream, a);
-    } else {
-        if (f64)
-            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, 32, 16, kNTSmall, kMoments>), grid, dim3(kNTSmall),
+            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, 64, 32, kNT64, kMoments, kForce>), grid, dim3(kNT64),
                                0, h->stream, a);
         else
-            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, 32, 16, kNTSmall, kMoments>), grid,
+            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, 64, 32, kNT32, kMoments, kForce>), grid,
+                               dim3(kNT32), 0, h->stream, a);
+    } else {
+        if (f64)
+            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, 32, 16, kNTSmall, kMoments, kForce>), grid,
+                               dim3(kNTSmall), 0, h->stream, a);
+        else
+            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, 32, 16, kNTSmall, kMoments, kForce>), grid,
                                dim3(kNTSmall), 0, h->stream, a);
     }
+}
+
+// the forcing option is a compile-time choice of the kernel (the moments do
+// not depend on it)
+template <bool kMoments>
+int launch_tile(lbm_axi_ctx* h, const lbm::StepArgs& a) {
+    if (!kMoments && (h->p.flags & LBM_AXI_FLAG_GUO))
+        launch_shape<kMoments, 1>(h, a);
+    else
+        launch_shape<kMoments, 0>(h, a);
     HIP_TRY(hipGetLastError(), "step kernel launch");
     return LBM_AXI_OK;
 }

@@ -141,8 +141,9 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
 
 // One TZ x TR tile of one lattice: the whole step (or the moments) for the
 // tile's nodes.  `tile` = tz * tiles_r + tr; `slot` indexes the per-block
-// partial sums of the moments mode.
-template <class P, int TZ, int TR, int NT, bool kMoments>
+// partial sums of the moments mode.  kForce: 0 velocity-shift forcing, 1 Guo
+// forcing, 2 chosen at run time by StepArgs::guo (instances of a batch).
+template <class P, int TZ, int TR, int NT, bool kMoments, int kForce = 0>
 __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, const int slot) {
     using S = typename P::S;
     using C = typename P::C;
@@ -420,7 +421,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
                 mass = -rho * ur * inv_r;
             }
             const C inv_rho = dev_rcp(rho);
-            const bool guo = a.guo != 0;
+            const bool guo = kForce == 2 ? a.guo != 0 : kForce == 1;
             // equilibrium velocity: shifted by tau F (Eq. ueq), or the
             // hydrodynamic velocity with Guo forcing
             const C qz = guo ? uz : (jz + tau * Fz) * inv_rho;
@@ -505,9 +506,9 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     }
 }
 
-template <class P, int TZ, int TR, int NT, bool kMoments>
+template <class P, int TZ, int TR, int NT, bool kMoments, int kForce = 0>
 __global__ __launch_bounds__(NT) void axi_tile_kernel(const StepArgs a) {
-    tile_body<P, TZ, TR, NT, kMoments>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x);
+    tile_body<P, TZ, TR, NT, kMoments, kForce>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x);
 }
 
 // Batched ensemble: many independent lattices (each with its own size,
@@ -519,7 +520,7 @@ struct BatchInstance {
     StepArgs args[2];  // [parity]: fin/fout swapped
 };
 
-template <class P, int TZ, int TR, int NT>
+template <class P, int TZ, int TR, int NT, int kForce = 0>
 __global__ __launch_bounds__(NT) void axi_batch_kernel(const BatchInstance* __restrict__ insts,
                                                       const int2* __restrict__ items, int n_items, int parity) {
     for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
@@ -529,7 +530,7 @@ __global__ __launch_bounds__(NT) void axi_batch_kernel(const BatchInstance* __re
         const int inst = __builtin_amdgcn_readfirstlane(w.x);
         const int tile = __builtin_amdgcn_readfirstlane(w.y);
         const StepArgs a = insts[inst].args[parity];
-        tile_body<P, TZ, TR, NT, false>(a, tile, 0);
+        tile_body<P, TZ, TR, NT, false, kForce>(a, tile, 0);
         __syncthreads();  // the next item reuses the LDS windows
     }
 }
