@@ -52,6 +52,14 @@ extern "C" {
  * (1 - 1/(2 tau)) W_i [3 (c_i - u) + 9 (c_i . u) c_i] . F.  Forces, sources
  * and boundary rules are the same.  The adjoint supports the default only. */
 #define LBM_AXI_FLAG_GUO 4
+/* flags: LBM_AXI_FLAG_NO_WALL_DERIV selects the other reading of the
+ * derivative rule at the outer wall (Sec. II.E only states that derivative
+ * terms vanish at the non-axis boundaries, not how).  Default: every field is reflected evenly across the wall and the
+ * stencils run unchanged.  With this flag: F^{gamma,sym} is zero on the 4
+ * rows next to the wall (its stencils reach 4 rows) and the velocity
+ * derivatives in H_z, H_r are zero on the 2 rows next to the wall; the
+ * other terms are unchanged.  May be combined with LBM_AXI_FLAG_GUO. */
+#define LBM_AXI_FLAG_NO_WALL_DERIV 2
 
 typedef struct lbm_axi_params {
     int32_t nz;        /* nodes along z (>= 1) */
@@ -64,7 +72,7 @@ typedef struct lbm_axi_params {
     int32_t wall;      /* LBM_AXI_WALL_NOSLIP or LBM_AXI_WALL_FREESLIP */
     int32_t axisym;    /* 1: axisymmetric method; 0: plain planar Shan–Chen (test mode) */
     int32_t precision; /* LBM_AXI_FP64 or LBM_AXI_FP32_SHIFTED */
-    int32_t flags;     /* 0 or LBM_AXI_FLAG_GUO; other bits are rejected (LBM_AXI_EUNSUP) */
+    int32_t flags;     /* LBM_AXI_FLAG_GUO | LBM_AXI_FLAG_NO_WALL_DERIV; other bits: LBM_AXI_EUNSUP */
     double rho_ref;    /* shift of the FP32 storage (ignored in FP64) */
 } lbm_axi_params;
 

@@ -64,7 +64,7 @@ typedef struct {
     double gz;            /* body acceleration along +z */
     int32_t wall;         /* 0: no-slip (mid-grid bounce-back), 1: free-slip (mid-grid specular) */
     int32_t axisym;       /* 1: axisymmetric terms on, 0: plain 2D Shan–Chen */
-    int32_t flags;        /* bit 2 (ORACLE_FLAG_GUO): Guo forcing instead of the velocity shift */
+    int32_t flags;        /* ORACLE_FLAG_GUO and/or ORACLE_FLAG_NO_WALL_DERIV (see below) */
     int32_t pad;
 } or_params;
 
@@ -77,6 +77,14 @@ typedef struct {
  * added in the collision.  The axisymmetric sources h_i and the forces are
  * the same in both cases. */
 #define ORACLE_FLAG_GUO 4
+
+/* Derivative terms at the outer wall.  Sec. II.E states only that they vanish
+ * at the non-axis boundaries.  Default reading: every field is reflected
+ * evenly across the wall and the stencils run unchanged.
+ * ORACLE_FLAG_NO_WALL_DERIV: the other reading -- F^{gamma,sym} is zero on
+ * rows whose stencils reach across the wall (the 4 rows next to it) and the
+ * velocity derivatives of H are zero on the 2 rows next to it. */
+#define ORACLE_FLAG_NO_WALL_DERIV 2
 
 /* order of the intermediate fields written by *_fields() */
 enum {
@@ -290,7 +298,8 @@ static void compute_fields(const or_params* p, const num* f, workspace* w) {
             /* axisymmetric extra force (Sec. II.D, Eq. scAxisExtra), c_s^4 = 1/9 */
             double rr = r + 0.5;
             num pref = -(G / 2.0) * (CS2 * CS2) * psi;
-            if (p->axisym) {
+            const int flat = (p->flags & ORACLE_FLAG_NO_WALL_DERIV) && r >= nr - 4;
+            if (p->axisym && !flat) {
                 F[FLD_FSYMZ][x] = pref * F[FLD_DZR][x] / rr;
                 F[FLD_FSYMR][x] = pref * (F[FLD_DRR][x] / rr - F[FLD_DR][x] / (rr * rr));
             } else {
@@ -328,9 +337,15 @@ static void compute_fields(const or_params* p, const num* f, workspace* w) {
     for (int r = 0; r < nr; ++r)
         for (int z = 0; z < nz; ++z) {
             size_t x = (size_t)r * nz + z;
-            F[FLD_DRUZ][x] = d_iso(w->uzE, nz, z, r, 1);
-            F[FLD_DZUR][x] = d_iso(w->urE, nz, z, r, 0);
-            F[FLD_DRUR][x] = d_iso(w->urE, nz, z, r, 1);
+            if ((p->flags & ORACLE_FLAG_NO_WALL_DERIV) && r >= nr - 2) {
+                F[FLD_DRUZ][x] = 0.0;
+                F[FLD_DZUR][x] = 0.0;
+                F[FLD_DRUR][x] = 0.0;
+            } else {
+                F[FLD_DRUZ][x] = d_iso(w->uzE, nz, z, r, 1);
+                F[FLD_DZUR][x] = d_iso(w->urE, nz, z, r, 0);
+                F[FLD_DRUR][x] = d_iso(w->urE, nz, z, r, 1);
+            }
 
             num rho = F[FLD_RHO][x], uz = F[FLD_UZ][x], ur = F[FLD_UR][x];
             double rr = r + 0.5;
@@ -409,7 +424,7 @@ static void stream(const or_params* p, const num* fstar, num* fout) {
 
 int API(check)(const or_params* p) {
     if (p->nz < 1 || p->nr < NG) return -1;
-    if (p->flags != 0 && p->flags != ORACLE_FLAG_GUO) return -1;
+    if ((p->flags & ~(ORACLE_FLAG_GUO | ORACLE_FLAG_NO_WALL_DERIV)) != 0) return -1;
     return 0;
 }
 

@@ -26,31 +26,31 @@ constexpr Config kCfg32[] = {{64, 16, 256}, {64, 16, 512}, {128, 16, 512}, {64, 
 constexpr Config kCfg64[] = {{64, 16, 512}, {64, 32, 512}, {64, 32, 1024}, {32, 16, 512}};
 constexpr int kNCfg32 = 5, kNCfg64 = 4;
 
-template <class P, int TZ, int TR, int NT, int kForce>
+template <class P, int TZ, int TR, int NT, int kOpt>
 void launch_batch_t(dim3 grid, hipStream_t s, const lbm::BatchInstance* insts, const int2* items, int n, int parity) {
-    hipLaunchKernelGGL((lbm::axi_batch_kernel<P, TZ, TR, NT, kForce>), grid, dim3(NT), 0, s, insts, items, n, parity);
+    hipLaunchKernelGGL((lbm::axi_batch_kernel<P, TZ, TR, NT, kOpt>), grid, dim3(NT), 0, s, insts, items, n, parity);
 }
-template <class P, int TZ, int TR, int NT, bool kMoments, int kForce>
+template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt>
 void launch_tile_t(dim3 grid, hipStream_t s, const lbm::StepArgs& a) {
-    hipLaunchKernelGGL((lbm::axi_tile_kernel<P, TZ, TR, NT, kMoments, kForce>), grid, dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((lbm::axi_tile_kernel<P, TZ, TR, NT, kMoments, kOpt>), grid, dim3(NT), 0, s, a);
 }
 
 using BatchFn = void (*)(dim3, hipStream_t, const lbm::BatchInstance*, const int2*, int, int);
 using TileFn = void (*)(dim3, hipStream_t, const lbm::StepArgs&);
 
-// [f] = forcing: 0 velocity shift everywhere, 1 per-instance choice at run
-// time (some instance uses the Guo option)
+// [o]: 0 every instance with the default options; 1 some instance sets an
+// option bit, which the kernels then read per instance at run time
 #define LBM_CFG32(F, ...) {F<lbm::PrecF32S, 64, 16, 256, __VA_ARGS__>, F<lbm::PrecF32S, 64, 16, 512, __VA_ARGS__>, \
                            F<lbm::PrecF32S, 128, 16, 512, __VA_ARGS__>, F<lbm::PrecF32S, 64, 32, 512, __VA_ARGS__>, \
                            F<lbm::PrecF32S, 32, 16, 512, __VA_ARGS__>}
 #define LBM_CFG64(F, ...) {F<lbm::PrecF64, 64, 16, 512, __VA_ARGS__>, F<lbm::PrecF64, 64, 32, 512, __VA_ARGS__>, \
                            F<lbm::PrecF64, 64, 32, 1024, __VA_ARGS__>, F<lbm::PrecF64, 32, 16, 512, __VA_ARGS__>}
-constexpr BatchFn kBatch32[2][kNCfg32] = {LBM_CFG32(launch_batch_t, 0), LBM_CFG32(launch_batch_t, 2)};
-constexpr BatchFn kBatch64[2][kNCfg64] = {LBM_CFG64(launch_batch_t, 0), LBM_CFG64(launch_batch_t, 2)};
-constexpr TileFn kStep32[2][kNCfg32] = {LBM_CFG32(launch_tile_t, false, 0), LBM_CFG32(launch_tile_t, false, 2)};
-constexpr TileFn kStep64[2][kNCfg64] = {LBM_CFG64(launch_tile_t, false, 0), LBM_CFG64(launch_tile_t, false, 2)};
-constexpr TileFn kMom32[kNCfg32] = LBM_CFG32(launch_tile_t, true, 0);
-constexpr TileFn kMom64[kNCfg64] = LBM_CFG64(launch_tile_t, true, 0);
+constexpr BatchFn kBatch32[2][kNCfg32] = {LBM_CFG32(launch_batch_t, 0), LBM_CFG32(launch_batch_t, -1)};
+constexpr BatchFn kBatch64[2][kNCfg64] = {LBM_CFG64(launch_batch_t, 0), LBM_CFG64(launch_batch_t, -1)};
+constexpr TileFn kStep32[2][kNCfg32] = {LBM_CFG32(launch_tile_t, false, 0), LBM_CFG32(launch_tile_t, false, -1)};
+constexpr TileFn kStep64[2][kNCfg64] = {LBM_CFG64(launch_tile_t, false, 0), LBM_CFG64(launch_tile_t, false, -1)};
+constexpr TileFn kMom32[2][kNCfg32] = {LBM_CFG32(launch_tile_t, true, 0), LBM_CFG32(launch_tile_t, true, -1)};
+constexpr TileFn kMom64[2][kNCfg64] = {LBM_CFG64(launch_tile_t, true, 0), LBM_CFG64(launch_tile_t, true, -1)};
 #undef LBM_CFG32
 #undef LBM_CFG64
 
@@ -70,7 +70,7 @@ struct lbm_axi_batch {
     int precision = 0;
     int parity = 0;
     int cfg = 0, grid_per_cu = 2, order = 1;
-    int any_guo = 0;  // 1 if some instance uses the Guo forcing option
+    int any_guo = 0;  // 1 if some instance sets an option bit (Guo forcing, wall derivatives)
     int n_items = 0, cus = 256;
     std::vector<lbm::BatchInstance> host_tab;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -134,7 +134,7 @@ lbm::StepArgs instance_args(lbm_axi_batch* b, int k, int parity) {
     a.big_nz = p.nz >= c.tz + 6 ? 1 : 0;
     a.wall = p.wall;
     a.axisym = p.axisym;
-    a.guo = (p.flags & LBM_AXI_FLAG_GUO) ? 1 : 0;
+    a.opts = lbm_host::option_bits(p.flags);
     a.G = p.G;
     a.tau = p.tau;
     a.rho0 = p.psi_rho0;
@@ -250,7 +250,7 @@ int lbm_axi_batch_create(const lbm_axi_params* ps, int32_t n_inst, const double*
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->precision = ps[0].precision;
     for (int k = 0; k < n_inst; ++k)
-        if (ps[k].flags & LBM_AXI_FLAG_GUO) b->any_guo = 1;
+        if (ps[k].flags != 0) b->any_guo = 1;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev), "get device");
     if (hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || b->cus < 1)
@@ -318,7 +318,7 @@ int lbm_axi_batch_moments(lbm_axi_batch_t b, int32_t k, double* d_rho, double* d
     a.uz_out = d_uz;
     a.ur_out = d_ur;
     a.partials = nullptr;
-    const TileFn fn = b->precision == LBM_AXI_FP64 ? kMom64[b->cfg] : kMom32[b->cfg];
+    const TileFn fn = b->precision == LBM_AXI_FP64 ? kMom64[b->any_guo][b->cfg] : kMom32[b->any_guo][b->cfg];
     fn(dim3(tiles_of(b->p[k], b->config())), b->stream, a);
     HIP_TRY(hipGetLastError(), "moments launch");
     return LBM_AXI_OK;

@@ -116,7 +116,7 @@ lbm::StepArgs make_args(lbm_axi_ctx* h) {
     a.big_nz = h->p.nz >= kShape[h->L.cfg].tz + 6 ? 1 : 0;
     a.wall = h->p.wall;
     a.axisym = h->p.axisym;
-    a.guo = (h->p.flags & LBM_AXI_FLAG_GUO) ? 1 : 0;
+    a.opts = lbm_host::option_bits(h->p.flags);
     a.G = h->p.G;
     a.tau = h->p.tau;
     a.rho0 = h->p.psi_rho0;
@@ -125,35 +125,38 @@ lbm::StepArgs make_args(lbm_axi_ctx* h) {
     return a;
 }
 
-template <bool kMoments, int kForce>
+template <bool kMoments, int kOpt>
 void launch_shape(lbm_axi_ctx* h, const lbm::StepArgs& a) {
     const dim3 grid(h->L.nblocks);
     const bool f64 = h->p.precision == LBM_AXI_FP64;
     if (h->L.cfg == 0) {
         if (f64)
-            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, 64, 32, kNT64, kMoments, kForce>), grid, dim3(kNT64),
+            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, 64, 32, kNT64, kMoments, kOpt>), grid, dim3(kNT64),
                                0, h->stream, a);
         else
-            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, 64, 32, kNT32, kMoments, kForce>), grid,
+            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, 64, 32, kNT32, kMoments, kOpt>), grid,
                                dim3(kNT32), 0, h->stream, a);
     } else {
         if (f64)
-            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, 32, 16, kNTSmall, kMoments, kForce>), grid,
+            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, 32, 16, kNTSmall, kMoments, kOpt>), grid,
                                dim3(kNTSmall), 0, h->stream, a);
         else
-            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, 32, 16, kNTSmall, kMoments, kForce>), grid,
+            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, 32, 16, kNTSmall, kMoments, kOpt>), grid,
                                dim3(kNTSmall), 0, h->stream, a);
     }
 }
 
-// the forcing option is a compile-time choice of the kernel (the moments do
-// not depend on it)
+// the options are compile-time choices of the kernel (the moments depend on
+// the wall-derivative option only)
 template <bool kMoments>
 int launch_tile(lbm_axi_ctx* h, const lbm::StepArgs& a) {
-    if (!kMoments && (h->p.flags & LBM_AXI_FLAG_GUO))
-        launch_shape<kMoments, 1>(h, a);
-    else
-        launch_shape<kMoments, 0>(h, a);
+    const int o = kMoments ? (a.opts & 2) : a.opts;
+    switch (o) {
+        case 0: launch_shape<kMoments, 0>(h, a); break;
+        case 1: launch_shape<kMoments, 1>(h, a); break;
+        case 2: launch_shape<kMoments, 2>(h, a); break;
+        default: launch_shape<kMoments, 3>(h, a); break;
+    }
     HIP_TRY(hipGetLastError(), "step kernel launch");
     return LBM_AXI_OK;
 }

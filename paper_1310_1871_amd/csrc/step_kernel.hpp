@@ -43,7 +43,7 @@ struct StepArgs {
     int big_nz;        // 1 if nz >= TZ + 6: periodic wrap needs one add/sub
     int wall;          // 0 no-slip, 1 free-slip
     int axisym;        // 1 axisymmetric terms on
-    int guo;           // 1: Guo forcing instead of the velocity shift
+    int opts;          // option bits: 1 Guo forcing, 2 no derivative terms across the wall
     double G, tau, rho0, gz, rho_ref;
 };
 
@@ -141,9 +141,12 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
 
 // One TZ x TR tile of one lattice: the whole step (or the moments) for the
 // tile's nodes.  `tile` = tz * tiles_r + tr; `slot` indexes the per-block
-// partial sums of the moments mode.  kForce: 0 velocity-shift forcing, 1 Guo
-// forcing, 2 chosen at run time by StepArgs::guo (instances of a batch).
-template <class P, int TZ, int TR, int NT, bool kMoments, int kForce = 0>
+// partial sums of the moments mode.  kOpt: the option bits, known at compile
+// time (1: Guo forcing instead of the velocity shift; 2: the derivative terms
+// -- F^{gamma,sym} and the velocity derivatives in H -- are zero on rows
+// whose stencils reach across the outer wall), or -1: read at run time from
+// StepArgs::opts (instances of a batch).
+template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt = 0>
 __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, const int slot) {
     using S = typename P::S;
     using C = typename P::C;
@@ -172,6 +175,9 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     const int t = threadIdx.x;
     const int tzi = tile / a.tiles_r;
     const int z0 = tzi * TZ, r0 = (tile - tzi * a.tiles_r) * TR;
+    const int opts = kOpt < 0 ? a.opts : kOpt;
+    const bool guo = (opts & 1) != 0;
+    const bool no_wall_deriv = (opts & 2) != 0;
     const C rho0 = C(a.rho0);
     const C inv_rho0 = C(1.0 / a.rho0);
     const C rho_ref = C(a.rho_ref);
@@ -287,7 +293,8 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         const C psi = s_psi[py * PZ + px];
         Fz = -G * psi * sz;
         Fr = -G * psi * sr;
-        if (a.axisym) {
+        // F^{gamma,sym} reads psi up to 4 rows away
+        if (a.axisym && !(no_wall_deriv && r0 - 2 + uy >= nr - 4)) {
             const C dr1 = s_dr[dy * DZ + dx];
             const C drr = d_iso<true>(s_dr, dy, dx, DZ);
             // mixed derivative: 1D fourth-order d_z of the 1D fourth-order d_r
@@ -411,9 +418,11 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             const C Fz = Fz_t[k], Fr = Fr_t[k];
             C hz = C(0), hr = C(0), mass = C(0);
             if (a.axisym) {
-                const C druz = d_iso<true>(s_uz, uy, ux, UZ);
-                const C dzur = d_iso<false>(s_ur, uy, ux, UZ);
-                const C drur = d_iso<true>(s_ur, uy, ux, UZ);
+                // the velocity derivatives read rows up to 2 away
+                const bool zd = no_wall_deriv && gr >= nr - 2;
+                const C druz = zd ? C(0) : d_iso<true>(s_uz, uy, ux, UZ);
+                const C dzur = zd ? C(0) : d_iso<false>(s_ur, uy, ux, UZ);
+                const C drur = zd ? C(0) : d_iso<true>(s_ur, uy, ux, UZ);
                 const C inv_r = dev_rcp(rr);
                 const C mu = rho * mu_fac;
                 hz = (mu * (druz + dzur) - rho * ur * uz) * inv_r;
@@ -421,7 +430,6 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
                 mass = -rho * ur * inv_r;
             }
             const C inv_rho = dev_rcp(rho);
-            const bool guo = kForce == 2 ? a.guo != 0 : kForce == 1;
             // equilibrium velocity: shifted by tau F (Eq. ueq), or the
             // hydrodynamic velocity with Guo forcing
             const C qz = guo ? uz : (jz + tau * Fz) * inv_rho;
@@ -506,9 +514,9 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     }
 }
 
-template <class P, int TZ, int TR, int NT, bool kMoments, int kForce = 0>
+template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt = 0>
 __global__ __launch_bounds__(NT) void axi_tile_kernel(const StepArgs a) {
-    tile_body<P, TZ, TR, NT, kMoments, kForce>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x);
+    tile_body<P, TZ, TR, NT, kMoments, kOpt>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x);
 }
 
 // Batched ensemble: many independent lattices (each with its own size,
@@ -520,7 +528,7 @@ struct BatchInstance {
     StepArgs args[2];  // [parity]: fin/fout swapped
 };
 
-template <class P, int TZ, int TR, int NT, int kForce = 0>
+template <class P, int TZ, int TR, int NT, int kOpt = 0>
 __global__ __launch_bounds__(NT) void axi_batch_kernel(const BatchInstance* __restrict__ insts,
                                                       const int2* __restrict__ items, int n_items, int parity) {
     for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
@@ -530,7 +538,7 @@ __global__ __launch_bounds__(NT) void axi_batch_kernel(const BatchInstance* __re
         const int inst = __builtin_amdgcn_readfirstlane(w.x);
         const int tile = __builtin_amdgcn_readfirstlane(w.y);
         const StepArgs a = insts[inst].args[parity];
-        tile_body<P, TZ, TR, NT, false, kForce>(a, tile, 0);
+        tile_body<P, TZ, TR, NT, false, kOpt>(a, tile, 0);
         __syncthreads();  // the next item reuses the LDS windows
     }
 }

@@ -25,6 +25,7 @@ WALL_FREESLIP = 1
 FP64 = 0
 FP32_SHIFTED = 1
 FLAG_GUO = 4  # Guo forcing instead of the velocity shift (include/lbm_axi.h)
+FLAG_NO_WALL_DERIV = 2  # derivative terms zero on rows whose stencils cross the wall
 NREDUCE = 4
 
 

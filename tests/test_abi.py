@@ -35,12 +35,13 @@ def test_parameter_validation():
     assert L.workspace_bytes(good) > 2 * 9 * 64 * 32 * 8
     for field, value, msg in [("nz", 0, "nz"), ("nr", 5, "nr"), ("tau", 0.5, "tau"), ("wall", 2, "wall"),
                               ("axisym", 3, "axisym"), ("precision", 7, "precision"), ("psi_rho0", 0.0, "psi_rho0"),
-                              ("flags", 1, "flags"), ("flags", 8, "flags")]:
+                              ("flags", 1, "flags"), ("flags", 8, "flags"), ("flags", 3, "flags")]:
         p = L.make_params(64, 32)
         setattr(p, field, value)
         assert L.workspace_bytes(p) == 0
         assert msg in L.last_error()
-    assert L.workspace_bytes(L.make_params(64, 32, flags=L.FLAG_GUO)) == L.workspace_bytes(good)
+    for flags in (L.FLAG_GUO, L.FLAG_NO_WALL_DERIV, L.FLAG_GUO | L.FLAG_NO_WALL_DERIV):
+        assert L.workspace_bytes(L.make_params(64, 32, flags=flags)) == L.workspace_bytes(good)
 
 
 def test_fp32_workspace_is_half():

@@ -67,6 +67,25 @@ def test_guo_forcing_ragged_and_body_force():
     _compare(nz, nr, rho, 200, G=-4.0, tau=0.8, wall=0, gz=1e-5, uz=uz, ur=ur, flags=4)
 
 
+@pytest.mark.parametrize("flags", [2, 6])
+@pytest.mark.parametrize("wall", [0, 1])
+def test_wall_derivative_option_static_drop(wall, flags):
+    """The other reading of the wall derivative rule (flag 2), alone and
+    with Guo forcing (flag 6), on a drop that touches the wall region:
+    512 steps against the oracle."""
+    from lbm_inputs import drop_density
+    rg, rl = coexistence_densities(-5.0)
+    rho = drop_density(64, 24, 32.0, 14.0, rl, rg, 2.0, {2: 1.5})
+    _compare(64, 24, rho, 512, G=-5.0, tau=0.9, wall=wall, flags=flags)
+
+
+def test_wall_derivative_option_large_tiles():
+    """Flag 2 on the 64 x 32 tile shape (ragged 4100 x 515), 4 steps."""
+    nz, nr = 4100, 515
+    rho, uz, ur = random_state_fields(4100516, nz, nr, rho_lo=0.3, rho_hi=2.0, u_amp=0.01)
+    _compare(nz, nr, rho, 4, G=-5.0, tau=0.9, wall=0, uz=uz, ur=ur, flags=2)
+
+
 def test_oscillating_drop_shape_1000_steps():
     """Drop oscillation lattice 256 x 128 (P2 perturbation, seeded noise),
     tau = 0.8 (the lowest tau of that workload the scheme keeps stable)."""
