@@ -117,6 +117,26 @@ int lbm_axi_moments(lbm_axi_t h, double* d_rho, double* d_uz, double* d_ur);
 #define LBM_AXI_NREDUCE 4
 int lbm_axi_reduce(lbm_axi_t h, double* h_out);
 
+/* FP64 interface diagnostics of the current state (Sec. IV.A-IV.C).  In
+ * every column z the interface radius R(z) is the outermost crossing of
+ * rho = rho_mid along r, interpolated linearly between the two nodes around
+ * it (nr - 1/2 if the top node is at or above rho_mid, 0 if no node of the
+ * column is).  d_radius: device array of nz doubles for R(z), or NULL.
+ * h_out[LBM_AXI_NINTERFACE] (host):
+ *   [0] A = R(z_col): radial intercept of a drop centred at column z_col
+ *       (the oscillation amplitude of Sec. IV.B)
+ *   [1] min_z R(z): neck radius of a thread (Sec. IV.C)
+ *   [2] max_z R(z)
+ *   [3] min_z rho on the row next to the axis: below rho_mid the thread has
+ *       broken (Sec. IV.C)
+ *   [4] rho_in  = rho(z_col, row 0)
+ *   [5] rho_out = rho(0, row nr - 1)
+ *   [6] dp = p(rho_in) - p(rho_out) with p = rho/3 + (G/6) psi^2 (Sec. II.A,
+ *       Eq. pressure): the Laplace pressure jump of Sec. IV.A
+ * 0 <= z_col < nz.  Synchronises the stream. */
+#define LBM_AXI_NINTERFACE 7
+int lbm_axi_interface(lbm_axi_t h, double rho_mid, int32_t z_col, double* d_radius, double* h_out);
+
 /* Size in bytes of the population state (9 nz nr values of the storage
  * type, in the library's structure-of-arrays layout [9][nr][nz]). */
 size_t lbm_axi_state_bytes(lbm_axi_t h);

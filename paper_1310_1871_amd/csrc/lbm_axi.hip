@@ -40,6 +40,7 @@ struct Layout {
     size_t off_b;         // second buffer
     size_t off_partials;  // [max blocks][4] doubles
     size_t off_red;       // [4] doubles
+    size_t off_iface;     // interface scratch: R(z) [nz], rho on row 0 [nz], outputs [8]
     size_t total;
     int cfg;              // tile shape in use
     int tiles_z, tiles_r, nblocks;
@@ -59,7 +60,8 @@ Layout layout_of(const lbm_axi_params* p, int cfg) {
     L.off_b = align_up(L.state_bytes);
     L.off_partials = L.off_b + align_up(L.state_bytes);
     L.off_red = L.off_partials + align_up((size_t)max_blocks * 4 * sizeof(double));
-    L.total = L.off_red + align_up(4 * sizeof(double));
+    L.off_iface = L.off_red + align_up(4 * sizeof(double));
+    L.total = L.off_iface + align_up((2 * (size_t)p->nz + 8) * sizeof(double));
     return L;
 }
 
@@ -89,6 +91,81 @@ __global__ void finalize_reduce_kernel(const double* partials, int nblocks, doub
         __syncthreads();
     }
     if (t < 4) out[t] = s[t][0];
+}
+
+// One thread per column: the interface radius R(z) (outermost rho_mid
+// crossing along r, the rows read from the top down so that the first
+// crossing found is the outermost) and rho on the row next to the axis.
+template <class P>
+__global__ void interface_columns_kernel(const typename P::S* __restrict__ f, long long plane, int nz, int nr,
+                                         double rho_ref, double rho_mid, double* __restrict__ radius,
+                                         double* __restrict__ rho_axis) {
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= nz) return;
+    auto rho_at = [&](int r) {
+        const long long x = (long long)r * nz + z;
+        double s = 0.0;
+        for (int i = 0; i < lbm::kQ; ++i) s += double(f[i * plane + x]);
+        return P::kShift ? s + rho_ref : s;
+    };
+    double R = 0.0, above = 0.0;
+    for (int r = nr - 1; r >= 0; --r) {
+        const double a = rho_at(r);
+        if (a >= rho_mid) {
+            R = (r == nr - 1) ? nr - 0.5 : (r + 0.5) + (a - rho_mid) / (a - above);
+            break;
+        }
+        above = a;
+    }
+    radius[z] = R;
+    rho_axis[z] = rho_at(0);
+}
+
+// single workgroup: min / max over the columns in a fixed order, then the
+// outputs of lbm_axi_interface
+template <class P>
+__global__ void interface_reduce_kernel(const typename P::S* __restrict__ f, long long plane, int nz, int nr,
+                                        double rho_ref, double G, double rho0, int z_col,
+                                        const double* __restrict__ radius, const double* __restrict__ rho_axis,
+                                        double* __restrict__ out) {
+    __shared__ double s_min[256], s_max[256], s_ax[256];
+    const int t = threadIdx.x;
+    double mn = 1e300, mx = -1e300, ax = 1e300;
+    for (int z = t; z < nz; z += 256) {
+        mn = fmin(mn, radius[z]);
+        mx = fmax(mx, radius[z]);
+        ax = fmin(ax, rho_axis[z]);
+    }
+    s_min[t] = mn;
+    s_max[t] = mx;
+    s_ax[t] = ax;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (t < k) {
+            s_min[t] = fmin(s_min[t], s_min[t + k]);
+            s_max[t] = fmax(s_max[t], s_max[t + k]);
+            s_ax[t] = fmin(s_ax[t], s_ax[t + k]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const long long top = (long long)(nr - 1) * nz;
+        double rout = 0.0;
+        for (int i = 0; i < lbm::kQ; ++i) rout += double(f[i * plane + top]);
+        if (P::kShift) rout += rho_ref;
+        const double rin = rho_axis[z_col];
+        auto pressure = [&](double rho) {
+            const double psi = rho0 * (1.0 - exp(-rho / rho0));
+            return rho / 3.0 + G / 6.0 * psi * psi;
+        };
+        out[0] = radius[z_col];
+        out[1] = s_min[0];
+        out[2] = s_max[0];
+        out[3] = s_ax[0];
+        out[4] = rin;
+        out[5] = rout;
+        out[6] = pressure(rin) - pressure(rout);
+    }
 }
 
 }  // namespace
@@ -250,6 +327,38 @@ int lbm_axi_reduce(lbm_axi_t h, double* h_out) {
     HIP_TRY(hipStreamSynchronize(h->stream), "reduce synchronize");
     for (int k = 0; k < LBM_AXI_NREDUCE; ++k)
         if (!std::isfinite(h_out[k])) return fail(LBM_AXI_ENONFINITE, "diagnostic %d is not finite", k);
+    return LBM_AXI_OK;
+}
+
+int lbm_axi_interface(lbm_axi_t h, double rho_mid, int32_t z_col, double* d_radius, double* h_out) {
+    if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
+    if (!h_out) return fail(LBM_AXI_EINVAL, "h_out is NULL");
+    if (z_col < 0 || z_col >= h->p.nz) return fail(LBM_AXI_EINVAL, "z_col out of range (0 .. %d)", h->p.nz - 1);
+    if (!std::isfinite(rho_mid)) return fail(LBM_AXI_EINVAL, "rho_mid must be finite");
+    double* scratch = reinterpret_cast<double*>(h->ws + h->L.off_iface);
+    double* radius = d_radius ? d_radius : scratch;
+    double* rho_axis = scratch + h->p.nz;
+    double* d_out = scratch + 2 * (size_t)h->p.nz;
+    const long long plane = (long long)h->p.nz * h->p.nr;
+    const double rho_ref = h->p.precision == LBM_AXI_FP64 ? 0.0 : h->p.rho_ref;
+    const dim3 cols((h->p.nz + 255) / 256);
+    if (h->p.precision == LBM_AXI_FP64) {
+        const double* f = static_cast<const double*>(state_ptr(h, h->cur));
+        hipLaunchKernelGGL(interface_columns_kernel<lbm::PrecF64>, cols, dim3(256), 0, h->stream, f, plane, h->p.nz,
+                           h->p.nr, rho_ref, rho_mid, radius, rho_axis);
+        hipLaunchKernelGGL(interface_reduce_kernel<lbm::PrecF64>, dim3(1), dim3(256), 0, h->stream, f, plane,
+                           h->p.nz, h->p.nr, rho_ref, h->p.G, h->p.psi_rho0, z_col, radius, rho_axis, d_out);
+    } else {
+        const float* f = static_cast<const float*>(state_ptr(h, h->cur));
+        hipLaunchKernelGGL(interface_columns_kernel<lbm::PrecF32S>, cols, dim3(256), 0, h->stream, f, plane, h->p.nz,
+                           h->p.nr, rho_ref, rho_mid, radius, rho_axis);
+        hipLaunchKernelGGL(interface_reduce_kernel<lbm::PrecF32S>, dim3(1), dim3(256), 0, h->stream, f, plane,
+                           h->p.nz, h->p.nr, rho_ref, h->p.G, h->p.psi_rho0, z_col, radius, rho_axis, d_out);
+    }
+    HIP_TRY(hipGetLastError(), "interface kernel launch");
+    HIP_TRY(hipMemcpyAsync(h_out, d_out, LBM_AXI_NINTERFACE * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+            "interface copy");
+    HIP_TRY(hipStreamSynchronize(h->stream), "interface synchronize");
     return LBM_AXI_OK;
 }
 

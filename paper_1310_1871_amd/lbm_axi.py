@@ -27,6 +27,7 @@ FP32_SHIFTED = 1
 FLAG_GUO = 4  # Guo forcing instead of the velocity shift (include/lbm_axi.h)
 FLAG_NO_WALL_DERIV = 2  # derivative terms zero on rows whose stencils cross the wall
 NREDUCE = 4
+NINTERFACE = 7
 
 
 class Params(ctypes.Structure):
@@ -64,6 +65,7 @@ def _load():
         "lbm_axi_step": (ctypes.c_int, [vp, ctypes.c_int64]),
         "lbm_axi_moments": (ctypes.c_int, [vp, vp, vp, vp]),
         "lbm_axi_reduce": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double)]),
+        "lbm_axi_interface": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]),
         "lbm_axi_state_bytes": (ctypes.c_size_t, [vp]),
         "lbm_axi_get_state": (ctypes.c_int, [vp, vp]),
         "lbm_axi_set_state": (ctypes.c_int, [vp, vp]),
@@ -173,6 +175,19 @@ class AxiLBM:
             raise LbmAxiError(rc, last_error() + f" {vals}")
         check(rc)
         return vals
+
+    def interface(self, rho_mid, z_col=None, radius_out=None):
+        """Interface diagnostics (include/lbm_axi.h, lbm_axi_interface):
+        dict with A, neck, r_max, rho_axis_min, rho_in, rho_out, dp; the
+        radius profile R(z) goes into ``radius_out`` (float64 device tensor
+        [nz]) if given.  Synchronises the stream."""
+        self._sync_stream()
+        z_col = self.nz // 2 if z_col is None else int(z_col)
+        out = (ctypes.c_double * NINTERFACE)()
+        check(lib.lbm_axi_interface(self._h, float(rho_mid), z_col, _ptr(radius_out) if radius_out is not None else None,
+                                    out))
+        keys = ("A", "neck", "r_max", "rho_axis_min", "rho_in", "rho_out", "dp")
+        return {k: float(v) for k, v in zip(keys, out)}
 
     def state_bytes(self):
         return int(lib.lbm_axi_state_bytes(self._h))

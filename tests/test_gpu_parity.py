@@ -144,6 +144,39 @@ def test_reduce_and_moments_match_oracle_diagnostics():
         assert abs(a - b) <= 1e-10 * max(1.0, abs(b)), (red, ref)
 
 
+@pytest.mark.parametrize("case", ["drop", "thread"])
+def test_interface_diagnostics_match_oracle(case):
+    """lbm_axi_interface against the oracle's diagnostics on the oracle's
+    state after the same steps: the drop intercept A(t), the radius profile
+    R(z) with its minimum (thread neck) and maximum, the minimum density on
+    the row next to the axis (break-up), and the Laplace pressure jump."""
+    L = _lib()
+    if case == "drop":
+        c = static_drop()
+        nz, nr, rho, G, tau, steps = c.nz, c.nr, c.rho, c.G, c.tau, 300
+        mid = 0.5 * (c.rho_l + c.rho_g)
+    else:
+        G, tau, nz, nr, steps = -5.5, 1.0, 512, 96, 200
+        rg, rl = coexistence_densities(G)
+        rho = thread_density(nz, nr, 24.0, rl, rg, 2.0, 0.2, 2)
+        mid = 0.5 * (rl + rg)
+    _say(f"interface diagnostics {case} {nz}x{nr}, {steps} steps")
+    sim = L.AxiLBM(L.make_params(nz, nr, G=G, tau=tau, wall=1), torch.from_numpy(rho).cuda())
+    sim.step(steps)
+    radius = torch.empty(nz, dtype=torch.float64, device="cuda")
+    got = sim.interface(mid, nz // 2, radius)
+    sim.close()
+    p = O.make_params(nz, nr, G=G, tau=tau, wall=1)
+    ro, _, _ = O.moments(p, O.run(p, O.equilibrium(p, rho, 0 * rho, 0 * rho), steps))
+    prof = np.array([D.axis_intercept(ro, z, mid) for z in range(nz)])
+    assert np.abs(radius.cpu().numpy() - prof).max() < 1e-9
+    want = {"A": prof[nz // 2], "neck": prof.min(), "r_max": prof.max(), "rho_axis_min": ro[0].min(),
+            "rho_in": ro[0, nz // 2], "rho_out": ro[-1, 0],
+            "dp": D.pressure(ro[0, nz // 2], G) - D.pressure(ro[-1, 0], G)}
+    for k, v in want.items():
+        assert abs(got[k] - v) < 1e-9 * max(1.0, abs(v)), (k, got[k], v)
+
+
 def test_state_roundtrip_and_resume():
     """get_state/set_state: a run checkpointed at step 100 and resumed
     reproduces the uninterrupted run bit for bit."""
