@@ -137,6 +137,24 @@ int lbm_axi_reduce(lbm_axi_t h, double* h_out);
 #define LBM_AXI_NINTERFACE 7
 int lbm_axi_interface(lbm_axi_t h, double rho_mid, int32_t z_col, double* d_radius, double* h_out);
 
+/* Drops on the axis once a thread has broken up (Sec. IV.C: the thread
+ * breaks into two or more drops when kappa* < 1).  A drop is a maximal run
+ * of consecutive columns, periodic in z, whose axis node (row 0) has
+ * rho >= rho_mid.  Its 3D volume is sum_z pi R(z)^2, the solid of revolution
+ * of the interface radius R(z) of lbm_axi_interface, and its centre the
+ * volume-weighted mean column, counted from the first column with
+ * rho < rho_mid on the axis onward and taken modulo nz.  Drops are listed in
+ * that order.
+ *   h_count (host): number of drops; 0 if no axis node reaches rho_mid; -1
+ *     if every axis node does (an unbroken thread).
+ *   h_volume[k], h_centre[k] (host, max_drops entries each) for
+ *     k < min(count, max_drops).
+ * 0 <= max_drops <= LBM_AXI_MAX_DROPS (h_volume and h_centre may be NULL
+ * when it is 0).  Synchronises the stream. */
+#define LBM_AXI_MAX_DROPS 64
+int lbm_axi_drops(lbm_axi_t h, double rho_mid, int32_t max_drops, int32_t* h_count, double* h_volume,
+                  double* h_centre);
+
 /* Size in bytes of the population state (9 nz nr values of the storage
  * type, in the library's structure-of-arrays layout [9][nr][nz]). */
 size_t lbm_axi_state_bytes(lbm_axi_t h);

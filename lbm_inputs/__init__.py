@@ -167,6 +167,20 @@ def rp_thread(nz=4096, nr=512, radius=64.0, eps=0.1, mode=1, G=-5.5, tau=0.7, wa
                 {"radius": radius, "eps": eps, "mode": mode})
 
 
+def rp_wavelength(lam, nr=450, radius=60.0, G=-6.0, tau=1.0, eps=4e-3, wall=1, steps=80000):
+    """Unperturbed liquid cylinder of radius R on a lam x nr lattice (one
+    wavelength, periodic in z) with the axial velocity eps sin(2 pi z / lam)
+    inside the liquid, weighted by the liquid fraction (the Rayleigh–Plateau
+    wavelength sweep, lam x 450, G = -6).  R = 60 and tau = 1 (nu = 1/6,
+    Oh = 0.094) follow from the sweep's kappa* = 0.65 panel and Oh = 0.09."""
+    rho_g, rho_l = coexistence_densities(G)
+    rho = thread_density(lam, nr, radius, rho_l, rho_g, 2.0)
+    z, _ = node_coords(lam, nr)
+    uz = eps * np.sin(2.0 * np.pi * z / lam) * (rho - rho_g) / (rho_l - rho_g)
+    return Case("rp_wavelength", lam, nr, G, tau, wall, rho, np.ascontiguousarray(uz), np.zeros_like(rho), steps,
+                rho_l, rho_g, {"radius": radius, "eps": eps, "kappa": 2.0 * np.pi * radius / lam})
+
+
 def adjoint_coeffs(seed, radius=40.0, ls=(2, 3, 4, 5, 6), frac=0.05):
     """Seeded Legendre coefficients a_l ~ U[-frac*R, frac*R]."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -134,6 +134,42 @@ def interface_radius(rho, weights, rho_l, rho_g):
     return np.array([np.dot(w, flat[idx]) for idx, w in weights])
 
 
+def drops(rho, rho_mid):
+    """Drops on the axis once a thread has broken up (Sec. IV.C).
+
+    Reading: a drop is a maximal run of consecutive columns, periodic in z,
+    whose axis node (row 0) has rho >= rho_mid.  Its 3D volume is the solid
+    of revolution of the interface radius R(z) of axis_intercept,
+    sum_z pi R(z)^2, and its centre the volume-weighted mean column, counted
+    without wrapping from the first gas column onward and then taken modulo
+    nz.  Returns (n, volumes, centres): n = -1 with no drops if every axis
+    node is liquid (an unbroken thread), n = 0 if none is.  Drops are listed
+    from the first gas column onward."""
+    nz = rho.shape[1]
+    liquid = rho[0] >= rho_mid
+    if liquid.all():
+        return -1, [], []
+    if not liquid.any():
+        return 0, [], []
+    start = int(np.argmin(liquid))  # first gas column
+    vols, cents = [], []
+    k = 0
+    while k < nz:
+        if not liquid[(start + k) % nz]:
+            k += 1
+            continue
+        v = m = 0.0
+        while k < nz and liquid[(start + k) % nz]:
+            R = axis_intercept(rho, (start + k) % nz, rho_mid)
+            w = np.pi * (R * R)
+            v += w
+            m += w * float(start + k)
+            k += 1
+        vols.append(v)
+        cents.append((m / v) % nz)
+    return len(vols), vols, cents
+
+
 def breakup_step(rho_axis_history, rho_mid):
     """First index at which any axis node (row 0) falls below rho_mid
     (reading of the break-up time), or None."""

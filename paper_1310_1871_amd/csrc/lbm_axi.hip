@@ -40,7 +40,7 @@ struct Layout {
     size_t off_b;         // second buffer
     size_t off_partials;  // [max blocks][4] doubles
     size_t off_red;       // [4] doubles
-    size_t off_iface;     // interface scratch: R(z) [nz], rho on row 0 [nz], outputs [8]
+    size_t off_iface;     // interface scratch: R(z) [nz], rho on row 0 [nz], outputs [8], drops [1 + 2 max]
     size_t total;
     int cfg;              // tile shape in use
     int tiles_z, tiles_r, nblocks;
@@ -61,7 +61,7 @@ Layout layout_of(const lbm_axi_params* p, int cfg) {
     L.off_partials = L.off_b + align_up(L.state_bytes);
     L.off_red = L.off_partials + align_up((size_t)max_blocks * 4 * sizeof(double));
     L.off_iface = L.off_red + align_up(4 * sizeof(double));
-    L.total = L.off_iface + align_up((2 * (size_t)p->nz + 8) * sizeof(double));
+    L.total = L.off_iface + align_up((2 * (size_t)p->nz + 8 + 1 + 2 * LBM_AXI_MAX_DROPS) * sizeof(double));
     return L;
 }
 
@@ -166,6 +166,49 @@ __global__ void interface_reduce_kernel(const typename P::S* __restrict__ f, lon
         out[5] = rout;
         out[6] = pressure(rin) - pressure(rout);
     }
+}
+
+// one thread: the drops along the axis (runs of columns whose row 0 is at
+// or above rho_mid, periodic in z), listed from the first gas column on;
+// volume sum_z pi R(z)^2 and volume-weighted centre of each.  out[0] is the
+// count (-1: every axis node is liquid), then max_drops volumes, then
+// max_drops centres.
+__global__ void drops_scan_kernel(const double* __restrict__ radius, const double* __restrict__ rho_axis, int nz,
+                                  double rho_mid, int max_drops, double* __restrict__ out) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int start = -1;
+    for (int z = 0; z < nz; ++z) {
+        if (rho_axis[z] < rho_mid) {
+            start = z;
+            break;
+        }
+    }
+    if (start < 0) {
+        out[0] = -1.0;
+        return;
+    }
+    auto col = [&](int k) { return start + k < nz ? start + k : start + k - nz; };
+    int n = 0, k = 0;
+    while (k < nz) {
+        if (rho_axis[col(k)] < rho_mid) {
+            ++k;
+            continue;
+        }
+        double v = 0.0, m = 0.0;
+        while (k < nz && rho_axis[col(k)] >= rho_mid) {
+            const double R = radius[col(k)];
+            const double w = 3.141592653589793 * (R * R);
+            v += w;
+            m += w * double(start + k);
+            ++k;
+        }
+        if (n < max_drops) {
+            out[1 + n] = v;
+            out[1 + max_drops + n] = fmod(m / v, double(nz));
+        }
+        ++n;
+    }
+    out[0] = double(n);
 }
 
 }  // namespace
@@ -359,6 +402,47 @@ int lbm_axi_interface(lbm_axi_t h, double rho_mid, int32_t z_col, double* d_radi
     HIP_TRY(hipMemcpyAsync(h_out, d_out, LBM_AXI_NINTERFACE * sizeof(double), hipMemcpyDeviceToHost, h->stream),
             "interface copy");
     HIP_TRY(hipStreamSynchronize(h->stream), "interface synchronize");
+    return LBM_AXI_OK;
+}
+
+int lbm_axi_drops(lbm_axi_t h, double rho_mid, int32_t max_drops, int32_t* h_count, double* h_volume,
+                  double* h_centre) {
+    if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
+    if (!h_count) return fail(LBM_AXI_EINVAL, "h_count is NULL");
+    if (max_drops < 0 || max_drops > LBM_AXI_MAX_DROPS)
+        return fail(LBM_AXI_EINVAL, "max_drops out of range (0 .. %d)", LBM_AXI_MAX_DROPS);
+    if (max_drops > 0 && (!h_volume || !h_centre)) return fail(LBM_AXI_EINVAL, "h_volume or h_centre is NULL");
+    if (!std::isfinite(rho_mid)) return fail(LBM_AXI_EINVAL, "rho_mid must be finite");
+    double* scratch = reinterpret_cast<double*>(h->ws + h->L.off_iface);
+    double* radius = scratch;
+    double* rho_axis = scratch + h->p.nz;
+    double* d_out = scratch + 2 * (size_t)h->p.nz + 8;
+    const long long plane = (long long)h->p.nz * h->p.nr;
+    const double rho_ref = h->p.precision == LBM_AXI_FP64 ? 0.0 : h->p.rho_ref;
+    const dim3 cols((h->p.nz + 255) / 256);
+    if (h->p.precision == LBM_AXI_FP64) {
+        const double* f = static_cast<const double*>(state_ptr(h, h->cur));
+        hipLaunchKernelGGL(interface_columns_kernel<lbm::PrecF64>, cols, dim3(256), 0, h->stream, f, plane, h->p.nz,
+                           h->p.nr, rho_ref, rho_mid, radius, rho_axis);
+    } else {
+        const float* f = static_cast<const float*>(state_ptr(h, h->cur));
+        hipLaunchKernelGGL(interface_columns_kernel<lbm::PrecF32S>, cols, dim3(256), 0, h->stream, f, plane, h->p.nz,
+                           h->p.nr, rho_ref, rho_mid, radius, rho_axis);
+    }
+    hipLaunchKernelGGL(drops_scan_kernel, dim3(1), dim3(64), 0, h->stream, radius, rho_axis, h->p.nz, rho_mid,
+                       max_drops, d_out);
+    HIP_TRY(hipGetLastError(), "drops kernel launch");
+    double host[1 + 2 * LBM_AXI_MAX_DROPS];
+    HIP_TRY(hipMemcpyAsync(host, d_out, (1 + 2 * (size_t)max_drops) * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream),
+            "drops copy");
+    HIP_TRY(hipStreamSynchronize(h->stream), "drops synchronize");
+    const int n = (int)host[0];
+    *h_count = n;
+    for (int k = 0; k < n && k < max_drops; ++k) {
+        h_volume[k] = host[1 + k];
+        h_centre[k] = host[1 + max_drops + k];
+    }
     return LBM_AXI_OK;
 }
 

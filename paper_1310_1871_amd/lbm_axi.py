@@ -28,6 +28,7 @@ FLAG_GUO = 4  # Guo forcing instead of the velocity shift (include/lbm_axi.h)
 FLAG_NO_WALL_DERIV = 2  # derivative terms zero on rows whose stencils cross the wall
 NREDUCE = 4
 NINTERFACE = 7
+MAX_DROPS = 64
 
 
 class Params(ctypes.Structure):
@@ -66,6 +67,8 @@ def _load():
         "lbm_axi_moments": (ctypes.c_int, [vp, vp, vp, vp]),
         "lbm_axi_reduce": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double)]),
         "lbm_axi_interface": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]),
+        "lbm_axi_drops": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
         "lbm_axi_state_bytes": (ctypes.c_size_t, [vp]),
         "lbm_axi_get_state": (ctypes.c_int, [vp, vp]),
         "lbm_axi_set_state": (ctypes.c_int, [vp, vp]),
@@ -188,6 +191,18 @@ class AxiLBM:
                                     out))
         keys = ("A", "neck", "r_max", "rho_axis_min", "rho_in", "rho_out", "dp")
         return {k: float(v) for k, v in zip(keys, out)}
+
+    def drops(self, rho_mid, max_drops=MAX_DROPS):
+        """Drops on the axis (include/lbm_axi.h, lbm_axi_drops): (n, volumes,
+        centres) with n = -1 for an unbroken thread.  Synchronises the
+        stream."""
+        self._sync_stream()
+        n = ctypes.c_int32()
+        vol = (ctypes.c_double * max(1, max_drops))()
+        cen = (ctypes.c_double * max(1, max_drops))()
+        check(lib.lbm_axi_drops(self._h, float(rho_mid), int(max_drops), ctypes.byref(n), vol, cen))
+        k = min(max(n.value, 0), max_drops)
+        return n.value, [float(v) for v in vol[:k]], [float(c) for c in cen[:k]]
 
     def state_bytes(self):
         return int(lib.lbm_axi_state_bytes(self._h))

@@ -64,6 +64,8 @@ def test_create_rejects_bad_pointers_without_device_work():
                               1 << 30, None, ctypes.byref(h))
     assert rc == L.EINVAL and "aligned" in L.last_error()
     assert L.lib.lbm_axi_step(None, 1) == L.EINVAL
+    n = ctypes.c_int32()
+    assert L.lib.lbm_axi_drops(None, 1.0, 4, ctypes.byref(n), None, None) == L.EINVAL
     L.lib.lbm_axi_destroy(None)
 
 

@@ -1,0 +1,160 @@
+"""The Rayleigh–Plateau wavelength sweep (Sec. IV.C) on the GPU, and the
+drop diagnostic it uses against the oracle's.
+
+A liquid cylinder of radius R is unstable to disturbances longer than its
+circumference (kappa* = 2 pi R / lambda < 1), and then breaks into two or
+more drops.  The sweep runs the paper's lambda x 450 lattices (G = -6,
+free-slip top, periodic z) with R = 60, so kappa* runs from 0.65 down to
+0.21, plus lambda = 320 (kappa* = 1.18) on the stable side."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import oracle.diagnostics as D
+from lbm_inputs import coexistence_densities, drop_density, rp_wavelength
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_1310_1871_amd import lbm_axi as L
+    return L
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_drops_match_oracle(precision):
+    """lbm_axi_drops against the oracle's drops() on the same density: three
+    drops, one of them across the periodic end, and the two degenerate cases
+    (an unbroken thread, pure gas)."""
+    L = _lib()
+    G = -5.5
+    rg, rl = coexistence_densities(G)
+    nz, nr = 300, 48
+    rho = drop_density(nz, nr, 60.0, 14.0, rl, rg)
+    for zc, a in ((170.0, 9.0), (292.0, 11.0)):
+        rho = np.maximum(rho, drop_density(nz, nr, zc, a, rl, rg))
+        rho = np.maximum(rho, drop_density(nz, nr, zc - nz, a, rl, rg))
+    mid = 0.5 * (rl + rg)
+    r = np.arange(nr)[:, None] + 0.5
+    cylinder = np.where(r < 12.0, rl, rg) * np.ones((1, nz))
+    for name, field, want_n in (("drops", rho, 3), ("thread", cylinder, -1), ("gas", np.full((nr, nz), rg), 0)):
+        _say(f"drops case {name} {precision}")
+        kw = dict(precision=L.FP32_SHIFTED, rho_ref=rg) if precision == "f32" else {}
+        sim = L.AxiLBM(L.make_params(nz, nr, G=G, tau=1.0, wall=1, **kw), torch.from_numpy(field).cuda())
+        n, vols, cents = sim.drops(mid)
+        # rho as the library forms it: the stored values summed in FP64 in
+        # direction order, plus the shift in FP32 storage
+        raw = sim.get_state()
+        if precision == "f64":
+            g = raw.view(torch.float64).reshape(9, nr, nz).cpu().numpy()
+            ro = g[0].copy()
+            for i in range(1, 9):
+                ro += g[i]
+        else:
+            g = raw.view(torch.float32).reshape(9, nr, nz).cpu().numpy().astype(np.float64)
+            ro = g[0].copy()
+            for i in range(1, 9):
+                ro += g[i]
+            ro += rg
+        sim.close()
+        on, ovols, ocents = D.drops(ro, mid)
+        assert n == on == want_n
+        tol = 1e-12
+        for v, c, ov, oc in zip(vols, cents, ovols, ocents):
+            assert v == pytest.approx(ov, rel=tol)
+            assert c == pytest.approx(oc, abs=tol * nz)
+
+
+def test_drops_count_limit():
+    """Fewer slots than drops: the count is still the true one, and the slots
+    hold the first drops in order."""
+    L = _lib()
+    G = -5.5
+    rg, rl = coexistence_densities(G)
+    nz, nr = 240, 32
+    rho = np.full((nr, nz), rg)
+    for zc in (30.0, 90.0, 150.0, 210.0):
+        rho = np.maximum(rho, drop_density(nz, nr, zc, 8.0, rl, rg))
+    sim = L.AxiLBM(L.make_params(nz, nr, G=G, tau=1.0), torch.from_numpy(rho).cuda())
+    n_all, v_all, c_all = sim.drops(0.5 * (rl + rg))
+    n2, v2, c2 = sim.drops(0.5 * (rl + rg), max_drops=2)
+    sim.close()
+    assert n_all == n2 == 4
+    assert v2 == v_all[:2] and c2 == c_all[:2]
+
+
+def _run_rp(lam, max_steps, check_every=500):
+    """Run one wavelength; every check_every steps record the neck, the
+    bulge and the thread volume pi sum_z R(z)^2; stop 3000 steps after
+    break-up.  Returns the case, the break-up step, the records, the volume
+    at the last check before break-up and the drops at the end."""
+    L = _lib()
+    c = rp_wavelength(lam)
+    mid = 0.5 * (c.rho_l + c.rho_g)
+    sim = L.AxiLBM(L.make_params(c.nz, c.nr, G=c.G, tau=c.tau, wall=c.wall), torch.from_numpy(c.rho).cuda(),
+                   torch.from_numpy(c.uz).cuda())
+    radius = torch.empty(c.nz, dtype=torch.float64, device="cuda")
+    brk, step, recs, v_before = None, 0, [], None
+    while step < max_steps:
+        sim.step(check_every)
+        step += check_every
+        d = sim.interface(mid, 0, radius)
+        vol = math.pi * float((radius * radius).sum())
+        if brk is None and d["rho_axis_min"] < mid:
+            brk = step
+            v_before = recs[-1][2]
+        recs.append((d["neck"], d["r_max"], vol))
+        if brk is not None and step >= brk + 3000:
+            break
+    n, vols, cents = sim.drops(mid)
+    sim.close()
+    return c, brk, recs, v_before, n, vols, cents
+
+
+def test_rayleigh_plateau_criterion_and_drops():
+    """kappa* < 1 breaks, kappa* > 1 does not (the criterion of Sec. IV.C).
+
+    Every paper wavelength breaks within 80 000 steps into two drops, a main
+    drop at lambda/2 (where the initial axial flow converges) and one at
+    z = 0, both on the mirror planes of the set-up.  Break-up comes later as
+    kappa* falls, since below kappa* = 0.7 Rayleigh's growth rate falls
+    with kappa*.  The drops hold the thread's volume of the last check
+    before break-up to within 5 %: the Shan–Chen liquid slowly evaporates
+    into the gas (about 0.3 % of its volume per 1000 steps before break-up,
+    faster from the small drops after it), since at tau = 1 the coexistence
+    densities differ slightly from the inputs'.  No drop exceeds the radius
+    of one drop holding the thread's volume.  On the stable
+    wavelength the initial axial flow only sets off a damped capillary
+    oscillation: the bulge-neck difference stays below R/4, has decayed to
+    a tenth of its peak by the end, and the thread never breaks over the
+    same 80 000 steps."""
+    c, brk, recs, _, n, _, _ = _run_rp(320, 80000)
+    amp = [rm - nk for nk, rm, _ in recs]
+    _say(f"lambda 320 kappa* {c.extra['kappa']:.3f}: break {brk}, neck {min(r[0] for r in recs):.1f}, "
+         f"bulge-neck first {amp[0]:.2f} max {max(amp):.2f} last {amp[-1]:.2f}")
+    assert brk is None and n == -1
+    assert max(amp) < 0.25 * c.extra["radius"] and amp[-1] < 0.1 * max(amp)
+    last = 0
+    for lam in (576, 768, 1024, 1280, 1536, 1792):
+        c, brk, recs, v_before, n, vols, cents = _run_rp(lam, 80000)
+        kap = c.extra["kappa"]
+        R = c.extra["radius"]
+        radii = [(3.0 * v / (4.0 * math.pi)) ** (1.0 / 3.0) / R for v in vols]
+        frac = sum(vols) / v_before
+        _say(f"lambda {lam} kappa* {kap:.3f}: break {brk}, drops {n}, R/R0 {[round(x, 3) for x in radii]}, "
+             f"centres {[round(z, 2) for z in cents]}, drops/thread volume {frac:.4f}, "
+             f"thread/cylinder before break-up {v_before / (math.pi * R * R * lam):.4f}")
+        assert brk is not None and brk > last
+        last = brk
+        assert n == 2
+        zs = sorted(min(z, lam - z) for z in cents)
+        assert zs[0] < 1e-3 and abs(zs[1] - lam / 2) < 1e-3
+        assert abs(frac - 1.0) < 0.05
+        assert max(radii) * R <= (3.0 * v_before / (4.0 * math.pi)) ** (1.0 / 3.0)

@@ -94,3 +94,51 @@ def test_bulk_pressures_balance_across_flat_interface():
     p_g = D.pressure(rr[-1:, :], G)[0, 0]
     assert rr[0, 0] / rr[-1, 0] > 20
     assert abs(p_l - p_g) < 1e-6 * abs(p_l)
+
+
+def _blocks(nz, nr, blocks, rho_l=2.0, rho_g=0.2):
+    """Sharp liquid blocks: rows 0..m-1 liquid on columns a .. a+L-1 (mod nz)."""
+    rho = np.full((nr, nz), rho_g)
+    for a, L, m in blocks:
+        for k in range(L):
+            rho[:m, (a + k) % nz] = rho_l
+    return rho
+
+
+def test_drops_of_sharp_blocks_are_exact():
+    """A block of m liquid rows over L columns with a sharp step and rho_mid
+    halfway: the interface crossing is exactly r = m (the last liquid node
+    sits at m - 1/2 and rho falls by twice rho_l - rho_mid over one
+    spacing), so the volume is pi m^2 L and the centre the block's middle
+    column.  One block wraps across the periodic end."""
+    nz, nr = 40, 16
+    blocks = [(4, 5, 4), (14, 7, 2), (37, 6, 6)]  # the last covers 37..39, 0..2
+    rho = _blocks(nz, nr, blocks)
+    n, vols, cents = D.drops(rho, 1.1)
+    assert n == 3
+    # listed from the first gas column (3) onward
+    want = [(np.pi * 16 * 5, 6.0), (np.pi * 4 * 7, 17.0), (np.pi * 36 * 6, 39.5)]
+    for (v, c), (wv, wc) in zip(zip(vols, cents), want):
+        assert v == pytest.approx(wv, rel=1e-14)
+        assert c == pytest.approx(wc, abs=1e-12)
+
+
+def test_drops_of_spheres_and_degenerate_cases():
+    """Diffuse spheres of radius a on the axis have volume (4/3) pi a^3 to
+    within the midpoint sum over columns (2 %); an unbroken cylinder gives
+    n = -1 and pure gas n = 0."""
+    nz, nr, rl, rg = 200, 40, 2.0, 0.1
+    r = np.arange(nr)[:, None] + 0.5
+    z = np.arange(nz)[None, :]
+    rho = np.full((nr, nz), rg)
+    for zc, a in ((50.0, 12.0), (150.0, 8.0)):
+        d = np.sqrt(r * r + (z - zc) ** 2)
+        rho = np.maximum(rho, rg + 0.5 * (rl - rg) * (1.0 - np.tanh((d - a) / 1.5)))
+    n, vols, cents = D.drops(rho, 0.5 * (rl + rg))
+    assert n == 2
+    for v, c, (zc, a) in zip(vols, cents, ((50.0, 12.0), (150.0, 8.0))):
+        assert v == pytest.approx(4.0 / 3.0 * np.pi * a ** 3, rel=0.02)
+        assert c == pytest.approx(zc, abs=0.05)
+    cyl = np.where(r < 10.0, rl, rg) * np.ones((1, nz))
+    assert D.drops(cyl, 0.5 * (rl + rg))[0] == -1
+    assert D.drops(np.full((nr, nz), rg), 0.5 * (rl + rg))[0] == 0
