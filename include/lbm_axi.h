@@ -60,6 +60,16 @@ extern "C" {
  * derivatives in H_z, H_r are zero on the 2 rows next to the wall; the
  * other terms are unchanged.  May be combined with LBM_AXI_FLAG_GUO. */
 #define LBM_AXI_FLAG_NO_WALL_DERIV 2
+/* flags: LBM_AXI_FLAG_ZWALLS closes both ends of z with no-slip walls
+ * (mid-grid bounce-back at z = -1/2 and z = nz - 1/2, Sec. II.E; the two
+ * discs of the radial-flow test of Sec. III) instead of joining them
+ * periodically.  psi is mirrored evenly across them for the Shan–Chen sum,
+ * and, as Sec. II.E asks at the boundaries other than the axis, the
+ * derivative terms are zero where their stencils would reach across:
+ * F^{gamma,sym} on the 4 columns and the velocity derivatives of H on the 2
+ * columns next to each wall.  Requires nz >= 8.  May be combined with the
+ * other flags. */
+#define LBM_AXI_FLAG_ZWALLS 8
 
 typedef struct lbm_axi_params {
     int32_t nz;        /* nodes along z (>= 1) */
@@ -72,7 +82,8 @@ typedef struct lbm_axi_params {
     int32_t wall;      /* LBM_AXI_WALL_NOSLIP or LBM_AXI_WALL_FREESLIP */
     int32_t axisym;    /* 1: axisymmetric method; 0: plain planar Shan–Chen (test mode) */
     int32_t precision; /* LBM_AXI_FP64 or LBM_AXI_FP32_SHIFTED */
-    int32_t flags;     /* LBM_AXI_FLAG_GUO | LBM_AXI_FLAG_NO_WALL_DERIV; other bits: LBM_AXI_EUNSUP */
+    int32_t flags;     /* LBM_AXI_FLAG_GUO | LBM_AXI_FLAG_NO_WALL_DERIV | LBM_AXI_FLAG_ZWALLS; other bits:
+                          LBM_AXI_EUNSUP */
     double rho_ref;    /* shift of the FP32 storage (ignored in FP64) */
 } lbm_axi_params;
 
@@ -136,6 +147,24 @@ int lbm_axi_reduce(lbm_axi_t h, double* h_out);
  * 0 <= z_col < nz.  Synchronises the stream. */
 #define LBM_AXI_NINTERFACE 7
 int lbm_axi_interface(lbm_axi_t h, double rho_mid, int32_t z_col, double* d_radius, double* h_out);
+
+/* Open boundaries (Sec. II.E: a prescribed velocity or pressure is imposed
+ * through the equilibrium populations, before streaming).  After every
+ * collision the populations of row in_row become f^eq(rho_in, u_in(z)) with
+ * u_in(z) = (d_uz_in[z], d_ur_in[z]) (device arrays of nz doubles, copied
+ * into the workspace on the stream by this call), and those of row out_row
+ * become f^eq(rho_out, u) with u the hydrodynamic velocity of the node one
+ * row below (an open outlet at imposed pressure passes the interior velocity
+ * on).  The flow domain is the rows between them; the rows outside still
+ * step but take no part in it.  The derivative terms are zero on rows whose
+ * stencils reach past an open row: F^{gamma,sym} within 3 rows inside it,
+ * the velocity derivatives within 1 row inside it, and every row outside.
+ * in_row = out_row = -1 turns both off (the default); either may be -1
+ * alone.  -1 <= in_row < out_row < nr when both are set, out_row >= 1,
+ * rho_in, rho_out > 0.  The step runs the kernel's run-time option path
+ * while open rows are set.  Not supported by the adjoint. */
+int lbm_axi_set_open(lbm_axi_t h, int32_t in_row, double rho_in, const double* d_uz_in, const double* d_ur_in,
+                     int32_t out_row, double rho_out);
 
 /* Drops on the axis once a thread has broken up (Sec. IV.C: the thread
  * breaks into two or more drops when kappa* < 1).  A drop is a maximal run

@@ -41,18 +41,34 @@ class Params(ctypes.Structure):
         ("tau", ctypes.c_double), ("tau_im", ctypes.c_double),
         ("psi_rho0", ctypes.c_double), ("gz", ctypes.c_double),
         ("wall", ctypes.c_int32), ("axisym", ctypes.c_int32),
-        ("flags", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("flags", ctypes.c_int32), ("in_row", ctypes.c_int32),
+        ("out_row", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
+        ("uz_in", ctypes.c_void_p), ("ur_in", ctypes.c_void_p),
     ]
 
 
 FLAG_GUO = 4  # Guo forcing instead of the velocity shift (see the C source)
 FLAG_NO_WALL_DERIV = 2  # derivative terms zero on rows whose stencils cross the wall
+FLAG_ZWALLS = 8  # no-slip walls at both ends of z instead of periodic z
 
 
 def make_params(nz, nr, G=-5.5, tau=1.0, psi_rho0=1.0, gz=0.0, wall=WALL_NOSLIP, axisym=1,
-                G_im=0.0, tau_im=0.0, flags=0):
-    return Params(int(nz), int(nr), float(G), float(G_im), float(tau), float(tau_im),
-                  float(psi_rho0), float(gz), int(wall), int(axisym), int(flags), 0)
+                G_im=0.0, tau_im=0.0, flags=0, in_row=-1, out_row=-1, rho_in=1.0, rho_out=1.0,
+                uz_in=None, ur_in=None):
+    """Oracle parameters.  Open boundaries (see the C source): in_row /
+    out_row >= 0 impose f^eq(rho_in, uz_in[z], ur_in[z]) on the inlet row and
+    f^eq(rho_out, u one row inside) on the outlet row after each collision."""
+    p = Params(int(nz), int(nr), float(G), float(G_im), float(tau), float(tau_im),
+               float(psi_rho0), float(gz), int(wall), int(axisym), int(flags), int(in_row), int(out_row), 0,
+               float(rho_in), float(rho_out), None, None)
+    if in_row >= 0:
+        uz = np.ascontiguousarray(np.zeros(nz) if uz_in is None else uz_in, dtype=np.float64)
+        ur = np.ascontiguousarray(np.zeros(nz) if ur_in is None else ur_in, dtype=np.float64)
+        assert uz.shape == (nz,) and ur.shape == (nz,)
+        p.uz_in, p.ur_in = uz.ctypes.data, ur.ctypes.data
+        p._keep = (uz, ur)  # the C side reads these arrays during run()
+    return p
 
 
 _lib = None

@@ -18,7 +18,8 @@
  * complex build is the analytic continuation of the real one.
  *
  * Conventions (paper Sec. II.C and II.E):
- *   - nodes z_k = k (k = 0..nz-1, periodic) and r_j = j + 1/2 (j = 0..nr-1);
+ *   - nodes z_k = k (k = 0..nz-1, periodic unless ORACLE_FLAG_ZWALLS) and
+ *     r_j = j + 1/2 (j = 0..nr-1);
  *     the axis r = 0 lies half-way between row 0 and its mirror row -1, the
  *     outer wall r = nr half-way between row nr-1 and its mirror row nr;
  *   - populations f[i][j][k] (direction, row, column), z fastest;
@@ -64,8 +65,14 @@ typedef struct {
     double gz;            /* body acceleration along +z */
     int32_t wall;         /* 0: no-slip (mid-grid bounce-back), 1: free-slip (mid-grid specular) */
     int32_t axisym;       /* 1: axisymmetric terms on, 0: plain 2D Shan–Chen */
-    int32_t flags;        /* ORACLE_FLAG_GUO and/or ORACLE_FLAG_NO_WALL_DERIV (see below) */
+    int32_t flags;        /* ORACLE_FLAG_* bits (see below) */
+    int32_t in_row;       /* open boundaries (see below): inlet row or -1 */
+    int32_t out_row;      /* outlet row or -1 */
     int32_t pad;
+    double rho_in;        /* density imposed at the inlet */
+    double rho_out;       /* density imposed at the outlet */
+    const double* uz_in;  /* [nz] velocity imposed at the inlet, per column */
+    const double* ur_in;
 } or_params;
 
 /* Force incorporation.  Default: the Shan–Chen velocity shift the paper's
@@ -86,6 +93,28 @@ typedef struct {
  * velocity derivatives of H are zero on the 2 rows next to it. */
 #define ORACLE_FLAG_NO_WALL_DERIV 2
 
+/* Closed ends in z.  Sec. II.E imposes no-slip walls by mid-grid
+ * bounce-back; with ORACLE_FLAG_ZWALLS the two ends of the z range are such
+ * walls (at z = -1/2 and z = nz - 1/2, the two discs of the radial-flow
+ * test of Sec. III) instead of a periodic join.  Reading for the fields
+ * across them: psi is reflected evenly (for the Shan–Chen sum), and, as
+ * Sec. II.E asks at the boundaries other than the axis, the derivative
+ * terms are zero wherever their stencils would reach across: F^{gamma,sym}
+ * on the 4 columns next to each wall, the velocity derivatives of H on the
+ * 2 columns next to each wall. */
+#define ORACLE_FLAG_ZWALLS 8
+
+/* Open boundaries (Sec. II.E: a prescribed velocity or pressure is imposed
+ * through the equilibrium populations, before streaming).  With
+ * in_row >= 0 the post-collision populations of that row are replaced by
+ * f^eq(rho_in, uz_in[z], ur_in[z]); with out_row >= 0 those of that row by
+ * f^eq(rho_out, u) with u the hydrodynamic velocity of the node one row
+ * inside (reading: an open outlet at imposed pressure passes the interior
+ * velocity on).  The flow domain is the rows between them; derivative terms
+ * are zero on rows whose stencils reach past an open row (F^{gamma,sym}
+ * within 3 rows inside it, the velocity derivatives within 1 row inside it,
+ * and on every row outside). */
+
 /* order of the intermediate fields written by *_fields() */
 enum {
     FLD_RHO, FLD_JZ, FLD_JR, FLD_PSI,
@@ -103,6 +132,14 @@ enum {
 static inline int wrap(int k, int n) {
     k %= n;
     return k < 0 ? k + n : k;
+}
+
+/* column of the node a (possibly ghost) column takes its value from:
+ * periodic, or mirrored about the walls at -1/2 and nz - 1/2 */
+static inline int col_of(int k, int n, int zw) {
+    if (!zw) return wrap(k, n);
+    while (k < 0 || k >= n) k = k < 0 ? -1 - k : 2 * n - 1 - k;
+    return k;
 }
 
 static inline num get_param_G(const or_params* p) {
@@ -128,9 +165,10 @@ static int dir_of(int cz, int cr) {
     abort();
 }
 
-/* value of an extended field (rows -NG..nr+NG-1) at column z, row r */
-static inline num ext_at(const num* E, int nz, int z, int r) {
-    return E[(size_t)(r + NG) * nz + wrap(z, nz)];
+/* value of an extended field (rows -NG..nr+NG-1) at column z, row r;
+ * zw: z-walls (even mirror) instead of periodic z */
+static inline num ext_at(const num* E, int nz, int z, int r, int zw) {
+    return E[(size_t)(r + NG) * nz + col_of(z, nz, zw)];
 }
 
 /* Ghost extension of a real-row field (Sec. II.E, last sentences).
@@ -154,12 +192,12 @@ static void extend_rows(const num* src, num* E, int nz, int nr, double axis_sign
 
 /* Isotropic first derivative on D2Q9 (Sec. II.D, first stencil and its
  * z-analogue): (1/36) sum_{i=1..8} (8 phi(x+c_i) - phi(x+2c_i)) c_i,axis. */
-static num d_iso(const num* E, int nz, int z, int r, int along_r) {
+static num d_iso(const num* E, int nz, int z, int r, int along_r, int zw) {
     num s = 0.0;
     for (int i = 1; i < 9; ++i) {
         int c = along_r ? CR[i] : CZ[i];
         if (c == 0) continue;
-        num t = 8.0 * ext_at(E, nz, z + CZ[i], r + CR[i]) - ext_at(E, nz, z + 2 * CZ[i], r + 2 * CR[i]);
+        num t = 8.0 * ext_at(E, nz, z + CZ[i], r + CR[i], zw) - ext_at(E, nz, z + 2 * CZ[i], r + 2 * CR[i], zw);
         s += t * (double)c;
     }
     return s / 36.0;
@@ -167,17 +205,17 @@ static num d_iso(const num* E, int nz, int z, int r, int along_r) {
 
 /* One-dimensional fourth-order first derivative along r (Sec. II.D, last
  * stencil). */
-static num d1_r(const num* E, int nz, int z, int r) {
-    return (-ext_at(E, nz, z, r + 2) + 8.0 * ext_at(E, nz, z, r + 1) - 8.0 * ext_at(E, nz, z, r - 1) +
-            ext_at(E, nz, z, r - 2)) / 12.0;
+static num d1_r(const num* E, int nz, int z, int r, int zw) {
+    return (-ext_at(E, nz, z, r + 2, zw) + 8.0 * ext_at(E, nz, z, r + 1, zw) - 8.0 * ext_at(E, nz, z, r - 1, zw) +
+            ext_at(E, nz, z, r - 2, zw)) / 12.0;
 }
 
 /* One-dimensional fourth-order first derivative along z of a real-row field
  * (the outer difference of the mixed-derivative stencil, Sec. II.D). */
-static num d1_z(const num* F, int nz, int z, int r) {
+static num d1_z(const num* F, int nz, int z, int r, int zw) {
     const num* row = F + (size_t)r * nz;
-    return (-row[wrap(z + 2, nz)] + 8.0 * row[wrap(z + 1, nz)] - 8.0 * row[wrap(z - 1, nz)] +
-            row[wrap(z - 2, nz)]) / 12.0;
+    return (-row[col_of(z + 2, nz, zw)] + 8.0 * row[col_of(z + 1, nz, zw)] - 8.0 * row[col_of(z - 1, nz, zw)] +
+            row[col_of(z - 2, nz, zw)]) / 12.0;
 }
 
 typedef struct {
@@ -239,6 +277,7 @@ static void compute_fields(const or_params* p, const num* f, workspace* w) {
     const num G = get_param_G(p);
     const num tau = get_param_tau(p);
     const double rho0 = p->psi_rho0;
+    const int zw = (p->flags & ORACLE_FLAG_ZWALLS) != 0;
     num** F = w->fld;
 
     /* moments (appendix, Eq. hydro_var) and pseudopotential (Sec. II.A) */
@@ -264,30 +303,30 @@ static void compute_fields(const or_params* p, const num* f, workspace* w) {
     /* isotropic d_r psi on the extended rows the second derivative needs */
 #pragma omp parallel for schedule(static)
     for (int r = -4; r < nr + 4; ++r)
-        for (int z = 0; z < nz; ++z) w->DrE[(size_t)(r + NG) * nz + z] = d_iso(w->psiE, nz, z, r, 1);
+        for (int z = 0; z < nz; ++z) w->DrE[(size_t)(r + NG) * nz + z] = d_iso(w->psiE, nz, z, r, 1, zw);
 
 #pragma omp parallel for schedule(static)
     for (int r = 0; r < nr; ++r)
         for (int z = 0; z < nz; ++z) {
             size_t x = (size_t)r * nz + z;
-            F[FLD_DR][x] = ext_at(w->DrE, nz, z, r);
+            F[FLD_DR][x] = ext_at(w->DrE, nz, z, r, zw);
             /* Reading: the second radial derivative applies the isotropic
              * stencil to the isotropic d_r field; the one-dimensional d_r is
              * used only inside the mixed derivative. */
-            F[FLD_DRR][x] = d_iso(w->DrE, nz, z, r, 1);
-            F[FLD_D1R][x] = d1_r(w->psiE, nz, z, r);
+            F[FLD_DRR][x] = d_iso(w->DrE, nz, z, r, 1, zw);
+            F[FLD_D1R][x] = d1_r(w->psiE, nz, z, r, zw);
         }
 
 #pragma omp parallel for schedule(static)
     for (int r = 0; r < nr; ++r)
         for (int z = 0; z < nz; ++z) {
             size_t x = (size_t)r * nz + z;
-            F[FLD_DZR][x] = d1_z(F[FLD_D1R], nz, z, r);
+            F[FLD_DZR][x] = d1_z(F[FLD_D1R], nz, z, r, zw);
 
             /* Shan–Chen force, first neighbours (Sec. II.A, Eq. scforce) */
             num sz = 0.0, sr = 0.0;
             for (int i = 1; i < 9; ++i) {
-                num ps = ext_at(w->psiE, nz, z + CZ[i], r + CR[i]);
+                num ps = ext_at(w->psiE, nz, z + CZ[i], r + CR[i], zw);
                 sz += WT[i] * ps * (double)CZ[i];
                 sr += WT[i] * ps * (double)CR[i];
             }
@@ -298,7 +337,9 @@ static void compute_fields(const or_params* p, const num* f, workspace* w) {
             /* axisymmetric extra force (Sec. II.D, Eq. scAxisExtra), c_s^4 = 1/9 */
             double rr = r + 0.5;
             num pref = -(G / 2.0) * (CS2 * CS2) * psi;
-            const int flat = (p->flags & ORACLE_FLAG_NO_WALL_DERIV) && r >= nr - 4;
+            const int flat = ((p->flags & ORACLE_FLAG_NO_WALL_DERIV) && r >= nr - 4) ||
+                             (zw && (z < 4 || z >= nz - 4)) || (p->in_row >= 0 && r <= p->in_row + 3) ||
+                             (p->out_row >= 0 && r >= p->out_row - 3);
             if (p->axisym && !flat) {
                 F[FLD_FSYMZ][x] = pref * F[FLD_DZR][x] / rr;
                 F[FLD_FSYMR][x] = pref * (F[FLD_DRR][x] / rr - F[FLD_DR][x] / (rr * rr));
@@ -337,14 +378,17 @@ static void compute_fields(const or_params* p, const num* f, workspace* w) {
     for (int r = 0; r < nr; ++r)
         for (int z = 0; z < nz; ++z) {
             size_t x = (size_t)r * nz + z;
-            if ((p->flags & ORACLE_FLAG_NO_WALL_DERIV) && r >= nr - 2) {
+            const int flat_u = ((p->flags & ORACLE_FLAG_NO_WALL_DERIV) && r >= nr - 2) ||
+                               (zw && (z < 2 || z >= nz - 2)) || (p->in_row >= 0 && r <= p->in_row + 1) ||
+                               (p->out_row >= 0 && r >= p->out_row - 1);
+            if (flat_u) {
                 F[FLD_DRUZ][x] = 0.0;
                 F[FLD_DZUR][x] = 0.0;
                 F[FLD_DRUR][x] = 0.0;
             } else {
-                F[FLD_DRUZ][x] = d_iso(w->uzE, nz, z, r, 1);
-                F[FLD_DZUR][x] = d_iso(w->urE, nz, z, r, 0);
-                F[FLD_DRUR][x] = d_iso(w->urE, nz, z, r, 1);
+                F[FLD_DRUZ][x] = d_iso(w->uzE, nz, z, r, 1, zw);
+                F[FLD_DZUR][x] = d_iso(w->urE, nz, z, r, 0, zw);
+                F[FLD_DRUR][x] = d_iso(w->urE, nz, z, r, 1, zw);
             }
 
             num rho = F[FLD_RHO][x], uz = F[FLD_UZ][x], ur = F[FLD_UR][x];
@@ -386,13 +430,28 @@ static void compute_fields(const or_params* p, const num* f, workspace* w) {
                 w->fstar[i * n + x] = fs;
             }
         }
+
+    /* open boundaries: imposed equilibrium populations, before streaming */
+    if (p->in_row >= 0)
+        for (int z = 0; z < nz; ++z)
+            for (int i = 0; i < 9; ++i)
+                w->fstar[i * n + (size_t)p->in_row * nz + z] = feq(i, p->rho_in, p->uz_in[z], p->ur_in[z]);
+    if (p->out_row >= 0)
+        for (int z = 0; z < nz; ++z) {
+            const size_t xi = (size_t)(p->out_row - 1) * nz + z;
+            for (int i = 0; i < 9; ++i)
+                w->fstar[i * n + (size_t)p->out_row * nz + z] = feq(i, p->rho_out, F[FLD_UZ][xi], F[FLD_UR][xi]);
+        }
 }
 
 /* Streaming with the pre-streaming boundary rules (Sec. II.E): the axis is a
  * mid-grid specular reflector; the outer wall is mid-grid bounce-back
- * (no-slip) or mid-grid specular reflection (free-slip); z is periodic. */
+ * (no-slip) or mid-grid specular reflection (free-slip); z is periodic, or
+ * closed by mid-grid bounce-back walls (ORACLE_FLAG_ZWALLS), which take
+ * precedence where a link leaves through both. */
 static void stream(const or_params* p, const num* fstar, num* fout) {
     const int nz = p->nz, nr = p->nr;
+    const int zw = (p->flags & ORACLE_FLAG_ZWALLS) != 0;
     const size_t n = (size_t)nz * nr;
     /* every (node, direction) receives exactly one population, so rows can
      * be processed in parallel without write conflicts */
@@ -401,7 +460,12 @@ static void stream(const or_params* p, const num* fstar, num* fout) {
         for (int z = 0; z < nz; ++z)
             for (int i = 0; i < 9; ++i) {
                 int tz = z + CZ[i], tr = r + CR[i], d = i;
-                if (tr < 0) {
+                if (zw && (tz < 0 || tz >= nz)) {
+                    /* a disc: the population returns to its node reversed */
+                    tz = z;
+                    tr = r;
+                    d = dir_of(-CZ[i], -CR[i]);
+                } else if (tr < 0) {
                     /* crossed the axis: mirror image re-enters row 0 with the
                      * radial velocity reversed */
                     tr = 0;
@@ -424,7 +488,10 @@ static void stream(const or_params* p, const num* fstar, num* fout) {
 
 int API(check)(const or_params* p) {
     if (p->nz < 1 || p->nr < NG) return -1;
-    if ((p->flags & ~(ORACLE_FLAG_GUO | ORACLE_FLAG_NO_WALL_DERIV)) != 0) return -1;
+    if ((p->flags & ~(ORACLE_FLAG_GUO | ORACLE_FLAG_NO_WALL_DERIV | ORACLE_FLAG_ZWALLS)) != 0) return -1;
+    if (p->in_row < -1 || p->in_row >= p->nr || p->out_row < -1 || p->out_row >= p->nr) return -1;
+    if (p->in_row >= 0 && (!p->uz_in || !p->ur_in)) return -1;
+    if (p->out_row == 0 || (p->in_row >= 0 && p->out_row >= 0 && p->out_row <= p->in_row)) return -1;
     return 0;
 }
 
@@ -508,19 +575,19 @@ void API(stream)(const or_params* p, const num* fstar, num* fout) { stream(p, fs
 num API(stencil_point)(int kind, int nz, int nr, const num* E, int z, int r) {
     (void)nr;
     switch (kind) {
-        case 0: return d_iso(E, nz, z, r, 1);
-        case 1: return d_iso(E, nz, z, r, 0);
-        case 2: return d1_r(E, nz, z, r);
+        case 0: return d_iso(E, nz, z, r, 1, 0);
+        case 1: return d_iso(E, nz, z, r, 0, 0);
+        case 2: return d1_r(E, nz, z, r, 0);
         case 3: {
             num v[5];
-            for (int k = -2; k <= 2; ++k) v[k + 2] = d1_r(E, nz, z + k, r);
+            for (int k = -2; k <= 2; ++k) v[k + 2] = d1_r(E, nz, z + k, r, 0);
             return (-v[4] + 8.0 * v[3] - 8.0 * v[1] + v[0]) / 12.0;
         }
         case 4: {
             num s = 0.0;
             for (int i = 1; i < 9; ++i) {
                 if (CR[i] == 0) continue;
-                num t = 8.0 * d_iso(E, nz, z + CZ[i], r + CR[i], 1) - d_iso(E, nz, z + 2 * CZ[i], r + 2 * CR[i], 1);
+                num t = 8.0 * d_iso(E, nz, z + CZ[i], r + CR[i], 1, 0) - d_iso(E, nz, z + 2 * CZ[i], r + 2 * CR[i], 1, 0);
                 s += t * (double)CR[i];
             }
             return s / 36.0;
@@ -528,7 +595,7 @@ num API(stencil_point)(int kind, int nz, int nr, const num* E, int z, int r) {
         case 5:
         case 6: {
             num s = 0.0;
-            for (int i = 1; i < 9; ++i) s += WT[i] * ext_at(E, nz, z + CZ[i], r + CR[i]) * (double)(kind == 5 ? CZ[i] : CR[i]);
+            for (int i = 1; i < 9; ++i) s += WT[i] * ext_at(E, nz, z + CZ[i], r + CR[i], 0) * (double)(kind == 5 ? CZ[i] : CR[i]);
             return s;
         }
         default: return 0.0;

@@ -70,7 +70,7 @@ struct lbm_axi_batch {
     int precision = 0;
     int parity = 0;
     int cfg = 0, grid_per_cu = 2, order = 1;
-    int any_guo = 0;  // 1 if some instance sets an option bit (Guo forcing, wall derivatives)
+    int any_guo = 0;  // 1 if some instance sets an option bit (Guo forcing, wall derivatives, z walls)
     int n_items = 0, cus = 256;
     std::vector<lbm::BatchInstance> host_tab;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -140,6 +140,8 @@ lbm::StepArgs instance_args(lbm_axi_batch* b, int k, int parity) {
     a.rho0 = p.psi_rho0;
     a.gz = p.gz;
     a.rho_ref = b->precision == LBM_AXI_FP64 ? 0.0 : p.rho_ref;
+    a.in_row = -1;  // batch instances have no open rows
+    a.out_row = -1;
     return a;
 }
 

@@ -41,6 +41,7 @@ struct Layout {
     size_t off_partials;  // [max blocks][4] doubles
     size_t off_red;       // [4] doubles
     size_t off_iface;     // interface scratch: R(z) [nz], rho on row 0 [nz], outputs [8], drops [1 + 2 max]
+    size_t off_open;      // inlet velocity profile [2][nz] (open rows)
     size_t total;
     int cfg;              // tile shape in use
     int tiles_z, tiles_r, nblocks;
@@ -61,7 +62,8 @@ Layout layout_of(const lbm_axi_params* p, int cfg) {
     L.off_partials = L.off_b + align_up(L.state_bytes);
     L.off_red = L.off_partials + align_up((size_t)max_blocks * 4 * sizeof(double));
     L.off_iface = L.off_red + align_up(4 * sizeof(double));
-    L.total = L.off_iface + align_up((2 * (size_t)p->nz + 8 + 1 + 2 * LBM_AXI_MAX_DROPS) * sizeof(double));
+    L.off_open = L.off_iface + align_up((2 * (size_t)p->nz + 8 + 1 + 2 * LBM_AXI_MAX_DROPS) * sizeof(double));
+    L.total = L.off_open + align_up(2 * (size_t)p->nz * sizeof(double));
     return L;
 }
 
@@ -220,6 +222,8 @@ struct lbm_axi_ctx {
     Layout L;
     int cur;  // index of the buffer holding the current state
     hipStream_t stream;
+    int in_row = -1, out_row = -1;  // open rows (lbm_axi_set_open), -1: none
+    double rho_in = 1.0, rho_out = 1.0;
 };
 
 namespace {
@@ -242,6 +246,12 @@ lbm::StepArgs make_args(lbm_axi_ctx* h) {
     a.rho0 = h->p.psi_rho0;
     a.gz = h->p.gz;
     a.rho_ref = h->p.precision == LBM_AXI_FP64 ? 0.0 : h->p.rho_ref;
+    a.in_row = h->in_row;
+    a.out_row = h->out_row;
+    a.rho_bc_in = h->rho_in;
+    a.rho_bc_out = h->rho_out;
+    a.u_in = reinterpret_cast<const double*>(h->ws + h->L.off_open);
+    if (h->in_row >= 0 || h->out_row >= 0) a.opts |= 8;
     return a;
 }
 
@@ -266,16 +276,18 @@ void launch_shape(lbm_axi_ctx* h, const lbm::StepArgs& a) {
     }
 }
 
-// the options are compile-time choices of the kernel (the moments depend on
-// the wall-derivative option only)
+// the forcing and wall-reading options are compile-time choices of the
+// kernel, the boundary options (z walls, open rows) are read at run time;
+// the moments do not depend on the forcing option
 template <bool kMoments>
 int launch_tile(lbm_axi_ctx* h, const lbm::StepArgs& a) {
-    const int o = kMoments ? (a.opts & 2) : a.opts;
+    const int o = kMoments ? (a.opts & ~1) : a.opts;
     switch (o) {
         case 0: launch_shape<kMoments, 0>(h, a); break;
         case 1: launch_shape<kMoments, 1>(h, a); break;
         case 2: launch_shape<kMoments, 2>(h, a); break;
-        default: launch_shape<kMoments, 3>(h, a); break;
+        case 3: launch_shape<kMoments, 3>(h, a); break;
+        default: launch_shape<kMoments, -1>(h, a); break;
     }
     HIP_TRY(hipGetLastError(), "step kernel launch");
     return LBM_AXI_OK;
@@ -402,6 +414,31 @@ int lbm_axi_interface(lbm_axi_t h, double rho_mid, int32_t z_col, double* d_radi
     HIP_TRY(hipMemcpyAsync(h_out, d_out, LBM_AXI_NINTERFACE * sizeof(double), hipMemcpyDeviceToHost, h->stream),
             "interface copy");
     HIP_TRY(hipStreamSynchronize(h->stream), "interface synchronize");
+    return LBM_AXI_OK;
+}
+
+int lbm_axi_set_open(lbm_axi_t h, int32_t in_row, double rho_in, const double* d_uz_in, const double* d_ur_in,
+                     int32_t out_row, double rho_out) {
+    if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
+    const int nr = h->p.nr;
+    if (in_row < -1 || in_row >= nr) return fail(LBM_AXI_EINVAL, "in_row out of range (-1 .. %d)", nr - 1);
+    if (out_row < -1 || out_row >= nr) return fail(LBM_AXI_EINVAL, "out_row out of range (-1 .. %d)", nr - 1);
+    if (out_row == 0) return fail(LBM_AXI_EINVAL, "out_row must be >= 1 (it takes the velocity of the row below)");
+    if (in_row >= 0 && out_row >= 0 && out_row <= in_row) return fail(LBM_AXI_EINVAL, "out_row must lie above in_row");
+    if (in_row >= 0 && (!d_uz_in || !d_ur_in)) return fail(LBM_AXI_EINVAL, "inlet velocity profile is NULL");
+    if (in_row >= 0 && !(rho_in > 0.0 && std::isfinite(rho_in))) return fail(LBM_AXI_EINVAL, "rho_in must be > 0");
+    if (out_row >= 0 && !(rho_out > 0.0 && std::isfinite(rho_out))) return fail(LBM_AXI_EINVAL, "rho_out must be > 0");
+    if (in_row >= 0) {
+        double* prof = reinterpret_cast<double*>(h->ws + h->L.off_open);
+        const size_t bytes = (size_t)h->p.nz * sizeof(double);
+        HIP_TRY(hipMemcpyAsync(prof, d_uz_in, bytes, hipMemcpyDeviceToDevice, h->stream), "inlet profile copy");
+        HIP_TRY(hipMemcpyAsync(prof + h->p.nz, d_ur_in, bytes, hipMemcpyDeviceToDevice, h->stream),
+                "inlet profile copy");
+    }
+    h->in_row = in_row;
+    h->out_row = out_row;
+    h->rho_in = rho_in;
+    h->rho_out = rho_out;
     return LBM_AXI_OK;
 }
 

@@ -43,8 +43,12 @@ struct StepArgs {
     int big_nz;        // 1 if nz >= TZ + 6: periodic wrap needs one add/sub
     int wall;          // 0 no-slip, 1 free-slip
     int axisym;        // 1 axisymmetric terms on
-    int opts;          // option bits: 1 Guo forcing, 2 no derivative terms across the wall
+    int opts;          // option bits: 1 Guo forcing, 2 no derivative terms across the wall,
+                       // 4 no-slip walls at both ends of z, 8 open rows
     double G, tau, rho0, gz, rho_ref;
+    int in_row, out_row;    // open rows (option 8): inlet / outlet row, or -1
+    double rho_bc_in, rho_bc_out;  // densities imposed there
+    const double* u_in;      // [2][nz]: u_z then u_r imposed on the inlet row
 };
 
 // storage / compute precision of a kernel instance
@@ -145,7 +149,16 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
 // time (1: Guo forcing instead of the velocity shift; 2: the derivative terms
 // -- F^{gamma,sym} and the velocity derivatives in H -- are zero on rows
 // whose stencils reach across the outer wall), or -1: read at run time from
-// StepArgs::opts (instances of a batch).
+// StepArgs::opts (instances of a batch, and the two boundary options).
+// Boundary options (Sec. II.E; run-time only): 4 closes both ends of z with
+// mid-grid bounce-back walls at z = -1/2 and z = nz - 1/2 (psi is mirrored
+// across them, the derivative terms whose stencils reach across are zero:
+// F^{gamma,sym} on 4 columns, the velocity derivatives on 2 columns next to
+// each wall); 8 imposes f^eq(rho_in, u_in(z)) on the inlet row and
+// f^eq(rho_out, u one row inside) on the outlet row after the collision,
+// with the derivative terms zero on rows whose stencils reach past them
+// (F^{gamma,sym} within 3 rows inside, the velocity derivatives within 1,
+// and every row outside).
 template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt = 0>
 __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, const int slot) {
     using S = typename P::S;
@@ -178,7 +191,28 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     const int opts = kOpt < 0 ? a.opts : kOpt;
     const bool guo = (opts & 1) != 0;
     const bool no_wall_deriv = (opts & 2) != 0;
+    const bool zwalls = (opts & 4) != 0;
+    const bool open = (opts & 8) != 0;
     const C rho0 = C(a.rho0);
+    // column of the node a (possibly ghost) window column reads: periodic,
+    // or mirrored about the z walls (clamped for columns no real node reads)
+    auto col_of = [&](int z) {
+        if (!zwalls) return wrap_z(z, nz, big);
+        z = z < 0 ? -1 - z : z;
+        z = z >= nz ? 2 * nz - 1 - z : z;
+        z = z < 0 ? 0 : z;
+        return z >= nz ? nz - 1 : z;
+    };
+    // F^{gamma,sym} and the velocity derivatives vanish where their
+    // stencils would reach across a boundary other than the axis
+    auto no_fsym = [&](int z, int r) {
+        return (no_wall_deriv && r >= nr - 4) || (zwalls && (z < 4 || z >= nz - 4)) ||
+               (open && ((a.in_row >= 0 && r <= a.in_row + 3) || (a.out_row >= 0 && r >= a.out_row - 3)));
+    };
+    auto no_du = [&](int z, int r) {
+        return (no_wall_deriv && r >= nr - 2) || (zwalls && (z < 2 || z >= nz - 2)) ||
+               (open && ((a.in_row >= 0 && r <= a.in_row + 1) || (a.out_row >= 0 && r >= a.out_row - 1)));
+    };
     const C inv_rho0 = C(1.0 / a.rho0);
     const C rho_ref = C(a.rho_ref);
 
@@ -233,7 +267,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             }
             const bool live = idx < NRING;
             hrz[it] = live ? (hr << 16) | hz : -1;
-            const int gz = wrap_z(z0 - 6 + hz, nz, big);
+            const int gz = col_of(z0 - 6 + hz);
             const int gr = mirror_row(r0 - 6 + (live ? hr : 6), nr);
             const unsigned node = (unsigned)(gr * nz + gz);
 #pragma unroll
@@ -242,7 +276,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             const int lr = lrb + k * RSTEP;
-            const int gz = wrap_z(z0 + lz, nz, big);
+            const int gz = col_of(z0 + lz);
             const int gr = mirror_row(r0 + lr, nr);
             const unsigned node = (unsigned)(gr * nz + gz);
 #pragma unroll
@@ -294,7 +328,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         Fz = -G * psi * sz;
         Fr = -G * psi * sr;
         // F^{gamma,sym} reads psi up to 4 rows away
-        if (a.axisym && !(no_wall_deriv && r0 - 2 + uy >= nr - 4)) {
+        if (a.axisym && !no_fsym(z0 - 2 + ux, r0 - 2 + uy)) {
             const C dr1 = s_dr[dy * DZ + dx];
             const C drr = d_iso<true>(s_dr, dy, dx, DZ);
             // mixed derivative: 1D fourth-order d_z of the 1D fourth-order d_r
@@ -419,7 +453,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             C hz = C(0), hr = C(0), mass = C(0);
             if (a.axisym) {
                 // the velocity derivatives read rows up to 2 away
-                const bool zd = no_wall_deriv && gr >= nr - 2;
+                const bool zd = no_du(gz, gr);
                 const C druz = zd ? C(0) : d_iso<true>(s_uz, uy, ux, UZ);
                 const C dzur = zd ? C(0) : d_iso<false>(s_ur, uy, ux, UZ);
                 const C drur = zd ? C(0) : d_iso<true>(s_ur, uy, ux, UZ);
@@ -437,6 +471,21 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             const C qq = C(1.5) * (qz * qz + qr * qr);
             const C gpre = C(1) - C(0.5) * inv_tau;  // Guo: (1 - 1/(2 tau))
             const C uF = uz * Fz + ur * Fr;
+            // open rows: the imposed equilibrium replaces the collision
+            const bool bc = open && (gr == a.in_row || gr == a.out_row);
+            C brho = C(0), bz = C(0), br = C(0);
+            if (bc) {
+                if (gr == a.in_row) {
+                    brho = C(a.rho_bc_in);
+                    bz = C(a.u_in[gz]);
+                    br = C(a.u_in[nz + gz]);
+                } else {
+                    brho = C(a.rho_bc_out);
+                    bz = s_uz[(uy - 1) * UZ + ux];
+                    br = s_ur[(uy - 1) * UZ + ux];
+                }
+            }
+            const C bqq = C(1.5) * (bz * bz + br * br);
             const __amdgpu_buffer_rsrc_t fout = pop_rsrc(a.fout, a.state_bytes);
             // FP32 weights sum to 1 + 7.45e-9, which would bias the mass of
             // f^eq (and of h) by that fraction at every collision; in FP32 the
@@ -471,10 +520,20 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
                     feq_acc += feq;
                     h_acc += hi;
                 }
-                const C fs = f[k][i] - (f[k][i] - feq) * inv_tau + hi;
+                C fs = f[k][i] - (f[k][i] - feq) * inv_tau + hi;
+                if (bc) {
+                    const C cb = C(cz(i)) * bz + C(cr(i)) * br;
+                    const C e = w * brho * (C(1) + C(3) * cb + C(4.5) * cb * cb - bqq);
+                    fs = P::kShift ? e - w * rho_ref : e;
+                }
                 // push to the neighbour with the pre-streaming boundary rules
                 int tz = gz + cz(i), trr = gr + cr(i), d = i;
-                if (cr(i) < 0 && gr == 0) {
+                if (zwalls && (tz < 0 || tz >= nz)) {
+                    // a z wall: the population returns to its node reversed
+                    tz = gz;
+                    trr = gr;
+                    d = opposite(i);
+                } else if (cr(i) < 0 && gr == 0) {
                     trr = 0;
                     d = mirror_r(i);
                 } else if (cr(i) > 0 && gr == nr - 1) {

@@ -26,6 +26,7 @@ FP64 = 0
 FP32_SHIFTED = 1
 FLAG_GUO = 4  # Guo forcing instead of the velocity shift (include/lbm_axi.h)
 FLAG_NO_WALL_DERIV = 2  # derivative terms zero on rows whose stencils cross the wall
+FLAG_ZWALLS = 8  # no-slip walls at both ends of z (mid-grid bounce-back) instead of periodic z
 NREDUCE = 4
 NINTERFACE = 7
 MAX_DROPS = 64
@@ -67,6 +68,8 @@ def _load():
         "lbm_axi_moments": (ctypes.c_int, [vp, vp, vp, vp]),
         "lbm_axi_reduce": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double)]),
         "lbm_axi_interface": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]),
+        "lbm_axi_set_open": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_double, vp, vp, ctypes.c_int32,
+                                            ctypes.c_double]),
         "lbm_axi_drops": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
         "lbm_axi_state_bytes": (ctypes.c_size_t, [vp]),
@@ -191,6 +194,26 @@ class AxiLBM:
                                     out))
         keys = ("A", "neck", "r_max", "rho_axis_min", "rho_in", "rho_out", "dp")
         return {k: float(v) for k, v in zip(keys, out)}
+
+    def set_open(self, in_row=-1, rho_in=1.0, uz_in=None, ur_in=None, out_row=-1, rho_out=1.0):
+        """Open boundaries (include/lbm_axi.h, lbm_axi_set_open): imposed
+        f^eq(rho_in, u_in(z)) on row in_row, f^eq(rho_out, u one row inside)
+        on row out_row; -1 turns a row off.  uz_in, ur_in: float64 arrays or
+        tensors of nz values."""
+        if in_row >= 0:
+            uz = self._column(uz_in)
+            ur = self._column(ur_in)
+            self._open_keep = (uz, ur)  # alive until the stream has copied them
+        else:
+            uz = ur = None
+        check(lib.lbm_axi_set_open(self._h, int(in_row), float(rho_in), _ptr(uz), _ptr(ur), int(out_row),
+                                   float(rho_out)))
+
+    def _column(self, a):
+        t = torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
+        if tuple(t.shape) != (self.nz,):
+            raise ValueError(f"profile shape {tuple(t.shape)} != (nz,) = ({self.nz},)")
+        return t
 
     def drops(self, rho_mid, max_drops=MAX_DROPS):
         """Drops on the axis (include/lbm_axi.h, lbm_axi_drops): (n, volumes,

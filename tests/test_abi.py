@@ -35,13 +35,15 @@ def test_parameter_validation():
     assert L.workspace_bytes(good) > 2 * 9 * 64 * 32 * 8
     for field, value, msg in [("nz", 0, "nz"), ("nr", 5, "nr"), ("tau", 0.5, "tau"), ("wall", 2, "wall"),
                               ("axisym", 3, "axisym"), ("precision", 7, "precision"), ("psi_rho0", 0.0, "psi_rho0"),
-                              ("flags", 1, "flags"), ("flags", 8, "flags"), ("flags", 3, "flags")]:
+                              ("flags", 1, "flags"), ("flags", 16, "flags"), ("flags", 3, "flags")]:
         p = L.make_params(64, 32)
         setattr(p, field, value)
         assert L.workspace_bytes(p) == 0
         assert msg in L.last_error()
-    for flags in (L.FLAG_GUO, L.FLAG_NO_WALL_DERIV, L.FLAG_GUO | L.FLAG_NO_WALL_DERIV):
+    for flags in (L.FLAG_GUO, L.FLAG_NO_WALL_DERIV, L.FLAG_GUO | L.FLAG_NO_WALL_DERIV, L.FLAG_ZWALLS,
+                  L.FLAG_ZWALLS | L.FLAG_GUO | L.FLAG_NO_WALL_DERIV):
         assert L.workspace_bytes(L.make_params(64, 32, flags=flags)) == L.workspace_bytes(good)
+    assert L.workspace_bytes(L.make_params(7, 32, flags=L.FLAG_ZWALLS)) == 0 and "nz" in L.last_error()
 
 
 def test_fp32_workspace_is_half():
@@ -66,6 +68,7 @@ def test_create_rejects_bad_pointers_without_device_work():
     assert L.lib.lbm_axi_step(None, 1) == L.EINVAL
     n = ctypes.c_int32()
     assert L.lib.lbm_axi_drops(None, 1.0, 4, ctypes.byref(n), None, None) == L.EINVAL
+    assert L.lib.lbm_axi_set_open(None, 9, 1.0, None, None, 20, 1.0) == L.EINVAL
     L.lib.lbm_axi_destroy(None)
 
 

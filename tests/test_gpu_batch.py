@@ -85,6 +85,32 @@ def test_guo_forcing_batch_matches_oracle():
     b.close()
 
 
+def test_zwalls_batch_matches_oracle():
+    """Instances closed by z walls (alone and with the Guo forcing) mixed
+    with a periodic one in one batch (FP64): each against the oracle."""
+    L, B = _libs()
+    cases = [(64, 32, -5.5, 1.0, 0, L.FLAG_ZWALLS), (96, 40, -5.0, 0.9, 1, 0),
+             (70, 24, -5.5, 1.0, 1, L.FLAG_ZWALLS | L.FLAG_GUO)]
+    params, rhos, raw = [], [], []
+    for nz, nr, G, tau, wall, flags in cases:
+        rg, rl = coexistence_densities(G)
+        rho = drop_density(nz, nr, nz / 3.0, 0.3 * nr, rl, rg, 2.0)
+        params.append(L.make_params(nz, nr, G=G, tau=tau, wall=wall, flags=flags))
+        rhos.append(torch.from_numpy(rho).cuda())
+        raw.append(rho)
+    _say("z-wall batch of 3, 200 steps, vs oracle")
+    b = B.AxiBatch(params, rhos)
+    b.step(200)
+    for k, ((nz, nr, G, tau, wall, flags), rho) in enumerate(zip(cases, raw)):
+        rg_, uzg, urg = (t.cpu().numpy() for t in b.moments(k))
+        p = O.make_params(nz, nr, G=G, tau=tau, wall=wall, flags=flags)
+        ro, uzo, uro = O.moments(p, O.run(p, O.equilibrium(p, rho, 0 * rho, 0 * rho), 200))
+        err = max(np.abs(rg_ - ro).max(), np.abs(uzg - uzo).max(), np.abs(urg - uro).max())
+        _say(f"  instance {k} flags {flags} max err {err:.2e}")
+        assert err < 1e-10
+    b.close()
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_batch_bitwise_equals_per_instance_and_solo(precision):
     L, B = _libs()
