@@ -47,8 +47,11 @@ int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const doubl
  * holds lam^{t0+k} = dL/df^{t0+k}; on return it holds lam^{t0}, the same
  * values as k calls of lbm_axi_adjoint_step from the last state back to the
  * first.  d_tmp: scratch of 9 nz nr doubles (not aliasing d_lam).
- * d_grad_acc (may be NULL) accumulates dL/dG, dL/dtau over the k steps.
- * k >= 0 (0 leaves d_lam unchanged). */
+ * d_grad_acc (may be NULL) accumulates dL/dG, dL/dtau over the k steps:
+ * the per-block partial sums run over the steps in the workspace and are
+ * reduced once at the end, so these two values equal those of the single
+ * steps up to the order of the additions.  k >= 0 (0 leaves d_lam
+ * unchanged). */
 int lbm_axi_adjoint_run(const lbm_axi_params* p, const double* d_states, int32_t k, double* d_lam, double* d_tmp,
                         double* d_grad_acc, void* d_ws, size_t ws_bytes, void* hip_stream);
 

@@ -48,6 +48,7 @@ struct AdjArgs {
     const double* lam_next;  // [9][n]
     double* lam;             // [9][n]
     double* w;               // field workspace
+    int accumulate;          // 1: add the block partials of dL/dG, dL/dtau to running sums
 };
 
 // field slots inside the workspace (each n doubles)
@@ -66,6 +67,10 @@ __host__ __device__ inline size_t eslot_off(int s, long long n, long long ne) { 
 __host__ __device__ inline size_t fbar_off(long long n, long long ne) { return (size_t)S_NSLOT * n + (size_t)E_NSLOT * ne; }
 // after f-bar: per-block partial sums of dL/dG and dL/dtau ([block][2])
 __host__ __device__ inline size_t part_off(long long n, long long ne) { return fbar_off(n, ne) + 9 * (size_t)n; }
+// running per-block sums of a multi-step run, after the step partials
+__host__ __device__ inline size_t run_off(long long n, long long ne) {
+    return part_off(n, ne) + 2 * (size_t)((n + kAdjBlock - 1) / kAdjBlock);
+}
 
 __device__ __forceinline__ int wrapz(int z, int nz) {
     int w = z % nz;
@@ -486,16 +491,23 @@ __global__ void rev_psi_final(AdjArgs a) {
         __syncthreads();
     }
     if (t == 0) {
-        w[part_off(n, a.ne) + 2 * (size_t)blockIdx.x] = s[0][0];
-        w[part_off(n, a.ne) + 2 * (size_t)blockIdx.x + 1] = s[1][0];
+        // one step: this step's partials; a run: the block's running sums
+        // over its steps, in step order
+        const size_t o = (a.accumulate ? run_off(n, a.ne) : part_off(n, a.ne)) + 2 * (size_t)blockIdx.x;
+        if (a.accumulate) {
+            w[o] += s[0][0];
+            w[o + 1] += s[1][0];
+        } else {
+            w[o] = s[0][0];
+            w[o + 1] = s[1][0];
+        }
     }
 }
-// acc[0] += dL/dG, acc[1] += dL/dtau of this step: the block partials
-// summed in a fixed order
-__global__ void rev_reduce(AdjArgs a, int nparts, double* acc) {
+// acc[0] += dL/dG, acc[1] += dL/dtau: the block partials (of one step, or
+// the running sums of a run) summed in a fixed order
+__global__ void rev_reduce(const double* __restrict__ part, int nparts, double* acc) {
     __shared__ double s[2][256];
     const int t = threadIdx.x;
-    const double* part = a.w + part_off(a.n, a.ne);
     double g = 0.0, q = 0.0;
     for (int b = t; b < nparts; b += 256) {
         g += part[2 * (size_t)b];
@@ -594,25 +606,12 @@ __global__ void misfit_kernel(const double* r, const double* target, int m, doub
 
 inline int nblk(long long n) { return (int)((n + 255) / 256); }
 
-}  // namespace
-
-extern "C" {
-
-size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr) {
-    if (nz < 1 || nr < 6) return 0;
-    const long long n = (long long)nz * nr, ne = (long long)nz * (nr + 2 * NGA);
-    const size_t nparts = (size_t)((n + kAdjBlock - 1) / kAdjBlock);
-    return ((size_t)S_NSLOT * n + (size_t)E_NSLOT * ne + 9 * (size_t)n + 2 * nparts) * sizeof(double);
+__global__ void zero_kernel(double* p, long long n) {
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) p[x] = 0.0;
 }
 
-int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const double* d_lam_next, double* d_lam,
-                         double* d_grad_acc, void* d_ws, size_t ws_bytes, void* hip_stream) {
-    if (!p || !d_f || !d_lam_next || !d_lam || !d_ws) return LBM_AXI_EINVAL;
-    if (p->nz < 1 || p->nr < 6 || !(p->tau > 0.5) || !(p->psi_rho0 > 0.0)) return LBM_AXI_EINVAL;
-    if (p->wall != 0 && p->wall != 1) return LBM_AXI_EINVAL;
-    if (p->precision != LBM_AXI_FP64 || p->flags != 0) return LBM_AXI_EUNSUP;
-    if (ws_bytes < lbm_axi_adjoint_workspace_bytes(p->nz, p->nr)) return LBM_AXI_ENOMEM;
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+AdjArgs adjoint_args(const lbm_axi_params* p, void* d_ws, int accumulate) {
     AdjArgs a{};
     a.nz = p->nz;
     a.nr = p->nr;
@@ -624,12 +623,20 @@ int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const doubl
     a.gz = p->gz;
     a.wall = p->wall;
     a.axisym = p->axisym;
-    a.f = d_f;
-    a.lam_next = d_lam_next;
-    a.lam = d_lam;
     a.w = static_cast<double*>(d_ws);
+    a.accumulate = accumulate;
+    return a;
+}
+
+int nparts_of(const AdjArgs& a) { return (int)((a.n + kAdjBlock - 1) / kAdjBlock); }
+
+// the kernels of one reverse step, in order
+void launch_reverse_step(AdjArgs a, const double* f, const double* lam_next, double* lam, hipStream_t s) {
+    a.f = f;
+    a.lam_next = lam_next;
+    a.lam = lam;
     const dim3 b(kAdjBlock);
-    const int bn = (int)((a.n + kAdjBlock - 1) / kAdjBlock), be = (int)((a.ne + kAdjBlock - 1) / kAdjBlock);
+    const int bn = nparts_of(a), be = (int)((a.ne + kAdjBlock - 1) / kAdjBlock);
     hipLaunchKernelGGL(fwd_moments, dim3(be), b, 0, s, a);
     hipLaunchKernelGGL(fwd_dr, dim3(be), b, 0, s, a);
     hipLaunchKernelGGL(fwd_force, dim3(be), b, 0, s, a);
@@ -638,27 +645,65 @@ int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const doubl
     hipLaunchKernelGGL(rev_dzr, dim3(bn), b, 0, s, a);
     hipLaunchKernelGGL(rev_dr, dim3(be), b, 0, s, a);
     hipLaunchKernelGGL(rev_psi_final, dim3(bn), b, 0, s, a);
-    if (d_grad_acc) hipLaunchKernelGGL(rev_reduce, dim3(1), dim3(256), 0, s, a, bn, d_grad_acc);
+}
+
+int check_adjoint(const lbm_axi_params* p, size_t ws_bytes) {
+    if (!p) return LBM_AXI_EINVAL;
+    if (p->nz < 1 || p->nr < 6 || !(p->tau > 0.5) || !(p->psi_rho0 > 0.0)) return LBM_AXI_EINVAL;
+    if (p->wall != 0 && p->wall != 1) return LBM_AXI_EINVAL;
+    if (p->precision != LBM_AXI_FP64 || p->flags != 0) return LBM_AXI_EUNSUP;
+    if (ws_bytes < lbm_axi_adjoint_workspace_bytes(p->nz, p->nr)) return LBM_AXI_ENOMEM;
+    return LBM_AXI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr) {
+    if (nz < 1 || nr < 6) return 0;
+    const long long n = (long long)nz * nr, ne = (long long)nz * (nr + 2 * NGA);
+    const size_t nparts = (size_t)((n + kAdjBlock - 1) / kAdjBlock);
+    return ((size_t)S_NSLOT * n + (size_t)E_NSLOT * ne + 9 * (size_t)n + 4 * nparts) * sizeof(double);
+}
+
+int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const double* d_lam_next, double* d_lam,
+                         double* d_grad_acc, void* d_ws, size_t ws_bytes, void* hip_stream) {
+    if (!p || !d_f || !d_lam_next || !d_lam || !d_ws) return LBM_AXI_EINVAL;
+    const int rc = check_adjoint(p, ws_bytes);
+    if (rc != LBM_AXI_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    AdjArgs a = adjoint_args(p, d_ws, 0);
+    launch_reverse_step(a, d_f, d_lam_next, d_lam, s);
+    if (d_grad_acc)
+        hipLaunchKernelGGL(rev_reduce, dim3(1), dim3(256), 0, s, a.w + part_off(a.n, a.ne), nparts_of(a), d_grad_acc);
     return hipGetLastError() == hipSuccess ? LBM_AXI_OK : LBM_AXI_EHIP;
 }
 
 int lbm_axi_adjoint_run(const lbm_axi_params* p, const double* d_states, int32_t k, double* d_lam, double* d_tmp,
                         double* d_grad_acc, void* d_ws, size_t ws_bytes, void* hip_stream) {
-    if (!p || !d_states || !d_lam || !d_tmp || d_tmp == d_lam || k < 0) return LBM_AXI_EINVAL;
+    if (!p || !d_states || !d_lam || !d_tmp || d_tmp == d_lam || !d_ws || k < 0) return LBM_AXI_EINVAL;
+    const int rc = check_adjoint(p, ws_bytes);
+    if (rc != LBM_AXI_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const size_t n9 = 9 * (size_t)p->nz * (size_t)p->nr;
+    AdjArgs a = adjoint_args(p, d_ws, 1);
+    double* run = a.w + run_off(a.n, a.ne);
+    const int nparts = nparts_of(a);
+    // the block sums of dL/dG, dL/dtau run over the k steps and are reduced
+    // once at the end (a kernel, not a memset, clears them)
+    hipLaunchKernelGGL(zero_kernel, dim3(nblk(2 * (long long)nparts)), dim3(256), 0, s, run, 2 * (long long)nparts);
     double* cur = d_lam;  // holds lam^{t0+j+1} before step j
     double* nxt = d_tmp;
     for (int32_t j = k - 1; j >= 0; --j) {
-        const int rc = lbm_axi_adjoint_step(p, d_states + (size_t)j * n9, cur, nxt, d_grad_acc, d_ws, ws_bytes,
-                                            hip_stream);
-        if (rc != LBM_AXI_OK) return rc;
+        launch_reverse_step(a, d_states + (size_t)j * n9, cur, nxt, s);
         double* t = cur;
         cur = nxt;
         nxt = t;
     }
-    if (cur != d_lam &&
-        hipMemcpyAsync(d_lam, cur, n9 * sizeof(double), hipMemcpyDeviceToDevice, static_cast<hipStream_t>(hip_stream)) !=
-            hipSuccess)
+    if (d_grad_acc && k > 0) hipLaunchKernelGGL(rev_reduce, dim3(1), dim3(256), 0, s, run, nparts, d_grad_acc);
+    if (hipGetLastError() != hipSuccess) return LBM_AXI_EHIP;
+    if (cur != d_lam && hipMemcpyAsync(d_lam, cur, n9 * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
         return LBM_AXI_EHIP;
     return LBM_AXI_OK;
 }

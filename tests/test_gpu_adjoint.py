@@ -278,7 +278,8 @@ def test_shape_loss_gradient_full_adjoint_workload():
 def test_record_and_adjoint_run_match_single_steps():
     """lbm_axi_record writes the same states as stepping one by one, and
     lbm_axi_adjoint_run over k recorded states equals k single adjoint
-    steps, bit for bit (same kernels, same order of the G/tau sums)."""
+    steps: lam bit for bit (same kernels), the G and tau derivatives to
+    rounding (the run reduces its block sums once, not every step)."""
     L, A = _libs()
     nz, nr, G, tau, k = 48, 24, -5.5, 0.9, 7
     _say("record / adjoint_run vs single steps")
@@ -308,7 +309,9 @@ def test_record_and_adjoint_run_match_single_steps():
     lam = lam0.clone()
     A.adjoint_run(params, rec[0], k, lam, torch.empty_like(lam), acc2, ws)
     assert torch.equal(lam, cur)
-    assert torch.equal(acc1, acc2)
+    # the run sums the G and tau partials per block over its steps before
+    # reducing them: the same terms in another order
+    assert torch.allclose(acc1, acc2, rtol=1e-13, atol=0.0)
 
 
 def test_checkpointing_is_exact():
