@@ -160,7 +160,7 @@ def batch_throughput(steps=200):
     return out
 
 
-def cpu_baseline(rho, budget_s=20.0):
+def cpu_baseline(rho, budget_s=30.0):
     """The oracle as it stands, on the host cores, over whole steps of the
     same 4096 x 512 workload until about budget_s seconds have elapsed."""
     import ctypes
