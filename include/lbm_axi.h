@@ -70,6 +70,17 @@ extern "C" {
  * columns next to each wall.  Requires nz >= 8.  May be combined with the
  * other flags. */
 #define LBM_AXI_FLAG_ZWALLS 8
+/* flags: LBM_AXI_FLAG_MIDLINK selects the other reading of where the source
+ * h_i is evaluated.  Sec. II.C places it at the mid-link, mid-step point
+ * without giving its discretisation; by default it is the node value
+ * h_i(x, t).  With this flag it is the average over the link,
+ * (h_i(x) + h_i(x + c_i)) / 2, with h_i(y) = W_i (mass(y) + 3 c_i . H(y))
+ * from the fields at y (across the axis the mirror node with H_r reversed,
+ * across the outer wall the mirror node).  Each step then runs two kernels:
+ * a moments pass that writes H and the mass source of every node (3 nz nr
+ * doubles more workspace), and the step, on its run-time option path.  Not
+ * with LBM_AXI_FLAG_ZWALLS or open rows; not in a batch or the adjoint. */
+#define LBM_AXI_FLAG_MIDLINK 16
 
 typedef struct lbm_axi_params {
     int32_t nz;        /* nodes along z (>= 1) */
@@ -82,8 +93,8 @@ typedef struct lbm_axi_params {
     int32_t wall;      /* LBM_AXI_WALL_NOSLIP or LBM_AXI_WALL_FREESLIP */
     int32_t axisym;    /* 1: axisymmetric method; 0: plain planar Shan–Chen (test mode) */
     int32_t precision; /* LBM_AXI_FP64 or LBM_AXI_FP32_SHIFTED */
-    int32_t flags;     /* LBM_AXI_FLAG_GUO | LBM_AXI_FLAG_NO_WALL_DERIV | LBM_AXI_FLAG_ZWALLS; other bits:
-                          LBM_AXI_EUNSUP */
+    int32_t flags;     /* LBM_AXI_FLAG_GUO | LBM_AXI_FLAG_NO_WALL_DERIV | LBM_AXI_FLAG_ZWALLS |
+                          LBM_AXI_FLAG_MIDLINK; other bits: LBM_AXI_EUNSUP */
     double rho_ref;    /* shift of the FP32 storage (ignored in FP64) */
 } lbm_axi_params;
 

@@ -51,6 +51,7 @@ class Params(ctypes.Structure):
 FLAG_GUO = 4  # Guo forcing instead of the velocity shift (see the C source)
 FLAG_NO_WALL_DERIV = 2  # derivative terms zero on rows whose stencils cross the wall
 FLAG_ZWALLS = 8  # no-slip walls at both ends of z instead of periodic z
+FLAG_MIDLINK = 16  # source h_i averaged over the two ends of each link (see the C source)
 
 
 def make_params(nz, nr, G=-5.5, tau=1.0, psi_rho0=1.0, gz=0.0, wall=WALL_NOSLIP, axisym=1,

@@ -104,6 +104,17 @@ typedef struct {
  * 2 columns next to each wall. */
 #define ORACLE_FLAG_ZWALLS 8
 
+/* Source term position.  Sec. II.C places h_i at the mid-link point
+ * (x + c_i/2, t + 1/2) without saying how it is evaluated; the default
+ * reading takes the node value h_i(x, t).  ORACLE_FLAG_MIDLINK takes the
+ * average of the two ends of the link, (h_i(x) + h_i(x + c_i)) / 2, with
+ * h_i(y) = W_i (mass(y) + 3 c_i . H(y)) from the fields at y.  Across the
+ * axis y is the mirror node with H_r reversed (H_z and the mass source are
+ * even there, H_r odd); across the outer wall the mirror node's values are
+ * used as they are (every field is even there).  Periodic z and no open
+ * rows only. */
+#define ORACLE_FLAG_MIDLINK 16
+
 /* Open boundaries (Sec. II.E: a prescribed velocity or pressure is imposed
  * through the equilibrium populations, before streaming).  With
  * in_row >= 0 the post-collision populations of that row are replaced by
@@ -409,14 +420,39 @@ static void compute_fields(const or_params* p, const num* f, workspace* w) {
 
             /* source h_i evaluated at the node and current time.  Reading: the
              * paper places h_i at the mid-link, mid-step point without giving
-             * its discretisation; the explicit node value is used. */
+             * its discretisation; the explicit node value is used (the
+             * mid-link average is the ORACLE_FLAG_MIDLINK option). */
+            for (int i = 0; i < 9; ++i) w->h[i * n + x] = WT[i] * (mass + (CZ[i] * hz + CR[i] * hr) / CS2);
+        }
+
+    const int midlink = (p->flags & ORACLE_FLAG_MIDLINK) != 0;
+#pragma omp parallel for schedule(static)
+    for (int r = 0; r < nr; ++r)
+        for (int z = 0; z < nz; ++z) {
+            size_t x = (size_t)r * nz + z;
+            num rho = F[FLD_RHO][x], uz = F[FLD_UZ][x], ur = F[FLD_UR][x];
             num uqz = F[FLD_UEQZ][x], uqr = F[FLD_UEQR][x];
             num inv_tau = 1.0 / tau;
             const int guo = (p->flags & ORACLE_FLAG_GUO) != 0;
             num Fz = F[FLD_FZ][x], Fr = F[FLD_FR][x];
             for (int i = 0; i < 9; ++i) {
-                num hi = WT[i] * (mass + (CZ[i] * hz + CR[i] * hr) / CS2);
-                w->h[i * n + x] = hi;
+                num hi = w->h[i * n + x];
+                if (midlink && i > 0) {
+                    /* h_i at the other end of the link, from that node's fields */
+                    int yr = r + CR[i];
+                    double sr = 1.0;  /* sign of H_r there */
+                    if (yr < 0) {
+                        yr = -1 - yr;
+                        sr = -1.0;
+                    } else if (yr >= nr) {
+                        yr = 2 * nr - 1 - yr;
+                    }
+                    const size_t y = (size_t)yr * nz + wrap(z + CZ[i], nz);
+                    num my = 0.0;
+                    if (p->axisym) my = -F[FLD_RHO][y] * F[FLD_UR][y] / (yr + 0.5);
+                    num hy = WT[i] * (my + (CZ[i] * F[FLD_HZ][y] + CR[i] * sr * F[FLD_HR][y]) / CS2);
+                    hi = 0.5 * (hi + hy);
+                }
                 num fi = f[i * n + x];
                 /* BGK collision plus source (Eq. lbm2d_mod_new) */
                 num fs = fi - (fi - feq(i, rho, uqz, uqr)) * inv_tau + hi;
@@ -488,7 +524,10 @@ static void stream(const or_params* p, const num* fstar, num* fout) {
 
 int API(check)(const or_params* p) {
     if (p->nz < 1 || p->nr < NG) return -1;
-    if ((p->flags & ~(ORACLE_FLAG_GUO | ORACLE_FLAG_NO_WALL_DERIV | ORACLE_FLAG_ZWALLS)) != 0) return -1;
+    if ((p->flags & ~(ORACLE_FLAG_GUO | ORACLE_FLAG_NO_WALL_DERIV | ORACLE_FLAG_ZWALLS | ORACLE_FLAG_MIDLINK)) != 0)
+        return -1;
+    if ((p->flags & ORACLE_FLAG_MIDLINK) && ((p->flags & ORACLE_FLAG_ZWALLS) || p->in_row >= 0 || p->out_row >= 0))
+        return -1;
     if (p->in_row < -1 || p->in_row >= p->nr || p->out_row < -1 || p->out_row >= p->nr) return -1;
     if (p->in_row >= 0 && (!p->uz_in || !p->ur_in)) return -1;
     if (p->out_row == 0 || (p->in_row >= 0 && p->out_row >= 0 && p->out_row <= p->in_row)) return -1;

@@ -116,6 +116,8 @@ int check_all(const lbm_axi_params* ps, int32_t n) {
         int rc = check_params(&ps[k]);
         if (rc != LBM_AXI_OK) return fail(rc, "instance %d: %s", k, g_last_error.c_str());
         if (ps[k].precision != ps[0].precision) return fail(LBM_AXI_EINVAL, "instance %d: precisions differ", k);
+        if (ps[k].flags & LBM_AXI_FLAG_MIDLINK)
+            return fail(LBM_AXI_EUNSUP, "instance %d: LBM_AXI_FLAG_MIDLINK is not supported in a batch", k);
     }
     return LBM_AXI_OK;
 }

@@ -59,11 +59,14 @@ inline int check_params(const lbm_axi_params* p) {
     if (p->axisym != 0 && p->axisym != 1) return fail(LBM_AXI_EINVAL, "axisym must be 0 or 1");
     if (p->precision != LBM_AXI_FP64 && p->precision != LBM_AXI_FP32_SHIFTED)
         return fail(LBM_AXI_EINVAL, "precision must be 0 (FP64) or 1 (FP32 shifted)");
-    if ((p->flags & ~(LBM_AXI_FLAG_GUO | LBM_AXI_FLAG_NO_WALL_DERIV | LBM_AXI_FLAG_ZWALLS)) != 0)
+    if ((p->flags & ~(LBM_AXI_FLAG_GUO | LBM_AXI_FLAG_NO_WALL_DERIV | LBM_AXI_FLAG_ZWALLS | LBM_AXI_FLAG_MIDLINK)) !=
+        0)
         return fail(LBM_AXI_EUNSUP,
-                    "flags may combine LBM_AXI_FLAG_GUO, LBM_AXI_FLAG_NO_WALL_DERIV and LBM_AXI_FLAG_ZWALLS only "
-                    "(got %d)",
+                    "flags may combine LBM_AXI_FLAG_GUO, LBM_AXI_FLAG_NO_WALL_DERIV, LBM_AXI_FLAG_ZWALLS and "
+                    "LBM_AXI_FLAG_MIDLINK only (got %d)",
                     p->flags);
+    if ((p->flags & LBM_AXI_FLAG_MIDLINK) && (p->flags & LBM_AXI_FLAG_ZWALLS))
+        return fail(LBM_AXI_EUNSUP, "LBM_AXI_FLAG_MIDLINK does not combine with LBM_AXI_FLAG_ZWALLS");
     if ((p->flags & LBM_AXI_FLAG_ZWALLS) && p->nz < 8)
         return fail(LBM_AXI_EINVAL, "nz must be >= 8 with LBM_AXI_FLAG_ZWALLS (got %d)", p->nz);
     if (!std::isfinite(p->rho_ref)) return fail(LBM_AXI_EINVAL, "rho_ref must be finite");
@@ -71,11 +74,11 @@ inline int check_params(const lbm_axi_params* p) {
 }
 
 // kernel option bits of a validated flags field (1 Guo forcing, 2 no
-// derivative terms across the wall, 4 z walls; 8, open rows, is set by
-// lbm_axi_set_open)
+// derivative terms across the wall, 4 z walls, 16 mid-link source; 8, open
+// rows, is set by lbm_axi_set_open)
 inline int option_bits(int flags) {
     return ((flags & LBM_AXI_FLAG_GUO) ? 1 : 0) | ((flags & LBM_AXI_FLAG_NO_WALL_DERIV) ? 2 : 0) |
-           ((flags & LBM_AXI_FLAG_ZWALLS) ? 4 : 0);
+           ((flags & LBM_AXI_FLAG_ZWALLS) ? 4 : 0) | ((flags & LBM_AXI_FLAG_MIDLINK) ? 16 : 0);
 }
 
 // f_i = f^eq_i(rho, u) with u^eq = u (initial state, no force shift)

@@ -42,6 +42,7 @@ struct Layout {
     size_t off_red;       // [4] doubles
     size_t off_iface;     // interface scratch: R(z) [nz], rho on row 0 [nz], outputs [8], drops [1 + 2 max]
     size_t off_open;      // inlet velocity profile [2][nz] (open rows)
+    size_t off_h;         // H_z, H_r, mass source [3][n] (mid-link source option only)
     size_t total;
     int cfg;              // tile shape in use
     int tiles_z, tiles_r, nblocks;
@@ -63,7 +64,8 @@ Layout layout_of(const lbm_axi_params* p, int cfg) {
     L.off_red = L.off_partials + align_up((size_t)max_blocks * 4 * sizeof(double));
     L.off_iface = L.off_red + align_up(4 * sizeof(double));
     L.off_open = L.off_iface + align_up((2 * (size_t)p->nz + 8 + 1 + 2 * LBM_AXI_MAX_DROPS) * sizeof(double));
-    L.total = L.off_open + align_up(2 * (size_t)p->nz * sizeof(double));
+    L.off_h = L.off_open + align_up(2 * (size_t)p->nz * sizeof(double));
+    L.total = L.off_h + ((p->flags & LBM_AXI_FLAG_MIDLINK) ? align_up(3 * n * sizeof(double)) : 0);
     return L;
 }
 
@@ -252,6 +254,7 @@ lbm::StepArgs make_args(lbm_axi_ctx* h) {
     a.rho_bc_out = h->rho_out;
     a.u_in = reinterpret_cast<const double*>(h->ws + h->L.off_open);
     if (h->in_row >= 0 || h->out_row >= 0) a.opts |= 8;
+    a.h_in = reinterpret_cast<const double*>(h->ws + h->L.off_h);
     return a;
 }
 
@@ -345,9 +348,17 @@ int lbm_axi_step(lbm_axi_t h, int64_t n) {
     if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
     if (n < 0) return fail(LBM_AXI_EINVAL, "n must be >= 0");
     lbm::StepArgs a = make_args(h);
+    const bool midlink = (a.opts & 16) != 0;
     for (int64_t s = 0; s < n; ++s) {
         a.fin = state_ptr(h, h->cur);
         a.fout = state_ptr(h, 1 - h->cur);
+        if (midlink) {
+            // the fields h_i is formed from, at every node, before the step
+            lbm::StepArgs m = a;
+            m.h_out = reinterpret_cast<double*>(h->ws + h->L.off_h);
+            int rc = launch_tile<true>(h, m);
+            if (rc != LBM_AXI_OK) return rc;
+        }
         int rc = launch_tile<false>(h, a);
         if (rc != LBM_AXI_OK) return rc;
         h->cur = 1 - h->cur;
@@ -426,6 +437,8 @@ int lbm_axi_set_open(lbm_axi_t h, int32_t in_row, double rho_in, const double* d
     if (out_row == 0) return fail(LBM_AXI_EINVAL, "out_row must be >= 1 (it takes the velocity of the row below)");
     if (in_row >= 0 && out_row >= 0 && out_row <= in_row) return fail(LBM_AXI_EINVAL, "out_row must lie above in_row");
     if (in_row >= 0 && (!d_uz_in || !d_ur_in)) return fail(LBM_AXI_EINVAL, "inlet velocity profile is NULL");
+    if ((in_row >= 0 || out_row >= 0) && (h->p.flags & LBM_AXI_FLAG_MIDLINK))
+        return fail(LBM_AXI_EUNSUP, "open rows do not combine with LBM_AXI_FLAG_MIDLINK");
     if (in_row >= 0 && !(rho_in > 0.0 && std::isfinite(rho_in))) return fail(LBM_AXI_EINVAL, "rho_in must be > 0");
     if (out_row >= 0 && !(rho_out > 0.0 && std::isfinite(rho_out))) return fail(LBM_AXI_EINVAL, "rho_out must be > 0");
     if (in_row >= 0) {

@@ -44,11 +44,13 @@ struct StepArgs {
     int wall;          // 0 no-slip, 1 free-slip
     int axisym;        // 1 axisymmetric terms on
     int opts;          // option bits: 1 Guo forcing, 2 no derivative terms across the wall,
-                       // 4 no-slip walls at both ends of z, 8 open rows
+                       // 4 no-slip walls at both ends of z, 8 open rows, 16 mid-link source
     double G, tau, rho0, gz, rho_ref;
     int in_row, out_row;    // open rows (option 8): inlet / outlet row, or -1
     double rho_bc_in, rho_bc_out;  // densities imposed there
     const double* u_in;      // [2][nz]: u_z then u_r imposed on the inlet row
+    double* h_out;           // moments mode: [3][n] H_z, H_r, mass source of every node, may be null
+    const double* h_in;      // option 16: the same fields, read at the far end of each link
 };
 
 // storage / compute precision of a kernel instance
@@ -158,7 +160,11 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
 // f^eq(rho_out, u one row inside) on the outlet row after the collision,
 // with the derivative terms zero on rows whose stencils reach past them
 // (F^{gamma,sym} within 3 rows inside, the velocity derivatives within 1,
-// and every row outside).
+// and every row outside).  Option 16 (run-time only): the source of each
+// link is the average of h_i at its two ends, (h_i(x) + h_i(x + c_i)) / 2,
+// with h_i(y) = W_i (mass(y) + 3 c_i . H(y)) from StepArgs::h_in (written by
+// a moments pass with h_out); across the axis y is the mirror node with H_r
+// reversed, across the outer wall the mirror node.
 template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt = 0>
 __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, const int slot) {
     using S = typename P::S;
@@ -193,6 +199,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     const bool no_wall_deriv = (opts & 2) != 0;
     const bool zwalls = (opts & 4) != 0;
     const bool open = (opts & 8) != 0;
+    const bool midlink = (opts & 16) != 0;
     const C rho0 = C(a.rho0);
     // column of the node a (possibly ghost) window column reads: periodic,
     // or mirrored about the z walls (clamped for columns no real node reads)
@@ -438,11 +445,31 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         const C uz = s_uz[uy * UZ + ux], ur = s_ur[uy * UZ + ux];
         const C rr = C(gr) + C(0.5);
 
+        // H and the mass source of the node (Eqs. H_terms, condition_h)
+        C hz = C(0), hr = C(0), mass = C(0);
+        if (a.axisym && (!kMoments || a.h_out)) {
+            // the velocity derivatives read rows up to 2 away
+            const bool zd = no_du(gz, gr);
+            const C druz = zd ? C(0) : d_iso<true>(s_uz, uy, ux, UZ);
+            const C dzur = zd ? C(0) : d_iso<false>(s_ur, uy, ux, UZ);
+            const C drur = zd ? C(0) : d_iso<true>(s_ur, uy, ux, UZ);
+            const C inv_r = dev_rcp(rr);
+            const C mu = rho * mu_fac;
+            hz = (mu * (druz + dzur) - rho * ur * uz) * inv_r;
+            hr = (C(2) * mu * (drur - ur * inv_r) - rho * ur * ur) * inv_r;
+            mass = -rho * ur * inv_r;
+        }
+
         if constexpr (kMoments) {
             const long long x = (long long)gr * nz + gz;
             if (a.rho_out) a.rho_out[x] = double(rho);
             if (a.uz_out) a.uz_out[x] = double(uz);
             if (a.ur_out) a.ur_out[x] = double(ur);
+            if (a.h_out) {
+                a.h_out[x] = double(hz);
+                a.h_out[a.plane + x] = double(hr);
+                a.h_out[2 * a.plane + x] = double(mass);
+            }
             const double two_pi_r = 6.283185307179586 * double(rr);
             part[0] += two_pi_r * double(rho);
             part[1] += two_pi_r * double(rho) * double(uz);
@@ -450,19 +477,6 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             part[3] += double(rho);
         } else {
             const C Fz = Fz_t[k], Fr = Fr_t[k];
-            C hz = C(0), hr = C(0), mass = C(0);
-            if (a.axisym) {
-                // the velocity derivatives read rows up to 2 away
-                const bool zd = no_du(gz, gr);
-                const C druz = zd ? C(0) : d_iso<true>(s_uz, uy, ux, UZ);
-                const C dzur = zd ? C(0) : d_iso<false>(s_ur, uy, ux, UZ);
-                const C drur = zd ? C(0) : d_iso<true>(s_ur, uy, ux, UZ);
-                const C inv_r = dev_rcp(rr);
-                const C mu = rho * mu_fac;
-                hz = (mu * (druz + dzur) - rho * ur * uz) * inv_r;
-                hr = (C(2) * mu * (drur - ur * inv_r) - rho * ur * ur) * inv_r;
-                mass = -rho * ur * inv_r;
-            }
             const C inv_rho = dev_rcp(rho);
             // equilibrium velocity: shifted by tau F (Eq. ueq), or the
             // hydrodynamic velocity with Guo forcing
@@ -498,7 +512,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             for (int ii = 0; ii < kQ; ++ii) {
                 const int i = kRem ? (ii + 1) % kQ : ii;
                 const C w = C(weight(i));
-                C feq, hi;
+                C feq, hi, hsrc = C(0);
                 if (kRem && i == 0) {
                     // the Guo term carries no mass either: its rest part is
                     // minus the sum of the others
@@ -510,7 +524,8 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
                     // f^eq(rho, u^eq) (Eq. e_distribution with u^eq
                     // throughout); in shifted storage, f^eq - W rho_ref
                     feq = P::kShift ? w * (sig + rho * poly) : w * rho * (C(1) + poly);
-                    hi = w * (mass + C(3) * (C(cz(i)) * hz + C(cr(i)) * hr));
+                    hsrc = w * (mass + C(3) * (C(cz(i)) * hz + C(cr(i)) * hr));
+                    hi = hsrc;
                     if (guo) {
                         // Guo et al.: W_i [3 (c_i - u) + 9 (c_i . u) c_i] . F
                         const C cF = C(cz(i)) * Fz + C(cr(i)) * Fr;
@@ -519,6 +534,23 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
                     }
                     feq_acc += feq;
                     h_acc += hi;
+                }
+                    if (midlink && i != 0) {
+                    // the source at the far end of the link, from that node's fields
+                    int yr = gr + cr(i);
+                    C sr = C(1);  // H_r is odd across the axis
+                    if (yr < 0) {
+                        yr = -1 - yr;
+                        sr = C(-1);
+                    } else if (yr >= nr) {
+                        yr = 2 * nr - 1 - yr;
+                    }
+                    int yz = gz + cz(i);
+                    yz = yz < 0 ? yz + nz : (yz >= nz ? yz - nz : yz);
+                    const long long y = (long long)yr * nz + yz;
+                    const C hy = w * (C(a.h_in[2 * a.plane + y]) +
+                                      C(3) * (C(cz(i)) * C(a.h_in[y]) + C(cr(i)) * sr * C(a.h_in[a.plane + y])));
+                    hi += C(0.5) * (hy - hsrc);  // the source part only: (h_i(x) + h_i(y)) / 2
                 }
                 C fs = f[k][i] - (f[k][i] - feq) * inv_tau + hi;
                 if (bc) {

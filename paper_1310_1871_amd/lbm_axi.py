@@ -27,6 +27,7 @@ FP32_SHIFTED = 1
 FLAG_GUO = 4  # Guo forcing instead of the velocity shift (include/lbm_axi.h)
 FLAG_NO_WALL_DERIV = 2  # derivative terms zero on rows whose stencils cross the wall
 FLAG_ZWALLS = 8  # no-slip walls at both ends of z (mid-grid bounce-back) instead of periodic z
+FLAG_MIDLINK = 16  # source h_i averaged over each link instead of the node value
 NREDUCE = 4
 NINTERFACE = 7
 MAX_DROPS = 64

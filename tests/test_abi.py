@@ -35,7 +35,7 @@ def test_parameter_validation():
     assert L.workspace_bytes(good) > 2 * 9 * 64 * 32 * 8
     for field, value, msg in [("nz", 0, "nz"), ("nr", 5, "nr"), ("tau", 0.5, "tau"), ("wall", 2, "wall"),
                               ("axisym", 3, "axisym"), ("precision", 7, "precision"), ("psi_rho0", 0.0, "psi_rho0"),
-                              ("flags", 1, "flags"), ("flags", 16, "flags"), ("flags", 3, "flags")]:
+                              ("flags", 1, "flags"), ("flags", 32, "flags"), ("flags", 3, "flags")]:
         p = L.make_params(64, 32)
         setattr(p, field, value)
         assert L.workspace_bytes(p) == 0
@@ -44,6 +44,11 @@ def test_parameter_validation():
                   L.FLAG_ZWALLS | L.FLAG_GUO | L.FLAG_NO_WALL_DERIV):
         assert L.workspace_bytes(L.make_params(64, 32, flags=flags)) == L.workspace_bytes(good)
     assert L.workspace_bytes(L.make_params(7, 32, flags=L.FLAG_ZWALLS)) == 0 and "nz" in L.last_error()
+    # the mid-link source needs 3 nz nr doubles more, and no closed z ends
+    extra = L.workspace_bytes(L.make_params(64, 32, flags=L.FLAG_MIDLINK)) - L.workspace_bytes(good)
+    assert 3 * 64 * 32 * 8 <= extra < 3 * 64 * 32 * 8 + 512
+    assert L.workspace_bytes(L.make_params(64, 32, flags=L.FLAG_MIDLINK | L.FLAG_ZWALLS)) == 0
+    assert "MIDLINK" in L.last_error()
 
 
 def test_fp32_workspace_is_half():
@@ -104,3 +109,11 @@ def test_ray_weights_host_builder_matches_oracle():
         small = (i32 * 1)()
         assert lib.lbm_axi_ray_weights(nz, nr, dbl(zc), tha, 16, dbl(0.5), dbl(s_max), 1, rp, small, val, npt,
                                        nodes, nrow, nval, ctypes.byref(nnz), ctypes.byref(nn)) == L.ENOMEM
+
+
+def test_batch_rejects_midlink_source():
+    from paper_1310_1871_amd import batch as B
+    from paper_1310_1871_amd import lbm_axi as L
+    ps = (L.Params * 2)(L.make_params(64, 32), L.make_params(64, 32, flags=L.FLAG_MIDLINK))
+    assert B._lib.lbm_axi_batch_workspace_bytes(ps, 2) == 0
+    assert "MIDLINK" in L.last_error()

@@ -86,6 +86,28 @@ def test_wall_derivative_option_large_tiles():
     _compare(nz, nr, rho, 4, G=-5.0, tau=0.9, wall=0, uz=uz, ur=ur, flags=2)
 
 
+@pytest.mark.parametrize("flags", [16, 16 | 4, 16 | 2])
+@pytest.mark.parametrize("wall", [0, 1])
+def test_midlink_source_static_drop(wall, flags):
+    """The mid-link reading of the source (flag 16: a moments pass writes H
+    and the mass source, the step averages h_i over each link), alone, with
+    Guo forcing and with the wall-derivative reading: 500 steps."""
+    from lbm_inputs import drop_density
+    rg, rl = coexistence_densities(-5.0)
+    rho = drop_density(64, 24, 32.0, 14.0, rl, rg, 2.0, {2: 1.5})
+    _compare(64, 24, rho, 500, G=-5.0, tau=0.9, wall=wall, flags=flags)
+
+
+def test_midlink_source_ragged_fields_and_large_tiles():
+    """Flag 16 with random fields and a body force on a ragged small-tile
+    grid (200 steps), and on the 64 x 32 tile shape (ragged 4100 x 515, 3
+    steps)."""
+    rho, uz, ur = random_state_fields(1616, 100, 37, rho_lo=0.5, rho_hi=1.5, u_amp=0.01)
+    _compare(100, 37, rho, 200, G=-4.0, tau=0.8, wall=0, gz=1e-5, uz=uz, ur=ur, flags=16)
+    rho, uz, ur = random_state_fields(4100517, 4100, 515, rho_lo=0.3, rho_hi=2.0, u_amp=0.01)
+    _compare(4100, 515, rho, 3, G=-5.0, tau=0.9, wall=1, uz=uz, ur=ur, flags=16)
+
+
 def test_oscillating_drop_shape_1000_steps():
     """Drop oscillation lattice 256 x 128 (P2 perturbation, seeded noise),
     tau = 0.8 (the lowest tau of that workload the scheme keeps stable)."""

@@ -1,0 +1,52 @@
+"""Pins of the oracle's mid-link source option (the other reading of where
+h_i is evaluated, Sec. II.C): (h_i(x) + h_i(x + c_i)) / 2 in place of the
+node value h_i(x)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from lbm_inputs import coexistence_densities, drop_density, node_coords
+
+
+def test_planar_mode_is_unchanged():
+    """Without the axisymmetric terms H and the mass source vanish, so both
+    readings run the same scheme bit for bit."""
+    G = -5.5
+    rg, rl = coexistence_densities(G)
+    rho = drop_density(64, 32, 32.0, 10.0, rl, rg)
+    z0 = np.zeros_like(rho)
+    pa = O.make_params(64, 32, G=G, tau=1.0, axisym=0)
+    pb = O.make_params(64, 32, G=G, tau=1.0, axisym=0, flags=O.FLAG_MIDLINK)
+    assert np.array_equal(O.run(pa, O.equilibrium(pa, rho, z0, z0), 200), O.run(pb, O.equilibrium(pb, rho, z0, z0), 200))
+
+
+def test_rest_state_is_invariant():
+    """A uniform fluid at rest has no source at either end of any link."""
+    p = O.make_params(16, 12, G=0.0, tau=0.8, flags=O.FLAG_MIDLINK)
+    one = np.ones((12, 16))
+    f0 = O.equilibrium(p, one, 0 * one, 0 * one)
+    assert np.abs(O.run(p, f0, 50) - f0).max() < 1e-15
+
+
+def test_hagen_poiseuille_with_midlink_source(golden):
+    """Sec. III.A pipe flow under the mid-link reading: U1 within 0.5 % of
+    the printed 3.84e-3 (0.13 %; the node reading gives 0.16 %), the profile
+    within 2 % of U1 of the parabola, and a radial velocity below 1e-3 U1."""
+    hp = golden["hagen_poiseuille"]
+    nz, nr = hp["nz"], hp["nr"]
+    p = O.make_params(nz, nr, G=0.0, tau=hp["tau"], gz=hp["g"], wall=0, axisym=1, flags=O.FLAG_MIDLINK)
+    one = np.ones((nr, nz))
+    _, uz, ur = O.moments(p, O.run(p, O.equilibrium(p, one, 0 * one, 0 * one), 20000))
+    _, r = node_coords(nz, nr)
+    U1 = hp["U1"]
+    assert np.polyfit(r[:4, 0] ** 2, uz[:4, 0], 1)[1] == pytest.approx(U1, rel=0.005)
+    assert np.abs(uz - U1 * (1.0 - r ** 2 / nr ** 2)).max() < 0.02 * U1
+    assert np.abs(ur).max() < 1e-3 * U1
+
+
+def test_midlink_rejects_closed_ends_and_open_rows():
+    one = np.ones((12, 16))
+    for kw in (dict(flags=O.FLAG_MIDLINK | O.FLAG_ZWALLS), dict(flags=O.FLAG_MIDLINK, out_row=10)):
+        p = O.make_params(16, 12, G=0.0, **kw)
+        with pytest.raises(ValueError):
+            O.run(p, O.equilibrium(p, one, 0 * one, 0 * one), 1)

@@ -172,13 +172,15 @@ def test_laplace_law(golden):
 
 
 @pytest.mark.slow
-def test_drop_oscillation_frequency(golden):
+@pytest.mark.parametrize("flags", [0, O.FLAG_MIDLINK])
+def test_drop_oscillation_frequency(golden, flags):
     """Sec. IV.B: an ellipsoidal drop (G = -6, rho 2.65/0.075, tau = 1,
     free-slip wall) oscillates in the l = 2 mode; A(t) fitted with
     g(t) = R_D + a exp(-b t) sin(w t + d) gives w close to Miller and
     Scriven's w_2 (Eq. freq-drop-miller) with the measured surface tension.
     The paper reports ~1%; this reading gives 2-4% on the small 160 x 80
-    lattice used here, and the tolerance is set to 6%.  The paper gives no
+    lattice used here (-2.4 % with the node source, -2.3 % with the
+    mid-link source), and the tolerance is set to 6%.  The paper gives no
     damping figure; the fitted rate is only checked to be of the size of
     Lamb's (l-1)(2l+1) nu / R^2 (within 25%)."""
     G, tau = -6.0, 1.0
@@ -190,7 +192,7 @@ def test_drop_oscillation_frequency(golden):
     req = (Ra * Rb * Rb) ** (1.0 / 3.0)
     s = np.sqrt(((z - nz / 2) / Ra) ** 2 + (r / Rb) ** 2)
     rho = tanh_profile(s * req, req, rl, rg, 2.0)
-    p = O.make_params(nz, nr, G=G, tau=tau, wall=1, axisym=1)
+    p = O.make_params(nz, nr, G=G, tau=tau, wall=1, axisym=1, flags=flags)
     f = O.equilibrium(p, rho, 0 * rho, 0 * rho)
     ts, A = [], []
     for k in range(250):
