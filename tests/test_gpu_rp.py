@@ -9,6 +9,7 @@ free-slip top, periodic z) with R = 60, so kappa* runs from 0.65 down to
 import math
 
 import numpy as np
+from scipy.special import i0, i1
 import pytest
 import torch
 
@@ -110,7 +111,7 @@ def _run_rp(lam, max_steps, check_every=500):
         if brk is None and d["rho_axis_min"] < mid:
             brk = step
             v_before = recs[-1][2]
-        recs.append((d["neck"], d["r_max"], vol))
+        recs.append((d["neck"], d["r_max"], vol, step))
         if brk is not None and step >= brk + 3000:
             break
     n, vols, cents = sim.drops(mid)
@@ -130,22 +131,44 @@ def test_rayleigh_plateau_criterion_and_drops():
     into the gas (about 0.3 % of its volume per 1000 steps before break-up,
     faster from the small drops after it), since at tau = 1 the coexistence
     densities differ slightly from the inputs'.  No drop exceeds the radius
-    of one drop holding the thread's volume.  On the stable
+    of one drop holding the thread's volume.
+
+    Growth (P16): the median of d ln a / dt, a = (bulge - neck) / 2, while
+    a runs from R/10 to R/2, falls with kappa* as Rayleigh's and Weber's
+    rates do, and lies between 0.6 and 1.1 of Weber's viscous long-wave
+    rate sqrt(gamma k^2 R^2 (1 - k^2 R^2) / (2 rho R^3) + (3 nu k^2 / 2)^2)
+    - 3 nu k^2 / 2 (gamma = 0.141): measured 0.70 at kappa* = 0.65 rising
+    to 0.96 at 0.21.  The shortfall grows with the curvature terms: the
+    velocity-shift forcing gives the axisymmetric Laplace pressure 25 %
+    low.  On the stable
     wavelength the initial axial flow only sets off a damped capillary
     oscillation: the bulge-neck difference stays below R/4, has decayed to
     a tenth of its peak by the end, and the thread never breaks over the
     same 80 000 steps."""
     c, brk, recs, _, n, _, _ = _run_rp(320, 80000)
-    amp = [rm - nk for nk, rm, _ in recs]
+    amp = [rm - nk for nk, rm, _, _ in recs]
     _say(f"lambda 320 kappa* {c.extra['kappa']:.3f}: break {brk}, neck {min(r[0] for r in recs):.1f}, "
          f"bulge-neck first {amp[0]:.2f} max {max(amp):.2f} last {amp[-1]:.2f}")
     assert brk is None and n == -1
     assert max(amp) < 0.25 * c.extra["radius"] and amp[-1] < 0.1 * max(amp)
     last = 0
+    rates = []
     for lam in (576, 768, 1024, 1280, 1536, 1792):
         c, brk, recs, v_before, n, vols, cents = _run_rp(lam, 80000)
         kap = c.extra["kappa"]
         R = c.extra["radius"]
+        a = np.array([0.5 * (rm - nk) for nk, rm, _, _ in recs])
+        t = np.array([st for _, _, _, st in recs], dtype=np.float64)
+        grow = (a[1:] > 0.1 * R) & (a[1:] < 0.5 * R) & (a[:-1] > 0.1 * R)
+        rate = float(np.median(np.diff(np.log(a))[grow] / np.diff(t)[grow]))
+        k = kap / R
+        nu = (c.tau - 0.5) / 3.0
+        weber = math.sqrt(0.141 * kap ** 2 * (1 - kap ** 2) / (2 * c.rho_l * R ** 3) + (1.5 * nu * k * k) ** 2) \
+            - 1.5 * nu * k * k
+        rayleigh = math.sqrt(0.141 / (c.rho_l * R ** 3) * kap * i1(kap) / i0(kap) * (1 - kap ** 2))
+        rates.append(rate)
+        _say(f"  growth {rate:.3e} / Weber {weber:.3e} = {rate / weber:.2f} (Rayleigh inviscid {rayleigh:.3e})")
+        assert 0.6 < rate / weber < 1.1
         radii = [(3.0 * v / (4.0 * math.pi)) ** (1.0 / 3.0) / R for v in vols]
         frac = sum(vols) / v_before
         _say(f"lambda {lam} kappa* {kap:.3f}: break {brk}, drops {n}, R/R0 {[round(x, 3) for x in radii]}, "
@@ -158,3 +181,4 @@ def test_rayleigh_plateau_criterion_and_drops():
         assert zs[0] < 1e-3 and abs(zs[1] - lam / 2) < 1e-3
         assert abs(frac - 1.0) < 0.05
         assert max(radii) * R <= (3.0 * v_before / (4.0 * math.pi)) ** (1.0 / 3.0)
+    assert all(x > y for x, y in zip(rates, rates[1:]))
