@@ -446,8 +446,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         const C rr = C(gr) + C(0.5);
 
         // H and the mass source of the node (Eqs. H_terms, condition_h)
-        C hz = C(0), hr = C(0), mass = C(0);
-        if (a.axisym && (!kMoments || a.h_out)) {
+        auto source_terms = [&](C& hz, C& hr, C& mass) {
             // the velocity derivatives read rows up to 2 away
             const bool zd = no_du(gz, gr);
             const C druz = zd ? C(0) : d_iso<true>(s_uz, uy, ux, UZ);
@@ -458,7 +457,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             hz = (mu * (druz + dzur) - rho * ur * uz) * inv_r;
             hr = (C(2) * mu * (drur - ur * inv_r) - rho * ur * ur) * inv_r;
             mass = -rho * ur * inv_r;
-        }
+        };
 
         if constexpr (kMoments) {
             const long long x = (long long)gr * nz + gz;
@@ -466,6 +465,8 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             if (a.uz_out) a.uz_out[x] = double(uz);
             if (a.ur_out) a.ur_out[x] = double(ur);
             if (a.h_out) {
+                C hz = C(0), hr = C(0), mass = C(0);
+                if (a.axisym) source_terms(hz, hr, mass);
                 a.h_out[x] = double(hz);
                 a.h_out[a.plane + x] = double(hr);
                 a.h_out[2 * a.plane + x] = double(mass);
@@ -477,6 +478,8 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             part[3] += double(rho);
         } else {
             const C Fz = Fz_t[k], Fr = Fr_t[k];
+            C hz = C(0), hr = C(0), mass = C(0);
+            if (a.axisym) source_terms(hz, hr, mass);
             const C inv_rho = dev_rcp(rho);
             // equilibrium velocity: shifted by tau F (Eq. ueq), or the
             // hydrodynamic velocity with Guo forcing
@@ -535,7 +538,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
                     feq_acc += feq;
                     h_acc += hi;
                 }
-                    if (midlink && i != 0) {
+                if (midlink && i != 0) {
                     // the source at the far end of the link, from that node's fields
                     int yr = gr + cr(i);
                     C sr = C(1);  // H_r is odd across the axis

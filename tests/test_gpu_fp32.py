@@ -205,3 +205,29 @@ def test_fp32_breakup_step_rayleigh_plateau():
     assert b64 is not None and b32 is not None
     assert 20000 < b64 < 35000
     assert abs(b32 - b64) <= max(100, 0.01 * b64)
+
+
+@pytest.mark.parametrize("flags", [16, 4])
+def test_fp32_options_field_error(flags):
+    """The run-time option path in FP32 shifted storage (rho_ref = rho_g):
+    the mid-link source (flag 16) and Guo forcing (flag 4) on the
+    oscillating drop at tau = 1 (with Guo forcing the scheme diverges at
+    tau = 0.8 on this drop, in the oracle as on the GPU), 2000 steps,
+    against the FP64 oracle with the same option, within the envelope of
+    the default path (max |d rho| < 1e-3, max |d u| < 1e-4)."""
+    L = _lib()
+    case = oscillating_drop(tau=1.0)
+    steps = 2000
+    p = O.make_params(case.nz, case.nr, G=case.G, tau=case.tau, wall=case.wall, axisym=1, flags=flags)
+    ro, uzo, uro = O.moments(p, O.run(p, O.equilibrium(p, case.rho, case.uz, case.ur), steps))
+    _say(f"fp32 option {flags} field error 256x128 {steps} steps")
+    pg = L.make_params(case.nz, case.nr, G=case.G, tau=case.tau, wall=case.wall, axisym=1,
+                       precision=L.FP32_SHIFTED, rho_ref=case.rho_g, flags=flags)
+    sim = L.AxiLBM(pg, torch.from_numpy(case.rho).cuda())
+    sim.step(steps)
+    rho32, uz32, ur32 = (t.cpu().numpy() for t in sim.moments())
+    sim.close()
+    drho = float(np.abs(rho32 - ro).max())
+    du = float(max(np.abs(uz32 - uzo).max(), np.abs(ur32 - uro).max()))
+    _say(f"  max|d rho| = {drho:.3e}  max|d u| = {du:.3e}")
+    assert drho < 1e-3 and du < 1e-4
