@@ -296,6 +296,20 @@ int launch_tile(lbm_axi_ctx* h, const lbm::StepArgs& a) {
     return LBM_AXI_OK;
 }
 
+// one step from state fin into state fout (the handle's layout); with the
+// mid-link source, the moments pass that writes H and the mass source first
+int step_into(lbm_axi_ctx* h, lbm::StepArgs a, const void* fin, void* fout) {
+    a.fin = fin;
+    a.fout = fout;
+    if (a.opts & 16) {
+        lbm::StepArgs m = a;
+        m.h_out = reinterpret_cast<double*>(h->ws + h->L.off_h);
+        const int rc = launch_tile<true>(h, m);
+        if (rc != LBM_AXI_OK) return rc;
+    }
+    return launch_tile<false>(h, a);
+}
+
 }  // namespace
 
 extern "C" {
@@ -347,19 +361,9 @@ int lbm_axi_create(const lbm_axi_params* p, const double* d_rho0, const double* 
 int lbm_axi_step(lbm_axi_t h, int64_t n) {
     if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
     if (n < 0) return fail(LBM_AXI_EINVAL, "n must be >= 0");
-    lbm::StepArgs a = make_args(h);
-    const bool midlink = (a.opts & 16) != 0;
+    const lbm::StepArgs a = make_args(h);
     for (int64_t s = 0; s < n; ++s) {
-        a.fin = state_ptr(h, h->cur);
-        a.fout = state_ptr(h, 1 - h->cur);
-        if (midlink) {
-            // the fields h_i is formed from, at every node, before the step
-            lbm::StepArgs m = a;
-            m.h_out = reinterpret_cast<double*>(h->ws + h->L.off_h);
-            int rc = launch_tile<true>(h, m);
-            if (rc != LBM_AXI_OK) return rc;
-        }
-        int rc = launch_tile<false>(h, a);
+        const int rc = step_into(h, a, state_ptr(h, h->cur), state_ptr(h, 1 - h->cur));
         if (rc != LBM_AXI_OK) return rc;
         h->cur = 1 - h->cur;
     }
@@ -518,16 +522,19 @@ int lbm_axi_record(lbm_axi_t h, int64_t n, void* d_states) {
     if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
     if (!d_states) return fail(LBM_AXI_EINVAL, "d_states is NULL");
     if (n < 1) return fail(LBM_AXI_EINVAL, "n must be >= 1");
+    // the steps write straight into the record: one copy in, one copy back
     char* dst = static_cast<char*>(d_states);
-    for (int64_t j = 0; j < n; ++j) {
-        if (j > 0) {
-            int rc = lbm_axi_step(h, 1);
-            if (rc != LBM_AXI_OK) return rc;
-        }
-        HIP_TRY(hipMemcpyAsync(dst + (size_t)j * h->L.state_bytes, state_ptr(h, h->cur), h->L.state_bytes,
-                               hipMemcpyDeviceToDevice, h->stream),
-                "record copy");
+    const size_t sb = h->L.state_bytes;
+    HIP_TRY(hipMemcpyAsync(dst, state_ptr(h, h->cur), sb, hipMemcpyDeviceToDevice, h->stream), "record copy");
+    const lbm::StepArgs a = make_args(h);
+    for (int64_t j = 1; j < n; ++j) {
+        const int rc = step_into(h, a, dst + (size_t)(j - 1) * sb, dst + (size_t)j * sb);
+        if (rc != LBM_AXI_OK) return rc;
     }
+    if (n > 1)
+        HIP_TRY(hipMemcpyAsync(state_ptr(h, h->cur), dst + (size_t)(n - 1) * sb, sb, hipMemcpyDeviceToDevice,
+                               h->stream),
+                "record copy");
     return LBM_AXI_OK;
 }
 
