@@ -392,28 +392,30 @@ __global__ void rev_velocity_force(AdjArgs a) {
     w[slot_off(S_GB, n) + x] = Gb;
 }
 
-// d_zr = 1D d_z of the 1D d_r: transpose of the outer z difference
-__global__ void rev_dzr(AdjArgs a) {
-    NODE_LOOP(a)
-    const double* b = a.w + slot_off(S_DZRB, a.n) + (long long)r * a.nz;
-    const int nz = a.nz;
-    // forward: out(z) = (-in(z+2) + 8 in(z+1) - 8 in(z-1) + in(z-2)) / 12
-    a.w[slot_off(S_D1B, a.n) + x] = (-b[wrapz(z - 2, nz)] + 8.0 * b[wrapz(z - 1, nz)] - 8.0 * b[wrapz(z + 1, nz)] +
-                                     b[wrapz(z + 2, nz)]) / 12.0;
-}
-
-// adjoint of d_r psi on extended rows -2 .. nr+1 (the rows d_rr reads):
-// transposed d_rr plus the direct use of d_r on real rows
+// Two independent transposed stencils in one pass (both read only what
+// rev_velocity_force wrote):
+// - adjoint of d_r psi on extended rows -2 .. nr+1 (the rows d_rr reads):
+//   transposed d_rr plus the direct use of d_r on real rows;
+// - on real rows, d_zr = 1D d_z of the 1D d_r: transpose of the outer z
+//   difference.
 __global__ void rev_dr(AdjArgs a) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= a.ne) return;
     const int y = (int)(e / a.nz) - NGA, z = (int)(e - (long long)(y + NGA) * a.nz);
+    const int nz = a.nz;
     double v = 0.0;
     if (y >= -2 && y < a.nr + 2) {
-        v = iso_transpose_real(a.w + slot_off(S_DRRB, a.n), z, y, a.nz, a.nr, true);
-        if (y >= 0 && y < a.nr) v += a.w[slot_off(S_DRB_REAL, a.n) + (long long)y * a.nz + z];
+        v = iso_transpose_real(a.w + slot_off(S_DRRB, a.n), z, y, nz, a.nr, true);
+        if (y >= 0 && y < a.nr) v += a.w[slot_off(S_DRB_REAL, a.n) + (long long)y * nz + z];
     }
     a.w[eslot_off(E_DRB, a.n, a.ne) + e] = v;
+    if (y >= 0 && y < a.nr) {
+        const double* b = a.w + slot_off(S_DZRB, a.n) + (long long)y * nz;
+        // forward: out(z) = (-in(z+2) + 8 in(z+1) - 8 in(z-1) + in(z-2)) / 12
+        a.w[slot_off(S_D1B, a.n) + (long long)y * nz + z] =
+            (-b[wrapz(z - 2, nz)] + 8.0 * b[wrapz(z - 1, nz)] - 8.0 * b[wrapz(z + 1, nz)] + b[wrapz(z + 2, nz)]) /
+            12.0;
+    }
 }
 
 // adjoint of extended psi at extended row e, column z (before folding)
@@ -642,7 +644,6 @@ void launch_reverse_step(AdjArgs a, const double* f, const double* lam_next, dou
     hipLaunchKernelGGL(fwd_force, dim3(be), b, 0, s, a);
     hipLaunchKernelGGL(rev_collision, dim3(bn), b, 0, s, a);
     hipLaunchKernelGGL(rev_velocity_force, dim3(bn), b, 0, s, a);
-    hipLaunchKernelGGL(rev_dzr, dim3(bn), b, 0, s, a);
     hipLaunchKernelGGL(rev_dr, dim3(be), b, 0, s, a);
     hipLaunchKernelGGL(rev_psi_final, dim3(bn), b, 0, s, a);
 }
