@@ -28,8 +28,9 @@
 extern "C" {
 #endif
 
-/* Bytes of FP64 scratch lbm_axi_adjoint_step needs for an nz x nr grid
- * (recomputed forward fields and adjoint fields); 0 if the size is
+/* Bytes of FP64 scratch lbm_axi_adjoint_step and lbm_axi_adjoint_run need
+ * for an nz x nr grid (two blocks of recomputed forward fields, used by
+ * alternate steps of a run, and the adjoint fields); 0 if the size is
  * invalid. */
 size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr);
 

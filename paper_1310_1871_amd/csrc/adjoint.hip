@@ -47,11 +47,13 @@ struct AdjArgs {
     const double* f;         // [9][n] state f^t
     const double* lam_next;  // [9][n]
     double* lam;             // [9][n]
-    double* w;               // field workspace
+    double* fw;              // forward fields of the step (recomputed)
+    double* w;               // adjoint fields, f-bar, partial sums
     int accumulate;          // 1: add the block partials of dL/dG, dL/dtau to running sums
 };
 
-// field slots inside the workspace (each n doubles)
+// field slots (each n doubles): the forward ones (S_RHO .. S_QR) in a
+// forward block, the adjoint ones (S_RHOB ..) in the adjoint block
 enum Slot {
     S_RHO, S_JZ, S_JR, S_PSI, S_DRR, S_DZR, S_FZ, S_FR, S_SCZ, S_SCR, S_UZ, S_UR, S_QZ, S_QR,
     // adjoints
@@ -59,12 +61,27 @@ enum Slot {
     S_PSIB_LOC, S_DZRB, S_DRRB, S_DRB_REAL, S_D1B, S_FSCZB, S_FSCRB, S_GB, S_TAUB,
     S_NSLOT
 };
-// extended slots (ne doubles each), after the plain ones
+// extended slots (ne doubles each), after the plain ones of their block
+// (E_PSI .. E_UR forward, E_DRB adjoint)
 enum SlotE { E_PSI, E_DR, E_UZ, E_UR, E_DRB, E_NSLOT };
-// after the extended slots: the partial f-bar, a population-sized field
-__host__ __device__ inline size_t slot_off(int s, long long n) { return (size_t)s * n; }
-__host__ __device__ inline size_t eslot_off(int s, long long n, long long ne) { return (size_t)S_NSLOT * n + (size_t)s * ne; }
-__host__ __device__ inline size_t fbar_off(long long n, long long ne) { return (size_t)S_NSLOT * n + (size_t)E_NSLOT * ne; }
+constexpr int kFwdSlots = S_RHOB, kFwdESlots = E_DRB;
+// doubles in one forward block
+__host__ __device__ inline size_t fwd_block(long long n, long long ne) {
+    return (size_t)kFwdSlots * n + (size_t)kFwdESlots * ne;
+}
+// a slot's field inside its block
+__device__ __forceinline__ double* fptr(const AdjArgs& a, int s) {
+    return s < kFwdSlots ? a.fw + (size_t)s * a.n : a.w + (size_t)(s - kFwdSlots) * a.n;
+}
+__device__ __forceinline__ double* eptr(const AdjArgs& a, int s) {
+    return s < kFwdESlots ? a.fw + (size_t)kFwdSlots * a.n + (size_t)s * a.ne
+                          : a.w + (size_t)(S_NSLOT - kFwdSlots) * a.n + (size_t)(s - kFwdESlots) * a.ne;
+}
+// in the adjoint block, after its extended slot: the partial f-bar, a
+// population-sized field
+__host__ __device__ inline size_t fbar_off(long long n, long long ne) {
+    return (size_t)(S_NSLOT - kFwdSlots) * n + (size_t)(E_NSLOT - kFwdESlots) * ne;
+}
 // after f-bar: per-block partial sums of dL/dG and dL/dtau ([block][2])
 __host__ __device__ inline size_t part_off(long long n, long long ne) { return fbar_off(n, ne) + 9 * (size_t)n; }
 // running per-block sums of a multi-step run, after the step partials
@@ -89,7 +106,7 @@ __device__ __forceinline__ int mirror_src(int y, int nr, double& sgn, double axi
 __device__ __forceinline__ long long eidx(int y, int z, int nz) { return (long long)(y + NGA) * nz + z; }
 
 #define NODE_LOOP(a)                                                 \
-    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; \
+    const long long x = gid;                                         \
     if (x >= (a).n) return;                                          \
     const int r = (int)(x / (a).nz), z = (int)(x - (long long)r * (a).nz);
 
@@ -112,8 +129,8 @@ __device__ double d_iso_e(const double* E, int z, int y, int nz, bool along_r) {
 // rho, j, psi on the real rows and psi on the extended rows -6 .. nr+5
 // (a ghost row takes the value of its mirror row: psi is even at the axis
 // and at the wall)
-__global__ void fwd_moments(AdjArgs a) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fwd_moments_at(const AdjArgs& a, const long long gid) {
+    const long long e = gid;
     if (e >= a.ne) return;
     const int y = (int)(e / a.nz) - NGA, z = (int)(e - (long long)(y + NGA) * a.nz);
     double sgn;
@@ -131,30 +148,30 @@ __global__ void fwd_moments(AdjArgs a) {
     }
     const double psi = a.rho0 * (1.0 - exp(-rho / a.rho0));
     if (y == ys) {
-        w[slot_off(S_RHO, n) + x] = rho;
-        w[slot_off(S_JZ, n) + x] = jz;
-        w[slot_off(S_JR, n) + x] = jr;
-        w[slot_off(S_PSI, n) + x] = psi;
+        fptr(a, S_RHO)[x] = rho;
+        fptr(a, S_JZ)[x] = jz;
+        fptr(a, S_JR)[x] = jr;
+        fptr(a, S_PSI)[x] = psi;
     }
-    w[eslot_off(E_PSI, n, a.ne) + e] = psi;
+    eptr(a, E_PSI)[e] = psi;
 }
 
 // isotropic d_r psi on extended rows -4 .. nr+3 (zero elsewhere)
-__global__ void fwd_dr(AdjArgs a) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fwd_dr_at(const AdjArgs& a, const long long gid) {
+    const long long e = gid;
     if (e >= a.ne) return;
     const int y = (int)(e / a.nz) - NGA, z = (int)(e - (long long)(y + NGA) * a.nz);
-    const double* psiE = a.w + eslot_off(E_PSI, a.n, a.ne);
+    const double* psiE = eptr(a, E_PSI);
     double v = 0.0;
     if (y >= -4 && y < a.nr + 4) v = d_iso_e(psiE, z, y, a.nz, true);
-    a.w[eslot_off(E_DR, a.n, a.ne) + e] = v;
+    eptr(a, E_DR)[e] = v;
 }
 
 // forces, hydrodynamic and equilibrium velocities on the real rows, and the
 // velocity on the extended rows (a ghost row recomputes its mirror row's
 // value: u_z even, u_r odd at the axis and even at the wall)
-__global__ void fwd_force(AdjArgs a) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fwd_force_at(const AdjArgs& a, const long long gid) {
+    const long long e = gid;
     if (e >= a.ne) return;
     const int y = (int)(e / a.nz) - NGA, z = (int)(e - (long long)(y + NGA) * a.nz);
     double sgn;
@@ -163,8 +180,8 @@ __global__ void fwd_force(AdjArgs a) {
     const long long n = a.n;
     const int nz = a.nz;
     const long long x = (long long)r * nz + z;
-    const double* psiE = w + eslot_off(E_PSI, n, a.ne);
-    const double* drE = w + eslot_off(E_DR, n, a.ne);
+    const double* psiE = eptr(a, E_PSI);
+    const double* drE = eptr(a, E_DR);
     // 1D fourth-order d_z of the 1D fourth-order d_r (Sec. II.D)
     auto d1 = [&](int zz) {
         zz = wrapz(zz, nz);
@@ -180,7 +197,7 @@ __global__ void fwd_force(AdjArgs a) {
         sz += lbm::weight(i) * ps * lbm::cz(i);
         sr += lbm::weight(i) * ps * lbm::cr(i);
     }
-    const double psi = w[slot_off(S_PSI, n) + x], rho = w[slot_off(S_RHO, n) + x];
+    const double psi = fptr(a, S_PSI)[x], rho = fptr(a, S_RHO)[x];
     double Fz = -a.G * psi * sz, Fr = -a.G * psi * sr;
     if (a.axisym) {
         const double rr = r + 0.5;
@@ -189,22 +206,22 @@ __global__ void fwd_force(AdjArgs a) {
         Fr += -(a.G / 18.0) * psi * (drr / rr - dr1 / (rr * rr));
     }
     Fz += rho * a.gz;
-    const double jz = w[slot_off(S_JZ, n) + x], jr = w[slot_off(S_JR, n) + x];
+    const double jz = fptr(a, S_JZ)[x], jr = fptr(a, S_JR)[x];
     const double uz = (jz + 0.5 * Fz) / rho, ur = (jr + 0.5 * Fr) / rho;
     if (y == r) {
-        w[slot_off(S_DZR, n) + x] = dzr;
-        w[slot_off(S_DRR, n) + x] = drr;
-        w[slot_off(S_SCZ, n) + x] = sz;
-        w[slot_off(S_SCR, n) + x] = sr;
-        w[slot_off(S_FZ, n) + x] = Fz;
-        w[slot_off(S_FR, n) + x] = Fr;
-        w[slot_off(S_UZ, n) + x] = uz;
-        w[slot_off(S_UR, n) + x] = ur;
-        w[slot_off(S_QZ, n) + x] = (jz + a.tau * Fz) / rho;
-        w[slot_off(S_QR, n) + x] = (jr + a.tau * Fr) / rho;
+        fptr(a, S_DZR)[x] = dzr;
+        fptr(a, S_DRR)[x] = drr;
+        fptr(a, S_SCZ)[x] = sz;
+        fptr(a, S_SCR)[x] = sr;
+        fptr(a, S_FZ)[x] = Fz;
+        fptr(a, S_FR)[x] = Fr;
+        fptr(a, S_UZ)[x] = uz;
+        fptr(a, S_UR)[x] = ur;
+        fptr(a, S_QZ)[x] = (jz + a.tau * Fz) / rho;
+        fptr(a, S_QR)[x] = (jr + a.tau * Fr) / rho;
     }
-    w[eslot_off(E_UZ, n, a.ne) + e] = uz;
-    w[eslot_off(E_UR, n, a.ne) + e] = sgn * ur;
+    eptr(a, E_UZ)[e] = uz;
+    eptr(a, E_UR)[e] = sgn * ur;
 }
 
 // ------------------------------------------------------------ reverse ----
@@ -232,14 +249,14 @@ __device__ __forceinline__ void push_target(int z, int r, int i, int nz, int nr,
 }
 
 // steps 2-3: streaming transpose, BGK / equilibrium / source reversed
-__global__ void rev_collision(AdjArgs a) {
+__device__ __forceinline__ void rev_collision_at(const AdjArgs& a, const long long gid) {
     NODE_LOOP(a)
     double* w = a.w;
     const long long n = a.n;
     const double tau = a.tau, inv_tau = 1.0 / tau;
-    const double rho = w[slot_off(S_RHO, n) + x];
-    const double qz = w[slot_off(S_QZ, n) + x], qr = w[slot_off(S_QR, n) + x];
-    const double uz = w[slot_off(S_UZ, n) + x], ur = w[slot_off(S_UR, n) + x];
+    const double rho = fptr(a, S_RHO)[x];
+    const double qz = fptr(a, S_QZ)[x], qr = fptr(a, S_QR)[x];
+    const double uz = fptr(a, S_UZ)[x], ur = fptr(a, S_UR)[x];
     const double rr = r + 0.5;
     double* fbar = w + fbar_off(n, a.ne);
 
@@ -269,8 +286,8 @@ __global__ void rev_collision(AdjArgs a) {
     double uzb = 0, urb = 0, druzb = 0, dzurb = 0, drurb = 0;
     if (a.axisym) {
         const double mu = rho * (tau - 0.5) / 3.0;
-        const double* uzE = w + eslot_off(E_UZ, n, a.ne);
-        const double* urE = w + eslot_off(E_UR, n, a.ne);
+        const double* uzE = eptr(a, E_UZ);
+        const double* urE = eptr(a, E_UR);
         const double druz = d_iso_e(uzE, z, r, a.nz, true), dzur = d_iso_e(urE, z, r, a.nz, false),
                      drur = d_iso_e(urE, z, r, a.nz, true);
         // mass = -rho u_r / r
@@ -293,22 +310,22 @@ __global__ void rev_collision(AdjArgs a) {
         taub += mub * rho / 3.0;
     }
     // u^eq = (j + tau F) / rho
-    const double Fz = w[slot_off(S_FZ, n) + x], Fr = w[slot_off(S_FR, n) + x];
+    const double Fz = fptr(a, S_FZ)[x], Fr = fptr(a, S_FR)[x];
     const double jzb = qzb / rho, jrb = qrb / rho;
     const double Fzb = tau * qzb / rho, Frb = tau * qrb / rho;
     taub += (qzb * Fz + qrb * Fr) / rho;
     rhob += -(qzb * qz + qrb * qr) / rho;
-    w[slot_off(S_RHOB, n) + x] = rhob;
-    w[slot_off(S_JZB, n) + x] = jzb;
-    w[slot_off(S_JRB, n) + x] = jrb;
-    w[slot_off(S_FZB, n) + x] = Fzb;
-    w[slot_off(S_FRB, n) + x] = Frb;
-    w[slot_off(S_UZB_H, n) + x] = uzb;
-    w[slot_off(S_URB_H, n) + x] = urb;
-    w[slot_off(S_DRUZB, n) + x] = druzb;
-    w[slot_off(S_DZURB, n) + x] = dzurb;
-    w[slot_off(S_DRURB, n) + x] = drurb;
-    w[slot_off(S_TAUB, n) + x] = taub;
+    fptr(a, S_RHOB)[x] = rhob;
+    fptr(a, S_JZB)[x] = jzb;
+    fptr(a, S_JRB)[x] = jrb;
+    fptr(a, S_FZB)[x] = Fzb;
+    fptr(a, S_FRB)[x] = Frb;
+    fptr(a, S_UZB_H)[x] = uzb;
+    fptr(a, S_URB_H)[x] = urb;
+    fptr(a, S_DRUZB)[x] = druzb;
+    fptr(a, S_DZURB)[x] = dzurb;
+    fptr(a, S_DRURB)[x] = drurb;
+    fptr(a, S_TAUB)[x] = taub;
 }
 
 // transposed isotropic stencil: sum over taps o of coef(o) * src(e - o),
@@ -327,17 +344,17 @@ __device__ double iso_transpose_real(const double* src, int z, int e, int nz, in
 }
 
 // step 4 for the velocities, then u = (j + F/2)/rho and the force reversed
-__global__ void rev_velocity_force(AdjArgs a) {
+__device__ __forceinline__ void rev_velocity_force_at(const AdjArgs& a, const long long gid) {
     NODE_LOOP(a)
     double* w = a.w;
     const long long n = a.n;
     const int nz = a.nz, nr = a.nr;
-    double uzb = w[slot_off(S_UZB_H, n) + x], urb = w[slot_off(S_URB_H, n) + x];
+    double uzb = fptr(a, S_UZB_H)[x], urb = fptr(a, S_URB_H)[x];
     if (a.axisym) {
         // images of row r in the extended velocity fields (reach 2)
-        const double* druzb = w + slot_off(S_DRUZB, n);
-        const double* dzurb = w + slot_off(S_DZURB, n);
-        const double* drurb = w + slot_off(S_DRURB, n);
+        const double* druzb = fptr(a, S_DRUZB);
+        const double* dzurb = fptr(a, S_DZURB);
+        const double* drurb = fptr(a, S_DRURB);
         int img[3];
         double sz[3], sr[3];
         int ni = 0;
@@ -350,24 +367,24 @@ __global__ void rev_velocity_force(AdjArgs a) {
             urb += sr[k] * (iso_transpose_real(dzurb, z, e, nz, nr, false) + iso_transpose_real(drurb, z, e, nz, nr, true));
         }
     }
-    const double rho = w[slot_off(S_RHO, n) + x];
-    const double uz = w[slot_off(S_UZ, n) + x], ur = w[slot_off(S_UR, n) + x];
-    double jzb = w[slot_off(S_JZB, n) + x] + uzb / rho;
-    double jrb = w[slot_off(S_JRB, n) + x] + urb / rho;
-    double Fzb = w[slot_off(S_FZB, n) + x] + 0.5 * uzb / rho;
-    double Frb = w[slot_off(S_FRB, n) + x] + 0.5 * urb / rho;
-    double rhob = w[slot_off(S_RHOB, n) + x] - (uzb * uz + urb * ur) / rho;
+    const double rho = fptr(a, S_RHO)[x];
+    const double uz = fptr(a, S_UZ)[x], ur = fptr(a, S_UR)[x];
+    double jzb = fptr(a, S_JZB)[x] + uzb / rho;
+    double jrb = fptr(a, S_JRB)[x] + urb / rho;
+    double Fzb = fptr(a, S_FZB)[x] + 0.5 * uzb / rho;
+    double Frb = fptr(a, S_FRB)[x] + 0.5 * urb / rho;
+    double rhob = fptr(a, S_RHOB)[x] - (uzb * uz + urb * ur) / rho;
     // F = F^SC + F^sym + rho g z^
     rhob += Fzb * a.gz;
-    const double psi = w[slot_off(S_PSI, n) + x];
-    const double sz = w[slot_off(S_SCZ, n) + x], sr = w[slot_off(S_SCR, n) + x];
+    const double psi = fptr(a, S_PSI)[x];
+    const double sz = fptr(a, S_SCZ)[x], sr = fptr(a, S_SCR)[x];
     double Gb = -psi * (Fzb * sz + Frb * sr);
     double psib = -a.G * (Fzb * sz + Frb * sr);
     double dzrb = 0, drrb = 0, dr1b = 0;
     if (a.axisym) {
         const double rr = r + 0.5;
-        const double dzr = w[slot_off(S_DZR, n) + x], drr = w[slot_off(S_DRR, n) + x];
-        const double dr1 = w[eslot_off(E_DR, n, a.ne) + eidx(r, z, nz)];
+        const double dzr = fptr(a, S_DZR)[x], drr = fptr(a, S_DRR)[x];
+        const double dr1 = eptr(a, E_DR)[eidx(r, z, nz)];
         const double g18 = a.G / 18.0;
         // F^sym_z = -(G/18) psi d_zr / r
         Gb += Fzb * (-psi * dzr / (18.0 * rr));
@@ -380,16 +397,16 @@ __global__ void rev_velocity_force(AdjArgs a) {
         drrb = Frb * (-g18 * psi / rr);
         dr1b = Frb * (g18 * psi / (rr * rr));
     }
-    w[slot_off(S_JZB, n) + x] = jzb;
-    w[slot_off(S_JRB, n) + x] = jrb;
-    w[slot_off(S_RHOB, n) + x] = rhob;
-    w[slot_off(S_FSCZB, n) + x] = Fzb;  // adjoint of F^SC equals that of F
-    w[slot_off(S_FSCRB, n) + x] = Frb;
-    w[slot_off(S_PSIB_LOC, n) + x] = psib;
-    w[slot_off(S_DZRB, n) + x] = dzrb;
-    w[slot_off(S_DRRB, n) + x] = drrb;
-    w[slot_off(S_DRB_REAL, n) + x] = dr1b;
-    w[slot_off(S_GB, n) + x] = Gb;
+    fptr(a, S_JZB)[x] = jzb;
+    fptr(a, S_JRB)[x] = jrb;
+    fptr(a, S_RHOB)[x] = rhob;
+    fptr(a, S_FSCZB)[x] = Fzb;  // adjoint of F^SC equals that of F
+    fptr(a, S_FSCRB)[x] = Frb;
+    fptr(a, S_PSIB_LOC)[x] = psib;
+    fptr(a, S_DZRB)[x] = dzrb;
+    fptr(a, S_DRRB)[x] = drrb;
+    fptr(a, S_DRB_REAL)[x] = dr1b;
+    fptr(a, S_GB)[x] = Gb;
 }
 
 // Two independent transposed stencils in one pass (both read only what
@@ -398,24 +415,52 @@ __global__ void rev_velocity_force(AdjArgs a) {
 //   transposed d_rr plus the direct use of d_r on real rows;
 // - on real rows, d_zr = 1D d_z of the 1D d_r: transpose of the outer z
 //   difference.
-__global__ void rev_dr(AdjArgs a) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void rev_dr_at(const AdjArgs& a, const long long gid) {
+    const long long e = gid;
     if (e >= a.ne) return;
     const int y = (int)(e / a.nz) - NGA, z = (int)(e - (long long)(y + NGA) * a.nz);
     const int nz = a.nz;
     double v = 0.0;
     if (y >= -2 && y < a.nr + 2) {
-        v = iso_transpose_real(a.w + slot_off(S_DRRB, a.n), z, y, nz, a.nr, true);
-        if (y >= 0 && y < a.nr) v += a.w[slot_off(S_DRB_REAL, a.n) + (long long)y * nz + z];
+        v = iso_transpose_real(fptr(a, S_DRRB), z, y, nz, a.nr, true);
+        if (y >= 0 && y < a.nr) v += fptr(a, S_DRB_REAL)[(long long)y * nz + z];
     }
-    a.w[eslot_off(E_DRB, a.n, a.ne) + e] = v;
+    eptr(a, E_DRB)[e] = v;
     if (y >= 0 && y < a.nr) {
-        const double* b = a.w + slot_off(S_DZRB, a.n) + (long long)y * nz;
+        const double* b = fptr(a, S_DZRB) + (long long)y * nz;
         // forward: out(z) = (-in(z+2) + 8 in(z+1) - 8 in(z-1) + in(z-2)) / 12
-        a.w[slot_off(S_D1B, a.n) + (long long)y * nz + z] =
+        fptr(a, S_D1B)[(long long)y * nz + z] =
             (-b[wrapz(z - 2, nz)] + 8.0 * b[wrapz(z - 1, nz)] - 8.0 * b[wrapz(z + 1, nz)] + b[wrapz(z + 2, nz)]) /
             12.0;
     }
+}
+
+__device__ __forceinline__ long long global_id() { return (long long)blockIdx.x * blockDim.x + threadIdx.x; }
+
+__global__ void fwd_moments(AdjArgs a) { fwd_moments_at(a, global_id()); }
+__global__ void fwd_dr(AdjArgs a) { fwd_dr_at(a, global_id()); }
+__global__ void fwd_force(AdjArgs a) { fwd_force_at(a, global_id()); }
+__global__ void rev_collision(AdjArgs a) { rev_collision_at(a, global_id()); }
+__global__ void rev_velocity_force(AdjArgs a) { rev_velocity_force_at(a, global_id()); }
+__global__ void rev_dr(AdjArgs a) { rev_dr_at(a, global_id()); }
+
+// In a run, the reverse kernels of step t share their launches with the
+// recomputation of step t - 1, whose fields go to the other forward block:
+// the two parts of a launch touch no common field.
+__global__ void rev_collision_fwd_moments(AdjArgs ar, AdjArgs af, int fwd) {
+    const long long g = global_id();
+    rev_collision_at(ar, g);
+    if (fwd) fwd_moments_at(af, g);
+}
+__global__ void rev_velocity_force_fwd_dr(AdjArgs ar, AdjArgs af, int fwd) {
+    const long long g = global_id();
+    rev_velocity_force_at(ar, g);
+    if (fwd) fwd_dr_at(af, g);
+}
+__global__ void rev_dr_fwd_force(AdjArgs ar, AdjArgs af, int fwd) {
+    const long long g = global_id();
+    rev_dr_at(ar, g);
+    if (fwd) fwd_force_at(af, g);
 }
 
 // adjoint of extended psi at extended row e, column z (before folding)
@@ -425,7 +470,7 @@ __device__ double psi_ext_adjoint(const AdjArgs& a, int z, int e) {
     const int nz = a.nz, nr = a.nr;
     double s = 0.0;
     // d_r psi = iso_r(psi_ext) on rows -4..nr+3; only rows -2..nr+1 carry adjoint
-    const double* drb = w + eslot_off(E_DRB, n, a.ne);
+    const double* drb = eptr(a, E_DRB);
 #pragma unroll
     for (int i = 1; i < lbm::kQ; ++i) {
         const int c = lbm::cr(i);
@@ -435,16 +480,16 @@ __device__ double psi_ext_adjoint(const AdjArgs& a, int z, int e) {
         if (y2 >= -2 && y2 < nr + 2) s -= (c / 36.0) * drb[eidx(y2, wrapz(z - 2 * lbm::cz(i), nz), nz)];
     }
     // 1D d_r psi on real rows: (-p(y+2) + 8 p(y+1) - 8 p(y-1) + p(y-2)) / 12
-    const double* d1b = w + slot_off(S_D1B, n);
+    const double* d1b = fptr(a, S_D1B);
     const int ys[4] = {e - 2, e - 1, e + 1, e + 2};
     const double cf[4] = {-1.0, 8.0, -8.0, 1.0};
 #pragma unroll
     for (int k = 0; k < 4; ++k)
         if (ys[k] >= 0 && ys[k] < nr) s += (cf[k] / 12.0) * d1b[(long long)ys[k] * nz + z];
     // Shan–Chen force: F^SC(x) = -G psi(x) sum_i W_i psi(x + c_i) c_i
-    const double* fzb = w + slot_off(S_FSCZB, n);
-    const double* frb = w + slot_off(S_FSCRB, n);
-    const double* psi = w + slot_off(S_PSI, n);
+    const double* fzb = fptr(a, S_FSCZB);
+    const double* frb = fptr(a, S_FSCRB);
+    const double* psi = fptr(a, S_PSI);
 #pragma unroll
     for (int i = 1; i < lbm::kQ; ++i) {
         const int ysrc = e - lbm::cr(i);
@@ -467,18 +512,18 @@ __global__ void rev_psi_final(AdjArgs a) {
     if (x < n) {
         const int nr = a.nr;
         const int r = (int)(x / a.nz), z = (int)(x - (long long)r * a.nz);
-        double psib = w[slot_off(S_PSIB_LOC, n) + x] + psi_ext_adjoint(a, z, r);
+        double psib = fptr(a, S_PSIB_LOC)[x] + psi_ext_adjoint(a, z, r);
         if (r <= 3) psib += psi_ext_adjoint(a, z, -1 - r);            // axis images (rows -4..-1)
         if (r >= nr - 4) psib += psi_ext_adjoint(a, z, 2 * nr - 1 - r);  // wall images (rows nr..nr+3)
-        const double rho = w[slot_off(S_RHO, n) + x];
-        const double rhob = w[slot_off(S_RHOB, n) + x] + psib * exp(-rho / a.rho0);
-        const double jzb = w[slot_off(S_JZB, n) + x], jrb = w[slot_off(S_JRB, n) + x];
+        const double rho = fptr(a, S_RHO)[x];
+        const double rhob = fptr(a, S_RHOB)[x] + psib * exp(-rho / a.rho0);
+        const double jzb = fptr(a, S_JZB)[x], jrb = fptr(a, S_JRB)[x];
         const double* fbar = w + fbar_off(n, a.ne);
 #pragma unroll
         for (int i = 0; i < lbm::kQ; ++i)
             a.lam[i * n + x] = fbar[i * n + x] + rhob + lbm::cz(i) * jzb + lbm::cr(i) * jrb;
-        g = w[slot_off(S_GB, n) + x];
-        q = w[slot_off(S_TAUB, n) + x];
+        g = fptr(a, S_GB)[x];
+        q = fptr(a, S_TAUB)[x];
     }
     __shared__ double s[2][kAdjBlock];
     const int t = threadIdx.x;
@@ -613,7 +658,9 @@ __global__ void zero_kernel(double* p, long long n) {
     if (x < n) p[x] = 0.0;
 }
 
-AdjArgs adjoint_args(const lbm_axi_params* p, void* d_ws, int accumulate) {
+// workspace: two forward blocks (a run recomputes step t - 1 into one while
+// step t is reversed from the other), then the adjoint block
+AdjArgs adjoint_args(const lbm_axi_params* p, void* d_ws, int accumulate, int parity = 0) {
     AdjArgs a{};
     a.nz = p->nz;
     a.nr = p->nr;
@@ -625,7 +672,9 @@ AdjArgs adjoint_args(const lbm_axi_params* p, void* d_ws, int accumulate) {
     a.gz = p->gz;
     a.wall = p->wall;
     a.axisym = p->axisym;
-    a.w = static_cast<double*>(d_ws);
+    double* base = static_cast<double*>(d_ws);
+    a.fw = base + (size_t)parity * fwd_block(a.n, a.ne);
+    a.w = base + 2 * fwd_block(a.n, a.ne);
     a.accumulate = accumulate;
     return a;
 }
@@ -665,7 +714,7 @@ size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr) {
     if (nz < 1 || nr < 6) return 0;
     const long long n = (long long)nz * nr, ne = (long long)nz * (nr + 2 * NGA);
     const size_t nparts = (size_t)((n + kAdjBlock - 1) / kAdjBlock);
-    return ((size_t)S_NSLOT * n + (size_t)E_NSLOT * ne + 9 * (size_t)n + 4 * nparts) * sizeof(double);
+    return (2 * fwd_block(n, ne) + fbar_off(n, ne) + 9 * (size_t)n + 4 * nparts) * sizeof(double);
 }
 
 int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const double* d_lam_next, double* d_lam,
@@ -694,13 +743,35 @@ int lbm_axi_adjoint_run(const lbm_axi_params* p, const double* d_states, int32_t
     // the block sums of dL/dG, dL/dtau run over the k steps and are reduced
     // once at the end (a kernel, not a memset, clears them)
     hipLaunchKernelGGL(zero_kernel, dim3(nblk(2 * (long long)nparts)), dim3(256), 0, s, run, 2 * (long long)nparts);
+    const dim3 b(kAdjBlock);
+    const int bn = nparts, be = (int)((a.ne + kAdjBlock - 1) / kAdjBlock);
     double* cur = d_lam;  // holds lam^{t0+j+1} before step j
     double* nxt = d_tmp;
+    if (k > 0) {
+        // fields of the last state, into forward block 0
+        AdjArgs f0 = adjoint_args(p, d_ws, 1, 0);
+        f0.f = d_states + (size_t)(k - 1) * n9;
+        hipLaunchKernelGGL(fwd_moments, dim3(be), b, 0, s, f0);
+        hipLaunchKernelGGL(fwd_dr, dim3(be), b, 0, s, f0);
+        hipLaunchKernelGGL(fwd_force, dim3(be), b, 0, s, f0);
+    }
+    int par = 0;
     for (int32_t j = k - 1; j >= 0; --j) {
-        launch_reverse_step(a, d_states + (size_t)j * n9, cur, nxt, s);
+        AdjArgs ar = adjoint_args(p, d_ws, 1, par);  // step j, fields in block par
+        ar.f = d_states + (size_t)j * n9;
+        ar.lam_next = cur;
+        ar.lam = nxt;
+        AdjArgs af = adjoint_args(p, d_ws, 1, 1 - par);  // step j - 1, into the other block
+        const int fwd = j > 0 ? 1 : 0;
+        af.f = fwd ? d_states + (size_t)(j - 1) * n9 : nullptr;
+        hipLaunchKernelGGL(rev_collision_fwd_moments, dim3(be), b, 0, s, ar, af, fwd);
+        hipLaunchKernelGGL(rev_velocity_force_fwd_dr, dim3(be), b, 0, s, ar, af, fwd);
+        hipLaunchKernelGGL(rev_dr_fwd_force, dim3(be), b, 0, s, ar, af, fwd);
+        hipLaunchKernelGGL(rev_psi_final, dim3(bn), b, 0, s, ar);
         double* t = cur;
         cur = nxt;
         nxt = t;
+        par = 1 - par;
     }
     if (d_grad_acc && k > 0) hipLaunchKernelGGL(rev_reduce, dim3(1), dim3(256), 0, s, run, nparts, d_grad_acc);
     if (hipGetLastError() != hipSuccess) return LBM_AXI_EHIP;
