@@ -132,7 +132,7 @@ lbm::StepArgs instance_args(lbm_axi_batch* b, int k, int parity) {
     a.state_bytes = (unsigned)b->state_bytes(k);
     a.nz = p.nz;
     a.nr = p.nr;
-    a.tiles_r = (p.nr + c.tr - 1) / c.tr;
+    a.tiles_z = (p.nz + c.tz - 1) / c.tz;
     a.big_nz = p.nz >= c.tz + 6 ? 1 : 0;
     a.wall = p.wall;
     a.axisym = p.axisym;

@@ -21,15 +21,16 @@ namespace {
 using namespace lbm_host;
 
 // Tile shapes of the fused kernel (chosen by timing on MI355X).  Large
-// lattices use 64 x 32 tiles (1024 threads in FP64, 512 in FP32); lattices
+// lattices use 64 x 16 tiles of 512 threads, two workgroups per compute
+// unit, numbered z fastest (4096 x 512: 84 us per FP64 step against 89-94 us
+// for 64 x 32 tiles of 1024 threads; 40 against 42 us in FP32); lattices
 // with fewer than 4 such tiles per compute unit use 32 x 16 tiles (512
-// threads), which keep more compute units busy (256 x 128: 7.5 instead of
-// 15 us per FP64 step).
+// threads), which keep more compute units busy.
 struct Shape {
     int tz, tr;
 };
-constexpr Shape kShape[2] = {{64, 32}, {32, 16}};  // [0] large, [1] small
-constexpr int kNT64 = 1024, kNT32 = 512, kNTSmall = 512;
+constexpr Shape kShape[2] = {{64, 16}, {32, 16}};  // [0] large, [1] small
+constexpr int kNT64 = 512, kNT32 = 512, kNTSmall = 512;
 
 int tiles_of(const lbm_axi_params* p, int c) {
     return ((p->nz + kShape[c].tz - 1) / kShape[c].tz) * ((p->nr + kShape[c].tr - 1) / kShape[c].tr);
@@ -238,7 +239,7 @@ lbm::StepArgs make_args(lbm_axi_ctx* h) {
     a.state_bytes = (unsigned)h->L.state_bytes;
     a.nz = h->p.nz;
     a.nr = h->p.nr;
-    a.tiles_r = h->L.tiles_r;
+    a.tiles_z = h->L.tiles_z;
     a.big_nz = h->p.nz >= kShape[h->L.cfg].tz + 6 ? 1 : 0;
     a.wall = h->p.wall;
     a.axisym = h->p.axisym;
@@ -264,10 +265,10 @@ void launch_shape(lbm_axi_ctx* h, const lbm::StepArgs& a) {
     const bool f64 = h->p.precision == LBM_AXI_FP64;
     if (h->L.cfg == 0) {
         if (f64)
-            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, 64, 32, kNT64, kMoments, kOpt>), grid, dim3(kNT64),
+            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, 64, 16, kNT64, kMoments, kOpt>), grid, dim3(kNT64),
                                0, h->stream, a);
         else
-            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, 64, 32, kNT32, kMoments, kOpt>), grid,
+            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, 64, 16, kNT32, kMoments, kOpt>), grid,
                                dim3(kNT32), 0, h->stream, a);
     } else {
         if (f64)

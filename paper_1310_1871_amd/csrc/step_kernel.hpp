@@ -39,7 +39,7 @@ struct StepArgs {
     long long plane;   // nz * nr
     unsigned state_bytes;  // 9 * plane * sizeof(storage) (< 4 GiB)
     int nz, nr;
-    int tiles_r;       // tiles along r (tile id = tz * tiles_r + tr)
+    int tiles_z;       // tiles along z (tile id = tr * tiles_z + tz: z fastest)
     int big_nz;        // 1 if nz >= TZ + 6: periodic wrap needs one add/sub
     int wall;          // 0 no-slip, 1 free-slip
     int axisym;        // 1 axisymmetric terms on
@@ -82,7 +82,9 @@ __device__ __forceinline__ float dev_rcp(float x) {
 }
 
 // hardware dispatches workgroup b to XCD b % 8; renumber so that each XCD
-// works on one contiguous run of tiles (neighbouring tiles share its L2)
+// works on one contiguous run of tiles.  Tiles are numbered z fastest, so
+// the workgroups resident on an XCD at one time cover whole rows of tiles
+// and read each other's side halos through its L2.
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
     const int q = nb >> 3, rem = nb & 7;
     const int x = b & 7, k = b >> 3;
@@ -146,7 +148,7 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
 }
 
 // One TZ x TR tile of one lattice: the whole step (or the moments) for the
-// tile's nodes.  `tile` = tz * tiles_r + tr; `slot` indexes the per-block
+// tile's nodes.  `tile` = tr * tiles_z + tz; `slot` indexes the per-block
 // partial sums of the moments mode.  kOpt: the option bits, known at compile
 // time (1: Guo forcing instead of the velocity shift; 2: the derivative terms
 // -- F^{gamma,sym} and the velocity derivatives in H -- are zero on rows
@@ -192,8 +194,8 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     const int nz = a.nz, nr = a.nr;
     const bool big = a.big_nz != 0;
     const int t = threadIdx.x;
-    const int tzi = tile / a.tiles_r;
-    const int z0 = tzi * TZ, r0 = (tile - tzi * a.tiles_r) * TR;
+    const int tri = tile / a.tiles_z;
+    const int z0 = (tile - tri * a.tiles_z) * TZ, r0 = tri * TR;
     const int opts = kOpt < 0 ? a.opts : kOpt;
     const bool guo = (opts & 1) != 0;
     const bool no_wall_deriv = (opts & 2) != 0;

@@ -80,7 +80,7 @@ def test_wall_derivative_option_static_drop(wall, flags):
 
 
 def test_wall_derivative_option_large_tiles():
-    """Flag 2 on the 64 x 32 tile shape (ragged 4100 x 515), 4 steps."""
+    """Flag 2 on the large 64 x 16 tile shape (ragged 4100 x 515), 4 steps."""
     nz, nr = 4100, 515
     rho, uz, ur = random_state_fields(4100516, nz, nr, rho_lo=0.3, rho_hi=2.0, u_amp=0.01)
     _compare(nz, nr, rho, 4, G=-5.0, tau=0.9, wall=0, uz=uz, ur=ur, flags=2)
@@ -100,7 +100,7 @@ def test_midlink_source_static_drop(wall, flags):
 
 def test_midlink_source_ragged_fields_and_large_tiles():
     """Flag 16 with random fields and a body force on a ragged small-tile
-    grid (200 steps), and on the 64 x 32 tile shape (ragged 4100 x 515, 3
+    grid (200 steps), and on the large 64 x 16 tile shape (ragged 4100 x 515, 3
     steps)."""
     rho, uz, ur = random_state_fields(1616, 100, 37, rho_lo=0.5, rho_hi=1.5, u_amp=0.01)
     _compare(100, 37, rho, 200, G=-4.0, tau=0.8, wall=0, gz=1e-5, uz=uz, ur=ur, flags=16)
@@ -142,9 +142,9 @@ def test_full_size_thread_fields():
 
 @pytest.mark.parametrize("wall", [0, 1])
 def test_large_tile_shape_ragged(wall):
-    """A lattice large enough for the 64 x 32 tiles (1105 of them) but not a
-    multiple of them: 4100 x 515 leaves a last tile column 4 wide and a last
-    tile row with 3 real rows, so the ghost rows beyond the wall fill most
+    """A lattice large enough for the large 64 x 16 tiles (2145 of them) but
+    not a multiple of them: 4100 x 515 leaves a last tile column 4 wide and a
+    last tile row with 3 real rows, so the ghost rows beyond the wall fill most
     of its velocity window.  Both wall rules, random smooth fields, 6 steps
     against the oracle."""
     nz, nr = 4100, 515
