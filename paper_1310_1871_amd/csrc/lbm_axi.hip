@@ -20,12 +20,16 @@ namespace {
 
 using namespace lbm_host;
 
-// Tile shapes of the fused kernel (chosen by timing on MI355X).  Large
-// lattices use 64 x 16 tiles of 512 threads, two workgroups per compute
-// unit, numbered z fastest (4096 x 512: 84 us per FP64 step against 89-94 us
-// for 64 x 32 tiles of 1024 threads; 40 against 42 us in FP32); lattices
-// with fewer than 4 such tiles per compute unit use 32 x 16 tiles (512
-// threads), which keep more compute units busy.
+// Tile shapes of the fused kernel (chosen by timing on MI355X, with the two
+// state buffers alternating as in a run).  Large lattices use 64 x 16 tiles
+// of 512 threads, two or more workgroups per compute unit.  In FP64 each XCD
+// takes runs of whole tile rows (4096 x 512: 82 us per step, against 89-94
+// us for 64 x 32 tiles of 1024 threads in r-fastest order).  In FP32 each XCD
+// takes a slab of tile columns, and the stores are written through L2 to the
+// memory-side cache, which holds both FP32 buffers (35 us, against 40 us
+// with row runs and cached stores; neither helps FP64, whose two buffers do
+// not fit).  Lattices with fewer than 4 large tiles per compute unit use
+// 32 x 16 tiles (512 threads), which keep more compute units busy.
 struct Shape {
     int tz, tr;
 };
@@ -268,7 +272,7 @@ void launch_shape(lbm_axi_ctx* h, const lbm::StepArgs& a) {
             hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, 64, 16, kNT64, kMoments, kOpt>), grid, dim3(kNT64),
                                0, h->stream, a);
         else
-            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, 64, 16, kNT32, kMoments, kOpt>), grid,
+            hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, 64, 16, kNT32, kMoments, kOpt, true, 16>), grid,
                                dim3(kNT32), 0, h->stream, a);
     } else {
         if (f64)

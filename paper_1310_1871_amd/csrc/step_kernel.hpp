@@ -139,12 +139,16 @@ __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned vo
 __device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
+// kAux: cache-policy bits of the store (16: device scope, written through
+// the XCD's L2 to the memory-side cache)
+template <int kAux = 0>
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v) {
     using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, kAux);
 }
+template <int kAux = 0>
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, kAux);
 }
 
 // One TZ x TR tile of one lattice: the whole step (or the moments) for the
@@ -166,8 +170,9 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
 // link is the average of h_i at its two ends, (h_i(x) + h_i(x + c_i)) / 2,
 // with h_i(y) = W_i (mass(y) + 3 c_i . H(y)) from StepArgs::h_in (written by
 // a moments pass with h_out); across the axis y is the mirror node with H_r
-// reversed, across the outer wall the mirror node.
-template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt = 0>
+// reversed, across the outer wall the mirror node.  kStoreAux: cache-policy
+// bits of the population stores (see buf_store).
+template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt = 0, int kStoreAux = 0>
 __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, const int slot) {
     using S = typename P::S;
     using C = typename P::C;
@@ -584,7 +589,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
                     }
                 }
                 tz = tz < 0 ? tz + nz : (tz >= nz ? tz - nz : tz);
-                buf_store(fout, (unsigned)(trr * nz + tz) * (unsigned)sizeof(S), d * plane_bytes, S(fs));
+                buf_store<kStoreAux>(fout, (unsigned)(trr * nz + tz) * (unsigned)sizeof(S), d * plane_bytes, S(fs));
             }
         }
     }
@@ -610,9 +615,23 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     }
 }
 
-template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt = 0>
+// tile of workgroup b (nb workgroups, one per tile) in slab order: XCD b % 8
+// takes a slab of tiles_z / 8 tile columns (when 8 divides tiles_z; else the
+// contiguous run of whole tile rows of xcd_remap) and walks it z fastest, so
+// the workgroups resident on an XCD form a compact block of tiles and each
+// round of tiles sits just above the previous one.
+__device__ __forceinline__ int slab_tile(int b, int nb, int tiles_z) {
+    if ((tiles_z & 7) != 0) return xcd_remap(b, nb);
+    const int sw = tiles_z >> 3, k = b >> 3;
+    const int tr = k / sw;
+    return tr * tiles_z + (b & 7) * sw + (k - tr * sw);
+}
+
+// kSlab: slab order (slab_tile) instead of runs of tile rows (xcd_remap)
+template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt = 0, bool kSlab = false, int kStoreAux = 0>
 __global__ __launch_bounds__(NT) void axi_tile_kernel(const StepArgs a) {
-    tile_body<P, TZ, TR, NT, kMoments, kOpt>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x);
+    const int tile = kSlab ? slab_tile(blockIdx.x, gridDim.x, a.tiles_z) : xcd_remap(blockIdx.x, gridDim.x);
+    tile_body<P, TZ, TR, NT, kMoments, kOpt, kStoreAux>(a, tile, blockIdx.x);
 }
 
 // Batched ensemble: many independent lattices (each with its own size,
