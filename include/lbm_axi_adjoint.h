@@ -31,7 +31,9 @@ extern "C" {
 /* Bytes of FP64 scratch lbm_axi_adjoint_step and lbm_axi_adjoint_run need
  * for an nz x nr grid (two blocks of recomputed forward fields, used by
  * alternate steps of a run, and the adjoint fields); 0 if the size is
- * invalid. */
+ * invalid.  The adjoint needs nz >= 4 and nr >= 6 (its stencils wrap at most
+ * two columns) and nz (nr + 12) < 2^31; other sizes give 0 here and
+ * LBM_AXI_EINVAL from the calls. */
 size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr);
 
 /* One reverse step.  With f' = step(f; G, tau) (post-streaming states,

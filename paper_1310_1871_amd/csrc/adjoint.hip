@@ -23,6 +23,8 @@
 // deterministic.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include <cmath>
 #include <map>
 #include <vector>
@@ -34,8 +36,9 @@
 namespace {
 
 constexpr int NGA = 6;  // ghost rows kept on extended adjoint fields
-// workgroup size of the per-node adjoint kernels: one wave, so that small
-// lattices still spread over every compute unit
+// workgroup size of the per-node adjoint kernels: one wave per workgroup: a small lattice still spreads over every CU; the
+// kernels declare it as their launch bound, which lets a thread keep all the
+// loads of a gather in flight in registers
 constexpr int kAdjBlock = 64;
 
 struct AdjArgs {
@@ -89,9 +92,11 @@ __host__ __device__ inline size_t run_off(long long n, long long ne) {
     return part_off(n, ne) + 2 * (size_t)((n + kAdjBlock - 1) / kAdjBlock);
 }
 
+// periodic column: the stencils here reach at most 2 columns and the
+// adjoint requires nz >= 4, so one add or subtract wraps
 __device__ __forceinline__ int wrapz(int z, int nz) {
-    int w = z % nz;
-    return w < 0 ? w + nz : w;
+    z = z < 0 ? z + nz : z;
+    return z >= nz ? z - nz : z;
 }
 __device__ __forceinline__ int mirror_src(int y, int nr, double& sgn, double axis_sign) {
     sgn = 1.0;
@@ -108,7 +113,7 @@ __device__ __forceinline__ long long eidx(int y, int z, int nz) { return (long l
 #define NODE_LOOP(a)                                                 \
     const long long x = gid;                                         \
     if (x >= (a).n) return;                                          \
-    const int r = (int)(x / (a).nz), z = (int)(x - (long long)r * (a).nz);
+    const int r = (int)x / (a).nz, z = (int)x - r * (a).nz;
 
 // isotropic first derivative at (z, y) of an extended field (Sec. II.D)
 __device__ double d_iso_e(const double* E, int z, int y, int nz, bool along_r) {
@@ -132,7 +137,7 @@ __device__ double d_iso_e(const double* E, int z, int y, int nz, bool along_r) {
 __device__ __forceinline__ void fwd_moments_at(const AdjArgs& a, const long long gid) {
     const long long e = gid;
     if (e >= a.ne) return;
-    const int y = (int)(e / a.nz) - NGA, z = (int)(e - (long long)(y + NGA) * a.nz);
+    const int y = (int)e / a.nz - NGA, z = (int)e - (y + NGA) * a.nz;
     double sgn;
     const int ys = mirror_src(y, a.nr, sgn, 1.0);
     double* w = a.w;
@@ -160,7 +165,7 @@ __device__ __forceinline__ void fwd_moments_at(const AdjArgs& a, const long long
 __device__ __forceinline__ void fwd_dr_at(const AdjArgs& a, const long long gid) {
     const long long e = gid;
     if (e >= a.ne) return;
-    const int y = (int)(e / a.nz) - NGA, z = (int)(e - (long long)(y + NGA) * a.nz);
+    const int y = (int)e / a.nz - NGA, z = (int)e - (y + NGA) * a.nz;
     const double* psiE = eptr(a, E_PSI);
     double v = 0.0;
     if (y >= -4 && y < a.nr + 4) v = d_iso_e(psiE, z, y, a.nz, true);
@@ -173,7 +178,7 @@ __device__ __forceinline__ void fwd_dr_at(const AdjArgs& a, const long long gid)
 __device__ __forceinline__ void fwd_force_at(const AdjArgs& a, const long long gid) {
     const long long e = gid;
     if (e >= a.ne) return;
-    const int y = (int)(e / a.nz) - NGA, z = (int)(e - (long long)(y + NGA) * a.nz);
+    const int y = (int)e / a.nz - NGA, z = (int)e - (y + NGA) * a.nz;
     double sgn;
     const int r = mirror_src(y, a.nr, sgn, -1.0);
     double* w = a.w;
@@ -248,9 +253,11 @@ __device__ __forceinline__ void push_target(int z, int r, int i, int nz, int nr,
     tz = wrapz(tz, nz);
 }
 
-// steps 2-3: streaming transpose, BGK / equilibrium / source reversed
-__device__ __forceinline__ void rev_collision_at(const AdjArgs& a, const long long gid) {
-    NODE_LOOP(a)
+// steps 2-3: streaming transpose, BGK / equilibrium / source reversed.
+// kIn: a row with no boundary link (1 <= r <= nr - 2), whose push targets
+// need no boundary rule, so the loop's loads carry no branches.
+template <bool kIn>
+__device__ __forceinline__ void rev_collision_node(const AdjArgs& a, const long long x, const int r, const int z) {
     double* w = a.w;
     const long long n = a.n;
     const double tau = a.tau, inv_tau = 1.0 / tau;
@@ -262,16 +269,39 @@ __device__ __forceinline__ void rev_collision_at(const AdjArgs& a, const long lo
 
     double rhob = 0, qzb = 0, qrb = 0, taub = 0, massb = 0, hzb = 0, hrb = 0;
     const double qq = 1.5 * (qz * qz + qr * qr);
+    // every load first: the f-bar stores below could alias them for all the
+    // compiler knows, and would otherwise make each load wait in turn
+    double druz = 0, dzur = 0, drur = 0;
+    if (a.axisym) {
+        const double* uzE = eptr(a, E_UZ);
+        const double* urE = eptr(a, E_UR);
+        druz = d_iso_e(uzE, z, r, a.nz, true);
+        dzur = d_iso_e(urE, z, r, a.nz, false);
+        drur = d_iso_e(urE, z, r, a.nz, true);
+    }
+    const double Fz = fptr(a, S_FZ)[x], Fr = fptr(a, S_FR)[x];
+    double nus[lbm::kQ], fis[lbm::kQ];
 #pragma unroll
     for (int i = 0; i < lbm::kQ; ++i) {
         int tz, tr, d;
-        push_target(z, r, i, a.nz, a.nr, a.wall, tz, tr, d);
-        const double nu = a.lam_next[d * n + (long long)tr * a.nz + tz];
+        if (kIn) {
+            tz = wrapz(z + lbm::cz(i), a.nz);
+            tr = r + lbm::cr(i);
+            d = i;
+        } else {
+            push_target(z, r, i, a.nz, a.nr, a.wall, tz, tr, d);
+        }
+        nus[i] = a.lam_next[d * n + (long long)tr * a.nz + tz];
+        fis[i] = a.f[i * n + x];
+    }
+#pragma unroll
+    for (int i = 0; i < lbm::kQ; ++i) {
+        const double nu = nus[i];
         const double wi = lbm::weight(i);
         const double cu = lbm::cz(i) * qz + lbm::cr(i) * qr;
         const double poly = 3.0 * cu + 4.5 * cu * cu - qq;
         const double feq = wi * rho * (1.0 + poly);
-        const double fi = a.f[i * n + x];
+        const double fi = fis[i];
         fbar[i * n + x] = nu * (1.0 - inv_tau);
         taub += nu * (fi - feq) * inv_tau * inv_tau;
         const double feqb = nu * inv_tau;
@@ -286,10 +316,6 @@ __device__ __forceinline__ void rev_collision_at(const AdjArgs& a, const long lo
     double uzb = 0, urb = 0, druzb = 0, dzurb = 0, drurb = 0;
     if (a.axisym) {
         const double mu = rho * (tau - 0.5) / 3.0;
-        const double* uzE = eptr(a, E_UZ);
-        const double* urE = eptr(a, E_UR);
-        const double druz = d_iso_e(uzE, z, r, a.nz, true), dzur = d_iso_e(urE, z, r, a.nz, false),
-                     drur = d_iso_e(urE, z, r, a.nz, true);
         // mass = -rho u_r / r
         rhob += -massb * ur / rr;
         urb += -massb * rho / rr;
@@ -310,7 +336,6 @@ __device__ __forceinline__ void rev_collision_at(const AdjArgs& a, const long lo
         taub += mub * rho / 3.0;
     }
     // u^eq = (j + tau F) / rho
-    const double Fz = fptr(a, S_FZ)[x], Fr = fptr(a, S_FR)[x];
     const double jzb = qzb / rho, jrb = qrb / rho;
     const double Fzb = tau * qzb / rho, Frb = tau * qrb / rho;
     taub += (qzb * Fz + qrb * Fr) / rho;
@@ -327,20 +352,35 @@ __device__ __forceinline__ void rev_collision_at(const AdjArgs& a, const long lo
     fptr(a, S_DRURB)[x] = drurb;
     fptr(a, S_TAUB)[x] = taub;
 }
+__device__ __forceinline__ void rev_collision_at(const AdjArgs& a, const long long gid) {
+    NODE_LOOP(a)
+    if (r >= 1 && r <= a.nr - 2)
+        rev_collision_node<true>(a, x, r, z);
+    else
+        rev_collision_node<false>(a, x, r, z);
+}
 
 // transposed isotropic stencil: sum over taps o of coef(o) * src(e - o),
-// src living on real rows of a plain field
-__device__ double iso_transpose_real(const double* src, int z, int e, int nz, int nr, bool along_r) {
+// src living on real rows of a plain field.  kAll: every tap row is a real
+// row, so the loads carry no bounds checks and a thread issues them all
+// before waiting on any (a check around each load makes each wait for the
+// previous one); the sum is the same either way.
+template <bool kAll>
+__device__ double iso_transpose_real_t(const double* src, int z, int e, int nz, int nr, bool along_r) {
     double s = 0.0;
 #pragma unroll
     for (int i = 1; i < lbm::kQ; ++i) {
         const int c = along_r ? lbm::cr(i) : lbm::cz(i);
         if (c == 0) continue;
         const int y1 = e - lbm::cr(i), y2 = e - 2 * lbm::cr(i);
-        if (y1 >= 0 && y1 < nr) s += 8.0 * c * src[(long long)y1 * nz + wrapz(z - lbm::cz(i), nz)];
-        if (y2 >= 0 && y2 < nr) s -= c * src[(long long)y2 * nz + wrapz(z - 2 * lbm::cz(i), nz)];
+        if (kAll || (y1 >= 0 && y1 < nr)) s += 8.0 * c * src[(long long)y1 * nz + wrapz(z - lbm::cz(i), nz)];
+        if (kAll || (y2 >= 0 && y2 < nr)) s -= c * src[(long long)y2 * nz + wrapz(z - 2 * lbm::cz(i), nz)];
     }
     return s / 36.0;
+}
+__device__ double iso_transpose_real(const double* src, int z, int e, int nz, int nr, bool along_r) {
+    return (e >= 2 && e <= nr - 3) ? iso_transpose_real_t<true>(src, z, e, nz, nr, along_r)
+                                   : iso_transpose_real_t<false>(src, z, e, nz, nr, along_r);
 }
 
 // step 4 for the velocities, then u = (j + F/2)/rho and the force reversed
@@ -355,17 +395,22 @@ __device__ __forceinline__ void rev_velocity_force_at(const AdjArgs& a, const lo
         const double* druzb = fptr(a, S_DRUZB);
         const double* dzurb = fptr(a, S_DZURB);
         const double* drurb = fptr(a, S_DRURB);
-        int img[3];
-        double sz[3], sr[3];
-        int ni = 0;
-        img[ni] = r; sz[ni] = 1.0; sr[ni] = 1.0; ++ni;
-        if (r <= 1) { img[ni] = -1 - r; sz[ni] = 1.0; sr[ni] = -1.0; ++ni; }
-        if (r >= nr - 2) { img[ni] = 2 * nr - 1 - r; sz[ni] = 1.0; sr[ni] = 1.0; ++ni; }
-        for (int k = 0; k < ni; ++k) {
-            const int e = img[k];
-            uzb += sz[k] * iso_transpose_real(druzb, z, e, nz, nr, true);
-            urb += sr[k] * (iso_transpose_real(dzurb, z, e, nz, nr, false) + iso_transpose_real(drurb, z, e, nz, nr, true));
-        }
+        // one interior test for the three gathers of an image row, so that
+        // their loads go out together
+        auto gather = [&](int e, double sgn_r) {
+            if (e >= 2 && e <= nr - 3) {
+                uzb += iso_transpose_real_t<true>(druzb, z, e, nz, nr, true);
+                urb += sgn_r * (iso_transpose_real_t<true>(dzurb, z, e, nz, nr, false) +
+                                iso_transpose_real_t<true>(drurb, z, e, nz, nr, true));
+            } else {
+                uzb += iso_transpose_real_t<false>(druzb, z, e, nz, nr, true);
+                urb += sgn_r * (iso_transpose_real_t<false>(dzurb, z, e, nz, nr, false) +
+                                iso_transpose_real_t<false>(drurb, z, e, nz, nr, true));
+            }
+        };
+        gather(r, 1.0);
+        if (r <= 1) gather(-1 - r, -1.0);          // axis image: u_r odd
+        if (r >= nr - 2) gather(2 * nr - 1 - r, 1.0);  // wall image
     }
     const double rho = fptr(a, S_RHO)[x];
     const double uz = fptr(a, S_UZ)[x], ur = fptr(a, S_UR)[x];
@@ -418,7 +463,7 @@ __device__ __forceinline__ void rev_velocity_force_at(const AdjArgs& a, const lo
 __device__ __forceinline__ void rev_dr_at(const AdjArgs& a, const long long gid) {
     const long long e = gid;
     if (e >= a.ne) return;
-    const int y = (int)(e / a.nz) - NGA, z = (int)(e - (long long)(y + NGA) * a.nz);
+    const int y = (int)e / a.nz - NGA, z = (int)e - (y + NGA) * a.nz;
     const int nz = a.nz;
     double v = 0.0;
     if (y >= -2 && y < a.nr + 2) {
@@ -437,34 +482,36 @@ __device__ __forceinline__ void rev_dr_at(const AdjArgs& a, const long long gid)
 
 __device__ __forceinline__ long long global_id() { return (long long)blockIdx.x * blockDim.x + threadIdx.x; }
 
-__global__ void fwd_moments(AdjArgs a) { fwd_moments_at(a, global_id()); }
-__global__ void fwd_dr(AdjArgs a) { fwd_dr_at(a, global_id()); }
-__global__ void fwd_force(AdjArgs a) { fwd_force_at(a, global_id()); }
-__global__ void rev_collision(AdjArgs a) { rev_collision_at(a, global_id()); }
-__global__ void rev_velocity_force(AdjArgs a) { rev_velocity_force_at(a, global_id()); }
-__global__ void rev_dr(AdjArgs a) { rev_dr_at(a, global_id()); }
+__global__ __launch_bounds__(kAdjBlock) void fwd_moments(AdjArgs a) { fwd_moments_at(a, global_id()); }
+__global__ __launch_bounds__(kAdjBlock) void fwd_dr(AdjArgs a) { fwd_dr_at(a, global_id()); }
+__global__ __launch_bounds__(kAdjBlock) void fwd_force(AdjArgs a) { fwd_force_at(a, global_id()); }
+__global__ __launch_bounds__(kAdjBlock) void rev_collision(AdjArgs a) { rev_collision_at(a, global_id()); }
+__global__ __launch_bounds__(kAdjBlock) void rev_velocity_force(AdjArgs a) { rev_velocity_force_at(a, global_id()); }
+__global__ __launch_bounds__(kAdjBlock) void rev_dr(AdjArgs a) { rev_dr_at(a, global_id()); }
 
 // In a run, the reverse kernels of step t share their launches with the
 // recomputation of step t - 1, whose fields go to the other forward block:
 // the two parts of a launch touch no common field.
-__global__ void rev_collision_fwd_moments(AdjArgs ar, AdjArgs af, int fwd) {
+__global__ __launch_bounds__(kAdjBlock) void rev_collision_fwd_moments(AdjArgs ar, AdjArgs af, int fwd) {
     const long long g = global_id();
     rev_collision_at(ar, g);
     if (fwd) fwd_moments_at(af, g);
 }
-__global__ void rev_velocity_force_fwd_dr(AdjArgs ar, AdjArgs af, int fwd) {
+__global__ __launch_bounds__(kAdjBlock) void rev_velocity_force_fwd_dr(AdjArgs ar, AdjArgs af, int fwd) {
     const long long g = global_id();
     rev_velocity_force_at(ar, g);
     if (fwd) fwd_dr_at(af, g);
 }
-__global__ void rev_dr_fwd_force(AdjArgs ar, AdjArgs af, int fwd) {
+__global__ __launch_bounds__(kAdjBlock) void rev_dr_fwd_force(AdjArgs ar, AdjArgs af, int fwd) {
     const long long g = global_id();
     rev_dr_at(ar, g);
     if (fwd) fwd_force_at(af, g);
 }
 
-// adjoint of extended psi at extended row e, column z (before folding)
-__device__ double psi_ext_adjoint(const AdjArgs& a, int z, int e) {
+// adjoint of extended psi at extended row e, column z (before folding);
+// kAll: 2 <= e <= nr - 3, every tap of the three gathers lies inside
+template <bool kAll>
+__device__ double psi_ext_adjoint_t(const AdjArgs& a, int z, int e) {
     const double* w = a.w;
     const long long n = a.n;
     const int nz = a.nz, nr = a.nr;
@@ -476,8 +523,8 @@ __device__ double psi_ext_adjoint(const AdjArgs& a, int z, int e) {
         const int c = lbm::cr(i);
         if (c == 0) continue;
         const int y1 = e - lbm::cr(i), y2 = e - 2 * lbm::cr(i);
-        if (y1 >= -2 && y1 < nr + 2) s += (8.0 * c / 36.0) * drb[eidx(y1, wrapz(z - lbm::cz(i), nz), nz)];
-        if (y2 >= -2 && y2 < nr + 2) s -= (c / 36.0) * drb[eidx(y2, wrapz(z - 2 * lbm::cz(i), nz), nz)];
+        if (kAll || (y1 >= -2 && y1 < nr + 2)) s += (8.0 * c / 36.0) * drb[eidx(y1, wrapz(z - lbm::cz(i), nz), nz)];
+        if (kAll || (y2 >= -2 && y2 < nr + 2)) s -= (c / 36.0) * drb[eidx(y2, wrapz(z - 2 * lbm::cz(i), nz), nz)];
     }
     // 1D d_r psi on real rows: (-p(y+2) + 8 p(y+1) - 8 p(y-1) + p(y-2)) / 12
     const double* d1b = fptr(a, S_D1B);
@@ -485,7 +532,7 @@ __device__ double psi_ext_adjoint(const AdjArgs& a, int z, int e) {
     const double cf[4] = {-1.0, 8.0, -8.0, 1.0};
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        if (ys[k] >= 0 && ys[k] < nr) s += (cf[k] / 12.0) * d1b[(long long)ys[k] * nz + z];
+        if (kAll || (ys[k] >= 0 && ys[k] < nr)) s += (cf[k] / 12.0) * d1b[(long long)ys[k] * nz + z];
     // Shan–Chen force: F^SC(x) = -G psi(x) sum_i W_i psi(x + c_i) c_i
     const double* fzb = fptr(a, S_FSCZB);
     const double* frb = fptr(a, S_FSCRB);
@@ -493,37 +540,45 @@ __device__ double psi_ext_adjoint(const AdjArgs& a, int z, int e) {
 #pragma unroll
     for (int i = 1; i < lbm::kQ; ++i) {
         const int ysrc = e - lbm::cr(i);
-        if (ysrc < 0 || ysrc >= nr) continue;
+        if (!kAll && (ysrc < 0 || ysrc >= nr)) continue;
         const long long xs = (long long)ysrc * nz + wrapz(z - lbm::cz(i), nz);
         s += -a.G * psi[xs] * lbm::weight(i) * (fzb[xs] * lbm::cz(i) + frb[xs] * lbm::cr(i));
     }
     return s;
+}
+__device__ double psi_ext_adjoint(const AdjArgs& a, int z, int e) {
+    return (e >= 2 && e <= a.nr - 3) ? psi_ext_adjoint_t<true>(a, z, e) : psi_ext_adjoint_t<false>(a, z, e);
 }
 
 // step 4 for psi (fold every image of the row), step 5, write lam
 // Last reverse kernel: lam = f-bar + rho-bar + c . j-bar, and the block's
 // partial sums of the node contributions to dL/dG and dL/dtau (a fixed
 // tree order, so the result does not depend on scheduling).
-__global__ void rev_psi_final(AdjArgs a) {
+__global__ __launch_bounds__(kAdjBlock) void rev_psi_final(AdjArgs a) {
     const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double* w = a.w;
     const long long n = a.n;
     double g = 0.0, q = 0.0;
     if (x < n) {
         const int nr = a.nr;
-        const int r = (int)(x / a.nz), z = (int)(x - (long long)r * a.nz);
-        double psib = fptr(a, S_PSIB_LOC)[x] + psi_ext_adjoint(a, z, r);
-        if (r <= 3) psib += psi_ext_adjoint(a, z, -1 - r);            // axis images (rows -4..-1)
-        if (r >= nr - 4) psib += psi_ext_adjoint(a, z, 2 * nr - 1 - r);  // wall images (rows nr..nr+3)
-        const double rho = fptr(a, S_RHO)[x];
-        const double rhob = fptr(a, S_RHOB)[x] + psib * exp(-rho / a.rho0);
+        const int r = (int)x / a.nz, z = (int)x - r * a.nz;
+        // the node's own fields first, so that no load waits behind the
+        // stores of lam (which could alias them for all the compiler knows)
+        const double psib_loc = fptr(a, S_PSIB_LOC)[x];
+        const double rho = fptr(a, S_RHO)[x], rhob_loc = fptr(a, S_RHOB)[x];
         const double jzb = fptr(a, S_JZB)[x], jrb = fptr(a, S_JRB)[x];
         const double* fbar = w + fbar_off(n, a.ne);
+        double fb[lbm::kQ];
 #pragma unroll
-        for (int i = 0; i < lbm::kQ; ++i)
-            a.lam[i * n + x] = fbar[i * n + x] + rhob + lbm::cz(i) * jzb + lbm::cr(i) * jrb;
+        for (int i = 0; i < lbm::kQ; ++i) fb[i] = fbar[i * n + x];
         g = fptr(a, S_GB)[x];
         q = fptr(a, S_TAUB)[x];
+        double psib = psib_loc + psi_ext_adjoint(a, z, r);
+        if (r <= 3) psib += psi_ext_adjoint(a, z, -1 - r);            // axis images (rows -4..-1)
+        if (r >= nr - 4) psib += psi_ext_adjoint(a, z, 2 * nr - 1 - r);  // wall images (rows nr..nr+3)
+        const double rhob = rhob_loc + psib * exp(-rho / a.rho0);
+#pragma unroll
+        for (int i = 0; i < lbm::kQ; ++i) a.lam[i * n + x] = fb[i] + rhob + lbm::cz(i) * jzb + lbm::cr(i) * jrb;
     }
     __shared__ double s[2][kAdjBlock];
     const int t = threadIdx.x;
@@ -699,7 +754,9 @@ void launch_reverse_step(AdjArgs a, const double* f, const double* lam_next, dou
 
 int check_adjoint(const lbm_axi_params* p, size_t ws_bytes) {
     if (!p) return LBM_AXI_EINVAL;
-    if (p->nz < 1 || p->nr < 6 || !(p->tau > 0.5) || !(p->psi_rho0 > 0.0)) return LBM_AXI_EINVAL;
+    if (p->nz < 4 || p->nr < 6 || !(p->tau > 0.5) || !(p->psi_rho0 > 0.0)) return LBM_AXI_EINVAL;
+    // node indices are split with 32-bit arithmetic
+    if ((long long)p->nz * (p->nr + 2 * NGA) > INT_MAX) return LBM_AXI_EINVAL;
     if (p->wall != 0 && p->wall != 1) return LBM_AXI_EINVAL;
     if (p->precision != LBM_AXI_FP64 || p->flags != 0) return LBM_AXI_EUNSUP;
     if (ws_bytes < lbm_axi_adjoint_workspace_bytes(p->nz, p->nr)) return LBM_AXI_ENOMEM;
@@ -711,7 +768,7 @@ int check_adjoint(const lbm_axi_params* p, size_t ws_bytes) {
 extern "C" {
 
 size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr) {
-    if (nz < 1 || nr < 6) return 0;
+    if (nz < 4 || nr < 6 || (long long)nz * (nr + 2 * NGA) > INT_MAX) return 0;
     const long long n = (long long)nz * nr, ne = (long long)nz * (nr + 2 * NGA);
     const size_t nparts = (size_t)((n + kAdjBlock - 1) / kAdjBlock);
     return (2 * fwd_block(n, ne) + fbar_off(n, ne) + 9 * (size_t)n + 4 * nparts) * sizeof(double);

@@ -117,3 +117,18 @@ def test_batch_rejects_midlink_source():
     ps = (L.Params * 2)(L.make_params(64, 32), L.make_params(64, 32, flags=L.FLAG_MIDLINK))
     assert B._lib.lbm_axi_batch_workspace_bytes(ps, 2) == 0
     assert "MIDLINK" in L.last_error()
+
+
+def test_adjoint_size_limits():
+    """The adjoint's stencils wrap at most two columns: it takes nz >= 4 and
+    nr >= 6; smaller grids get no workspace size, and the calls return
+    LBM_AXI_EINVAL before any device work."""
+    from paper_1310_1871_amd import adjoint as A
+    from paper_1310_1871_amd import lbm_axi as L
+    ws = A._lib.lbm_axi_adjoint_workspace_bytes
+    assert ws(4, 6) > 0 and ws(5, 8) > ws(4, 6)
+    assert ws(3, 64) == 0 and ws(64, 5) == 0 and ws(1, 64) == 0
+    p = L.make_params(3, 64)
+    dummy = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    rc = A._lib.lbm_axi_adjoint_step(ctypes.byref(p), dummy, dummy, ctypes.c_void_p(32), None, dummy, 1 << 20, None)
+    assert rc == L.EINVAL
