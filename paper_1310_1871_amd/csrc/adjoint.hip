@@ -390,6 +390,16 @@ __device__ __forceinline__ void rev_velocity_force_at(const AdjArgs& a, const lo
     const long long n = a.n;
     const int nz = a.nz, nr = a.nr;
     double uzb = fptr(a, S_UZB_H)[x], urb = fptr(a, S_URB_H)[x];
+    // the node's own fields, loaded together with the gathers below
+    const double rho = fptr(a, S_RHO)[x];
+    const double uz = fptr(a, S_UZ)[x], ur = fptr(a, S_UR)[x];
+    const double jzb0 = fptr(a, S_JZB)[x], jrb0 = fptr(a, S_JRB)[x];
+    const double Fzb0 = fptr(a, S_FZB)[x], Frb0 = fptr(a, S_FRB)[x];
+    const double rhob0 = fptr(a, S_RHOB)[x];
+    const double psi = fptr(a, S_PSI)[x];
+    const double sz = fptr(a, S_SCZ)[x], sr = fptr(a, S_SCR)[x];
+    const double dzr = fptr(a, S_DZR)[x], drr = fptr(a, S_DRR)[x];
+    const double dr1 = eptr(a, E_DR)[eidx(r, z, nz)];
     if (a.axisym) {
         // images of row r in the extended velocity fields (reach 2)
         const double* druzb = fptr(a, S_DRUZB);
@@ -412,24 +422,18 @@ __device__ __forceinline__ void rev_velocity_force_at(const AdjArgs& a, const lo
         if (r <= 1) gather(-1 - r, -1.0);          // axis image: u_r odd
         if (r >= nr - 2) gather(2 * nr - 1 - r, 1.0);  // wall image
     }
-    const double rho = fptr(a, S_RHO)[x];
-    const double uz = fptr(a, S_UZ)[x], ur = fptr(a, S_UR)[x];
-    double jzb = fptr(a, S_JZB)[x] + uzb / rho;
-    double jrb = fptr(a, S_JRB)[x] + urb / rho;
-    double Fzb = fptr(a, S_FZB)[x] + 0.5 * uzb / rho;
-    double Frb = fptr(a, S_FRB)[x] + 0.5 * urb / rho;
-    double rhob = fptr(a, S_RHOB)[x] - (uzb * uz + urb * ur) / rho;
+    double jzb = jzb0 + uzb / rho;
+    double jrb = jrb0 + urb / rho;
+    double Fzb = Fzb0 + 0.5 * uzb / rho;
+    double Frb = Frb0 + 0.5 * urb / rho;
+    double rhob = rhob0 - (uzb * uz + urb * ur) / rho;
     // F = F^SC + F^sym + rho g z^
     rhob += Fzb * a.gz;
-    const double psi = fptr(a, S_PSI)[x];
-    const double sz = fptr(a, S_SCZ)[x], sr = fptr(a, S_SCR)[x];
     double Gb = -psi * (Fzb * sz + Frb * sr);
     double psib = -a.G * (Fzb * sz + Frb * sr);
     double dzrb = 0, drrb = 0, dr1b = 0;
     if (a.axisym) {
         const double rr = r + 0.5;
-        const double dzr = fptr(a, S_DZR)[x], drr = fptr(a, S_DRR)[x];
-        const double dr1 = eptr(a, E_DR)[eidx(r, z, nz)];
         const double g18 = a.G / 18.0;
         // F^sym_z = -(G/18) psi d_zr / r
         Gb += Fzb * (-psi * dzr / (18.0 * rr));
@@ -491,7 +495,9 @@ __global__ __launch_bounds__(kAdjBlock) void rev_dr(AdjArgs a) { rev_dr_at(a, gl
 
 // In a run, the reverse kernels of step t share their launches with the
 // recomputation of step t - 1, whose fields go to the other forward block:
-// the two parts of a launch touch no common field.
+// the two parts of a launch touch no common field.  (Giving the two parts
+// separate workgroups of one launch, or issuing the recomputation's loads
+// ahead of the reverse part, was no faster.)
 __global__ __launch_bounds__(kAdjBlock) void rev_collision_fwd_moments(AdjArgs ar, AdjArgs af, int fwd) {
     const long long g = global_id();
     rev_collision_at(ar, g);
