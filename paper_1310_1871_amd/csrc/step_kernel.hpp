@@ -7,7 +7,8 @@
 //      halo rows below the axis and above the wall hold the mirrored values
 //      (symmetry rule at the axis, zero-derivative rule at the wall,
 //      Sec. II.E), columns wrap periodically;
-//   2. the isotropic d_r psi on a 4-node halo (Sec. II.D, first stencil);
+//   2. the isotropic d_r psi on a 4-node halo (Sec. II.D, first stencil),
+//      and the 1D fourth-order d_r psi that d_zr differences along z;
 //   3. the total force F = F^SC (Eq. scforce) + F^{gamma,sym}
 //      (Eq. scAxisExtra, with d_rr = isotropic d_r of d_r and d_zr = 1D d_z of
 //      1D d_r, Sec. II.D) + rho g z^, and the hydrodynamic velocity
@@ -190,6 +191,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
 
     __shared__ C s_psi[PR * PZ];
     __shared__ C s_dr[DR * DZ];
+    __shared__ C s_d1[DR * DZ];  // 1D fourth-order d_r psi (rows 2 .. DR-3 used)
     __shared__ C s_uz[UR * UZ];
     __shared__ C s_ur[UR * UZ];
     __shared__ C s_mom[3][NU];  // rho, j_z, j_r of the velocity-ring nodes
@@ -315,10 +317,17 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     for (int k = 0; k < NPT; ++k) s_psi[(lrb + k * RSTEP + 6) * PZ + lz + 6] = psi_of(rho_of(f[k]));
     __syncthreads();
 
-    // ---- 2. isotropic d_r psi on the 4-node halo -------------------------
+    // ---- 2. isotropic d_r psi on the 4-node halo, and the 1D d_r psi that
+    // the mixed derivative d_zr differences along z ----------------------
     for (int idx = t; idx < DR * DZ; idx += NT) {
         const int y = idx / DZ, x = idx - y * DZ;
         s_dr[idx] = d_iso<true>(s_psi, y + 2, x + 2, PZ);
+        if (y >= 2 && y < DR - 2) {
+            const int c = x + 2;  // psi-window column; rows y .. y + 4
+            s_d1[idx] = (-s_psi[(y + 4) * PZ + c] + C(8) * s_psi[(y + 3) * PZ + c] - C(8) * s_psi[(y + 1) * PZ + c] +
+                         s_psi[y * PZ + c]) *
+                        C(1.0 / 12.0);
+        }
     }
     __syncthreads();
 
@@ -346,14 +355,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             const C dr1 = s_dr[dy * DZ + dx];
             const C drr = d_iso<true>(s_dr, dy, dx, DZ);
             // mixed derivative: 1D fourth-order d_z of the 1D fourth-order d_r
-            C d1[5];
-#pragma unroll
-            for (int m = 0; m < 5; ++m) {
-                const int xx = px - 2 + m;
-                d1[m] = (-s_psi[(py + 2) * PZ + xx] + C(8) * s_psi[(py + 1) * PZ + xx] -
-                         C(8) * s_psi[(py - 1) * PZ + xx] + s_psi[(py - 2) * PZ + xx]) *
-                        C(1.0 / 12.0);
-            }
+            const C* d1 = s_d1 + dy * DZ + dx - 2;
             const C dzr = (-d1[4] + C(8) * d1[3] - C(8) * d1[1] + d1[0]) * C(1.0 / 12.0);
             const C inv_r = dev_rcp(rr);
             const C pre = -g18 * psi;

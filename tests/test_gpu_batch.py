@@ -197,3 +197,33 @@ def test_full_ensemble_runs_finite():
         assert torch.isfinite(rho).all() and torch.isfinite(uz).all(), k
         assert float(uz.abs().max()) < 0.2
     b.close()
+
+
+@pytest.mark.parametrize("prec_name,nz,nr", [("fp32", 4096, 512), ("fp32", 4100, 515), ("fp64", 4100, 515)])
+def test_large_lattice_path_matches_batch_kernel(prec_name, nz, nr):
+    """The single-lattice step on a large lattice uses 64 x 16 tiles of 512
+    threads: in FP32 each XCD takes a slab of tile columns (4096 x 512), or
+    runs of whole tile rows when 8 does not divide the tile columns (65 of
+    them at 4100 x 515); in FP64 runs of tile rows.  The batch kernel with
+    its 64 x 16 / 512 configuration runs the same tile body with another
+    mapping of workgroups to tiles and another store policy, so after 4
+    steps the two must agree bit for bit: a tile done twice, or left out,
+    would show."""
+    L, B = _libs()
+    fp32 = prec_name == "fp32"
+    G = -5.5
+    rg, rl = coexistence_densities(G)
+    rho = thread_density(nz, nr, 64.0, rl, rg, 2.0, 0.1, 1)
+    p = L.make_params(nz, nr, G=G, tau=0.8, wall=L.WALL_FREESLIP,
+                      precision=L.FP32_SHIFTED if fp32 else L.FP64, rho_ref=rg if fp32 else 0.0)
+    _say(f"large-lattice path vs batch kernel: {prec_name} {nz}x{nr}")
+    sim = L.AxiLBM(p, torch.from_numpy(rho).cuda())
+    sim.step(4)
+    single = sim.populations()
+    sim.close()
+    b = B.AxiBatch([p], [torch.from_numpy(rho).cuda()])
+    b.set_schedule(b.configs().index((64, 16, 512)), 2, 0)
+    b.step(4)
+    batched = b.populations(0)
+    b.close()
+    assert torch.equal(single, batched)
