@@ -434,6 +434,9 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     }
 
     // ---- 4. collision + streaming (or moments) for the tile nodes --------
+    // (uniform over the workgroup) no tile row is the axis row or the wall
+    // row, no push crosses the ends of z, and no z walls
+    const bool plain = !zwalls && r0 >= 1 && r0 + TR <= nr - 1 && z0 >= 1 && z0 + TZ <= nz - 1;
     const C tau = C(a.tau);
     const C inv_tau = C(1) / tau;
     const C mu_fac = (tau - C(0.5)) * C(1.0 / 3.0);  // mu = rho c_s^2 (tau - 1/2)
@@ -570,28 +573,49 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
                     const C e = w * brho * (C(1) + C(3) * cb + C(4.5) * cb * cb - bqq);
                     fs = P::kShift ? e - w * rho_ref : e;
                 }
-                // push to the neighbour with the pre-streaming boundary rules
-                int tz = gz + cz(i), trr = gr + cr(i), d = i;
-                if (zwalls && (tz < 0 || tz >= nz)) {
-                    // a z wall: the population returns to its node reversed
-                    tz = gz;
-                    trr = gr;
-                    d = opposite(i);
-                } else if (cr(i) < 0 && gr == 0) {
-                    trr = 0;
-                    d = mirror_r(i);
-                } else if (cr(i) > 0 && gr == nr - 1) {
-                    if (a.wall == 0) {
+                f[k][i] = fs;  // the pre-collision value is not read again
+            }
+            // push to the neighbours with the pre-streaming boundary rules.
+            // A tile that holds neither the axis row nor the wall row and
+            // needs no wrap in z sends population i to (z + c_z, r + c_r)
+            // in plane i: one vector offset for all nine stores, the
+            // displacement folded into the scalar offset.
+            if (plain) {
+                const unsigned node_off = (unsigned)(gr * nz + gz) * (unsigned)sizeof(S);
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) {
+                    // i * plane + displacement is the (non-negative) offset of the
+                    // target in plane i; unsigned wrap-around adds the signed
+                    // displacement exactly
+                    const unsigned disp = (unsigned)((cr(i) * nz + cz(i)) * (int)sizeof(S));
+                    buf_store<kStoreAux>(fout, node_off, (unsigned)i * plane_bytes + disp, S(f[k][i]));
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) {
+                    int tz = gz + cz(i), trr = gr + cr(i), d = i;
+                    if (zwalls && (tz < 0 || tz >= nz)) {
+                        // a z wall: the population returns to its node reversed
                         tz = gz;
                         trr = gr;
                         d = opposite(i);
-                    } else {
+                    } else if (cr(i) < 0 && gr == 0) {
+                        trr = 0;
                         d = mirror_r(i);
-                        trr = gr;
+                    } else if (cr(i) > 0 && gr == nr - 1) {
+                        if (a.wall == 0) {
+                            tz = gz;
+                            trr = gr;
+                            d = opposite(i);
+                        } else {
+                            d = mirror_r(i);
+                            trr = gr;
+                        }
                     }
+                    tz = tz < 0 ? tz + nz : (tz >= nz ? tz - nz : tz);
+                    buf_store<kStoreAux>(fout, (unsigned)(trr * nz + tz) * (unsigned)sizeof(S), d * plane_bytes,
+                                         S(f[k][i]));
                 }
-                tz = tz < 0 ? tz + nz : (tz >= nz ? tz - nz : tz);
-                buf_store<kStoreAux>(fout, (unsigned)(trr * nz + tz) * (unsigned)sizeof(S), d * plane_bytes, S(fs));
             }
         }
     }
