@@ -265,10 +265,10 @@ int lbm_axi_batch_create(const lbm_axi_params* ps, int32_t n_inst, const double*
         const int blocks = (int)((n + 255) / 256);
         if (b->precision == LBM_AXI_FP64)
             hipLaunchKernelGGL(init_equilibrium_kernel<lbm::PrecF64>, dim3(blocks), dim3(256), 0, b->stream,
-                               static_cast<double*>(b->buf(k, 0)), h_d_rho0[k], nullptr, nullptr, n, 0.0);
+                               static_cast<double*>(b->buf(k, 0)), h_d_rho0[k], nullptr, nullptr, n, n, 0.0);
         else
             hipLaunchKernelGGL(init_equilibrium_kernel<lbm::PrecF32S>, dim3(blocks), dim3(256), 0, b->stream,
-                               static_cast<float*>(b->buf(k, 0)), h_d_rho0[k], nullptr, nullptr, n, ps[k].rho_ref);
+                               static_cast<float*>(b->buf(k, 0)), h_d_rho0[k], nullptr, nullptr, n, n, ps[k].rho_ref);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {

@@ -44,11 +44,16 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 inline size_t storage_size(int precision) { return precision == LBM_AXI_FP64 ? sizeof(double) : sizeof(float); }
 
+// padding, in elements, of each population plane in the single-lattice
+// library's own buffers (see lbm_axi.hip)
+constexpr long long kPlanePad = 1024;
+
 inline int check_params(const lbm_axi_params* p) {
     if (!p) return fail(LBM_AXI_EINVAL, "params is NULL");
     if (p->nz < 1) return fail(LBM_AXI_EINVAL, "nz must be >= 1 (got %d)", p->nz);
     if (p->nr < 6) return fail(LBM_AXI_EINVAL, "nr must be >= 6 for the derivative stencils (got %d)", p->nr);
-    if (9.0 * (double)p->nz * (double)p->nr * (p->precision == LBM_AXI_FP64 ? 8.0 : 4.0) >= 4294967296.0)
+    // (with room for the padding of the single-lattice buffers' planes)
+    if (9.0 * ((double)p->nz * (double)p->nr + (double)kPlanePad) * (p->precision == LBM_AXI_FP64 ? 8.0 : 4.0) >= 4294967296.0)
         return fail(LBM_AXI_EINVAL, "grid too large: the population state must stay below 4 GiB");
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_AXI_EINVAL, "tau must be > 1/2 (got %g)", p->tau);
     if (!std::isfinite(p->G)) return fail(LBM_AXI_EINVAL, "G must be finite");
@@ -84,7 +89,7 @@ inline int option_bits(int flags) {
 // f_i = f^eq_i(rho, u) with u^eq = u (initial state, no force shift)
 template <class P>
 __global__ void init_equilibrium_kernel(typename P::S* f, const double* rho, const double* uz,
-                                        const double* ur, long long n, double rho_ref) {
+                                        const double* ur, long long n, long long pitch, double rho_ref) {
     const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const double r = rho[x];
@@ -97,7 +102,7 @@ __global__ void init_equilibrium_kernel(typename P::S* f, const double* rho, con
         const double poly = 3.0 * cu + 4.5 * cu * cu - qq;
         const double w = lbm::weight(i);
         double v = P::kShift ? w * ((r - rho_ref) + r * poly) : w * r * (1.0 + poly);
-        f[(long long)i * n + x] = typename P::S(v);
+        f[(long long)i * pitch + x] = typename P::S(v);
     }
 }
 

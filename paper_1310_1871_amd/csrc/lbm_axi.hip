@@ -40,8 +40,15 @@ int tiles_of(const lbm_axi_params* p, int c) {
     return ((p->nz + kShape[c].tz - 1) / kShape[c].tz) * ((p->nr + kShape[c].tr - 1) / kShape[c].tr);
 }
 
+// Population planes inside the library are padded by kPlanePad elements: planes
+// exactly 2^k bytes apart (16 MiB at 4096 x 512 in FP64) map the same node
+// of every plane onto the same memory channels.  A padded pitch made the
+// 4096 x 512 step 5% faster in FP64 and 8% in FP32.  The state a caller
+// sees (get/set_state, record) keeps the plain [9][nr][nz] layout.
 struct Layout {
-    size_t state_bytes;   // one population buffer
+    size_t state_bytes;   // the caller's view of one state: 9 nz nr values
+    long long pitch;      // plane pitch of the library's buffers (nz nr + kPlanePad)
+    size_t buf_bytes;     // one population buffer: 9 pitch values
     size_t off_b;         // second buffer
     size_t off_partials;  // [max blocks][4] doubles
     size_t off_red;       // [4] doubles
@@ -59,13 +66,15 @@ Layout layout_of(const lbm_axi_params* p, int cfg) {
     Layout L{};
     const size_t n = (size_t)p->nz * p->nr;
     L.state_bytes = 9 * n * storage_size(p->precision);
+    L.pitch = (long long)n + kPlanePad;
+    L.buf_bytes = 9 * (size_t)L.pitch * storage_size(p->precision);
     L.cfg = cfg;
     L.tiles_z = (p->nz + kShape[cfg].tz - 1) / kShape[cfg].tz;
     L.tiles_r = (p->nr + kShape[cfg].tr - 1) / kShape[cfg].tr;
     L.nblocks = L.tiles_z * L.tiles_r;
     const int max_blocks = tiles_of(p, 1) > tiles_of(p, 0) ? tiles_of(p, 1) : tiles_of(p, 0);
-    L.off_b = align_up(L.state_bytes);
-    L.off_partials = L.off_b + align_up(L.state_bytes);
+    L.off_b = align_up(L.buf_bytes);
+    L.off_partials = L.off_b + align_up(L.buf_bytes);
     L.off_red = L.off_partials + align_up((size_t)max_blocks * 4 * sizeof(double));
     L.off_iface = L.off_red + align_up(4 * sizeof(double));
     L.off_open = L.off_iface + align_up((2 * (size_t)p->nz + 8 + 1 + 2 * LBM_AXI_MAX_DROPS) * sizeof(double));
@@ -239,8 +248,8 @@ void* state_ptr(lbm_axi_ctx* h, int which) { return h->ws + (which == 0 ? 0 : h-
 
 lbm::StepArgs make_args(lbm_axi_ctx* h) {
     lbm::StepArgs a{};
-    a.plane = (long long)h->p.nz * h->p.nr;
-    a.state_bytes = (unsigned)h->L.state_bytes;
+    a.plane = h->L.pitch;
+    a.state_bytes = (unsigned)h->L.buf_bytes;
     a.nz = h->p.nz;
     a.nr = h->p.nr;
     a.tiles_z = h->L.tiles_z;
@@ -350,10 +359,10 @@ int lbm_axi_create(const lbm_axi_params* p, const double* d_rho0, const double* 
     const double rho_ref = p->precision == LBM_AXI_FP64 ? 0.0 : p->rho_ref;
     if (p->precision == LBM_AXI_FP64)
         hipLaunchKernelGGL(init_equilibrium_kernel<lbm::PrecF64>, dim3(blocks), dim3(threads), 0, h->stream,
-                           static_cast<double*>(state_ptr(h, 0)), d_rho0, d_uz0, d_ur0, n, rho_ref);
+                           static_cast<double*>(state_ptr(h, 0)), d_rho0, d_uz0, d_ur0, n, L.pitch, rho_ref);
     else
         hipLaunchKernelGGL(init_equilibrium_kernel<lbm::PrecF32S>, dim3(blocks), dim3(threads), 0, h->stream,
-                           static_cast<float*>(state_ptr(h, 0)), d_rho0, d_uz0, d_ur0, n, rho_ref);
+                           static_cast<float*>(state_ptr(h, 0)), d_rho0, d_uz0, d_ur0, n, L.pitch, rho_ref);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         delete h;
@@ -414,7 +423,7 @@ int lbm_axi_interface(lbm_axi_t h, double rho_mid, int32_t z_col, double* d_radi
     double* radius = d_radius ? d_radius : scratch;
     double* rho_axis = scratch + h->p.nz;
     double* d_out = scratch + 2 * (size_t)h->p.nz;
-    const long long plane = (long long)h->p.nz * h->p.nr;
+    const long long plane = h->L.pitch;
     const double rho_ref = h->p.precision == LBM_AXI_FP64 ? 0.0 : h->p.rho_ref;
     const dim3 cols((h->p.nz + 255) / 256);
     if (h->p.precision == LBM_AXI_FP64) {
@@ -476,7 +485,7 @@ int lbm_axi_drops(lbm_axi_t h, double rho_mid, int32_t max_drops, int32_t* h_cou
     double* radius = scratch;
     double* rho_axis = scratch + h->p.nz;
     double* d_out = scratch + 2 * (size_t)h->p.nz + 8;
-    const long long plane = (long long)h->p.nz * h->p.nr;
+    const long long plane = h->L.pitch;
     const double rho_ref = h->p.precision == LBM_AXI_FP64 ? 0.0 : h->p.rho_ref;
     const dim3 cols((h->p.nz + 255) / 256);
     if (h->p.precision == LBM_AXI_FP64) {
@@ -507,19 +516,27 @@ int lbm_axi_drops(lbm_axi_t h, double rho_mid, int32_t max_drops, int32_t* h_cou
 
 size_t lbm_axi_state_bytes(lbm_axi_t h) { return h ? h->L.state_bytes : 0; }
 
+namespace {
+// the nine planes between the library's padded buffers and the caller's
+// plain [9][nr][nz] layout
+hipError_t copy_planes(lbm_axi_ctx* h, void* dst, bool dst_padded, const void* src, bool src_padded) {
+    const size_t row = h->L.state_bytes / 9, padded = h->L.buf_bytes / 9;
+    return hipMemcpy2DAsync(dst, dst_padded ? padded : row, src, src_padded ? padded : row, row, 9,
+                            hipMemcpyDeviceToDevice, h->stream);
+}
+}  // namespace
+
 int lbm_axi_get_state(lbm_axi_t h, void* d_dst) {
     if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
     if (!d_dst) return fail(LBM_AXI_EINVAL, "d_dst is NULL");
-    HIP_TRY(hipMemcpyAsync(d_dst, state_ptr(h, h->cur), h->L.state_bytes, hipMemcpyDeviceToDevice, h->stream),
-            "get_state copy");
+    HIP_TRY(copy_planes(h, d_dst, false, state_ptr(h, h->cur), true), "get_state copy");
     return LBM_AXI_OK;
 }
 
 int lbm_axi_set_state(lbm_axi_t h, const void* d_src) {
     if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
     if (!d_src) return fail(LBM_AXI_EINVAL, "d_src is NULL");
-    HIP_TRY(hipMemcpyAsync(state_ptr(h, h->cur), d_src, h->L.state_bytes, hipMemcpyDeviceToDevice, h->stream),
-            "set_state copy");
+    HIP_TRY(copy_planes(h, state_ptr(h, h->cur), true, d_src, false), "set_state copy");
     return LBM_AXI_OK;
 }
 
@@ -527,19 +544,19 @@ int lbm_axi_record(lbm_axi_t h, int64_t n, void* d_states) {
     if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
     if (!d_states) return fail(LBM_AXI_EINVAL, "d_states is NULL");
     if (n < 1) return fail(LBM_AXI_EINVAL, "n must be >= 1");
-    // the steps write straight into the record: one copy in, one copy back
+    // the steps write straight into the record, in the caller's plain
+    // layout: one copy in, one copy back
     char* dst = static_cast<char*>(d_states);
     const size_t sb = h->L.state_bytes;
-    HIP_TRY(hipMemcpyAsync(dst, state_ptr(h, h->cur), sb, hipMemcpyDeviceToDevice, h->stream), "record copy");
-    const lbm::StepArgs a = make_args(h);
+    HIP_TRY(copy_planes(h, dst, false, state_ptr(h, h->cur), true), "record copy");
+    lbm::StepArgs a = make_args(h);
+    a.plane = (long long)h->p.nz * h->p.nr;
+    a.state_bytes = (unsigned)sb;
     for (int64_t j = 1; j < n; ++j) {
         const int rc = step_into(h, a, dst + (size_t)(j - 1) * sb, dst + (size_t)j * sb);
         if (rc != LBM_AXI_OK) return rc;
     }
-    if (n > 1)
-        HIP_TRY(hipMemcpyAsync(state_ptr(h, h->cur), dst + (size_t)(n - 1) * sb, sb, hipMemcpyDeviceToDevice,
-                               h->stream),
-                "record copy");
+    if (n > 1) HIP_TRY(copy_planes(h, state_ptr(h, h->cur), true, dst + (size_t)(n - 1) * sb, false), "record copy");
     return LBM_AXI_OK;
 }
 

@@ -37,7 +37,7 @@ struct StepArgs {
     double* uz_out;
     double* ur_out;
     double* partials;  // moments mode: [gridDim.x][4] block sums, may be null
-    long long plane;   // nz * nr
+    long long plane;   // population plane pitch in elements (>= nz * nr)
     unsigned state_bytes;  // 9 * plane * sizeof(storage) (< 4 GiB)
     int nz, nr;
     int tiles_z;       // tiles along z (tile id = tr * tiles_z + tz: z fastest)
@@ -479,9 +479,10 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             if (a.h_out) {
                 C hz = C(0), hr = C(0), mass = C(0);
                 if (a.axisym) source_terms(hz, hr, mass);
+                const long long hn = (long long)nz * nr;  // the H fields are [3][nr][nz]
                 a.h_out[x] = double(hz);
-                a.h_out[a.plane + x] = double(hr);
-                a.h_out[2 * a.plane + x] = double(mass);
+                a.h_out[hn + x] = double(hr);
+                a.h_out[2 * hn + x] = double(mass);
             }
             const double two_pi_r = 6.283185307179586 * double(rr);
             part[0] += two_pi_r * double(rho);
@@ -563,8 +564,9 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
                     int yz = gz + cz(i);
                     yz = yz < 0 ? yz + nz : (yz >= nz ? yz - nz : yz);
                     const long long y = (long long)yr * nz + yz;
-                    const C hy = w * (C(a.h_in[2 * a.plane + y]) +
-                                      C(3) * (C(cz(i)) * C(a.h_in[y]) + C(cr(i)) * sr * C(a.h_in[a.plane + y])));
+                    const long long hn = (long long)nz * nr;
+                    const C hy = w * (C(a.h_in[2 * hn + y]) +
+                                      C(3) * (C(cz(i)) * C(a.h_in[y]) + C(cr(i)) * sr * C(a.h_in[hn + y])));
                     hi += C(0.5) * (hy - hsrc);  // the source part only: (h_i(x) + h_i(y)) / 2
                 }
                 C fs = f[k][i] - (f[k][i] - feq) * inv_tau + hi;
