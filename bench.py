@@ -30,10 +30,11 @@ NZ, NR = 4096, 512
 G, TAU, RADIUS, EPS = -5.5, 0.8, 64.0, 0.1
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 BYTES_PER_LU = {"f64": 9 * 2 * 8, "f32": 9 * 2 * 4}  # read + write every population once
-# the kernel and the launch code that picks its tile shape, order and store
-# policy: a change to any of them invalidates the committed counter figures
+# the kernel, the launch code that picks its tile shape, order and store
+# policy, and the buffer layout: a change to any of them invalidates the
+# committed counter figures
 KERNEL_SOURCES = ("paper_1310_1871_amd/csrc/step_kernel.hpp", "paper_1310_1871_amd/csrc/lattice.hpp",
-                  "paper_1310_1871_amd/csrc/lbm_axi.hip")
+                  "paper_1310_1871_amd/csrc/lbm_axi.hip", "paper_1310_1871_amd/csrc/common.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_axi_step_4096x512.md")
 
 
