@@ -77,7 +77,14 @@ struct lbm_axi_batch {
 
     const Config& config() const { return precision == LBM_AXI_FP64 ? kCfg64[cfg] : kCfg32[cfg]; }
     int n_cfg() const { return precision == LBM_AXI_FP64 ? kNCfg64 : kNCfg32; }
+    // the caller's view of instance k's state: 9 nz nr values
     size_t state_bytes(int k) const { return 9 * (size_t)p[k].nz * p[k].nr * storage_size(precision); }
+    // the instance's buffers pad each plane by kPlanePadBytes, as the
+    // single-lattice library does (planes 2^k bytes apart share channels)
+    long long pitch(int k) const {
+        return (long long)p[k].nz * p[k].nr + kPlanePadBytes / (long long)storage_size(precision);
+    }
+    size_t buf_bytes(int k) const { return 9 * (size_t)pitch(k) * storage_size(precision); }
     void* buf(int k, int which) { return ws + off[which][k]; }
 };
 
@@ -88,7 +95,8 @@ size_t layout(const lbm_axi_params* ps, int32_t n, lbm_axi_batch* b) {
     const int prec = ps[0].precision;
     for (int w = 0; w < 3; ++w) {
         for (int k = 0; k < n; ++k) {
-            const size_t bytes = 9 * (size_t)ps[k].nz * ps[k].nr * storage_size(prec);
+            const size_t bytes =
+                9 * ((size_t)ps[k].nz * ps[k].nr + (size_t)kPlanePadBytes / storage_size(prec)) * storage_size(prec);
             if (b) b->off[w].push_back(off);
             off += align_up(bytes);
         }
@@ -128,8 +136,8 @@ lbm::StepArgs instance_args(lbm_axi_batch* b, int k, int parity) {
     lbm::StepArgs a{};
     a.fin = b->buf(k, parity);
     a.fout = b->buf(k, 1 - parity);
-    a.plane = (long long)p.nz * p.nr;
-    a.state_bytes = (unsigned)b->state_bytes(k);
+    a.plane = b->pitch(k);
+    a.state_bytes = (unsigned)b->buf_bytes(k);
     a.nz = p.nz;
     a.nr = p.nr;
     a.tiles_z = (p.nz + c.tz - 1) / c.tz;
@@ -220,7 +228,7 @@ int ensure_graph(lbm_axi_batch* b, int parity) {
 
 int copy_states(lbm_axi_batch* b, int from, int to) {
     for (size_t k = 0; k < b->p.size(); ++k)
-        HIP_TRY(hipMemcpyAsync(b->buf((int)k, to), b->buf((int)k, from), b->state_bytes((int)k),
+        HIP_TRY(hipMemcpyAsync(b->buf((int)k, to), b->buf((int)k, from), b->buf_bytes((int)k),
                                hipMemcpyDeviceToDevice, b->stream),
                 "batch state copy");
     return LBM_AXI_OK;
@@ -265,10 +273,10 @@ int lbm_axi_batch_create(const lbm_axi_params* ps, int32_t n_inst, const double*
         const int blocks = (int)((n + 255) / 256);
         if (b->precision == LBM_AXI_FP64)
             hipLaunchKernelGGL(init_equilibrium_kernel<lbm::PrecF64>, dim3(blocks), dim3(256), 0, b->stream,
-                               static_cast<double*>(b->buf(k, 0)), h_d_rho0[k], nullptr, nullptr, n, n, 0.0);
+                               static_cast<double*>(b->buf(k, 0)), h_d_rho0[k], nullptr, nullptr, n, b->pitch(k), 0.0);
         else
             hipLaunchKernelGGL(init_equilibrium_kernel<lbm::PrecF32S>, dim3(blocks), dim3(256), 0, b->stream,
-                               static_cast<float*>(b->buf(k, 0)), h_d_rho0[k], nullptr, nullptr, n, n, ps[k].rho_ref);
+                               static_cast<float*>(b->buf(k, 0)), h_d_rho0[k], nullptr, nullptr, n, b->pitch(k), ps[k].rho_ref);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -330,7 +338,8 @@ int lbm_axi_batch_moments(lbm_axi_batch_t b, int32_t k, double* d_rho, double* d
 
 int lbm_axi_batch_get_state(lbm_axi_batch_t b, int32_t k, void* d_dst) {
     if (!b || k < 0 || k >= (int)b->p.size() || !d_dst) return fail(LBM_AXI_EINVAL, "bad batch, instance or dst");
-    HIP_TRY(hipMemcpyAsync(d_dst, b->buf(k, b->parity), b->state_bytes(k), hipMemcpyDeviceToDevice, b->stream),
+    const size_t row = b->state_bytes(k) / 9, padded = b->buf_bytes(k) / 9;
+    HIP_TRY(hipMemcpy2DAsync(d_dst, row, b->buf(k, b->parity), padded, row, 9, hipMemcpyDeviceToDevice, b->stream),
             "get_state copy");
     return LBM_AXI_OK;
 }
