@@ -216,6 +216,39 @@ def test_state_roundtrip_and_resume():
     assert torch.equal(fa, b.populations())
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_padded_buffers_keep_the_plain_state_layout(fp32):
+    """The library pads every population plane of its own buffers; the
+    caller sees the plain [9][nr][nz] layout.  On a ragged 4100 x 515
+    lattice: a state set and read back is unchanged bit for bit; a record of
+    3 states starts with that state, and its last state is the handle's
+    state afterwards; a step on the handle equals a step in the record."""
+    L = _lib()
+    nz, nr = 4100, 515
+    rho, uz, ur = random_state_fields(515, nz, nr, rho_lo=0.5, rho_hi=1.5, u_amp=0.01)
+    p = L.make_params(nz, nr, G=-4.0, tau=0.9, wall=1, precision=L.FP32_SHIFTED if fp32 else L.FP64,
+                      rho_ref=0.5 if fp32 else 0.0)
+    _say(f"padded layout round trip {nz}x{nr} fp32={fp32}")
+    sim = L.AxiLBM(p, torch.from_numpy(rho).cuda(), torch.from_numpy(uz).cuda(), torch.from_numpy(ur).cuda())
+    sim.step(2)
+    s0 = sim.get_state()
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    noise = torch.rand(s0.numel() // (4 if fp32 else 8), generator=gen, device="cuda",
+                       dtype=torch.float32 if fp32 else torch.float64) * 1e-3
+    st = (s0.view(noise.dtype) + noise).view(torch.uint8)
+    sim.set_state(st)
+    assert torch.equal(sim.get_state(), st)
+    rec = torch.empty(3 * st.numel(), dtype=torch.uint8, device="cuda")
+    sim.record(3, rec)
+    n = st.numel()
+    assert torch.equal(rec[:n], st)
+    assert torch.equal(sim.get_state(), rec[2 * n:])
+    sim.set_state(rec[n:2 * n])
+    sim.step(1)
+    assert torch.equal(sim.get_state(), rec[2 * n:])
+    sim.close()
+
+
 @pytest.mark.parametrize("rho_val", [0.1, 2.3])
 @pytest.mark.parametrize("wall", [0, 1])
 def test_rest_state_invariant_on_gpu(wall, rho_val):
