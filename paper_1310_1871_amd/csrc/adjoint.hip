@@ -92,6 +92,10 @@ __host__ __device__ inline size_t run_off(long long n, long long ne) {
     return part_off(n, ne) + 2 * (size_t)((n + kAdjBlock - 1) / kAdjBlock);
 }
 
+// row clamped into [lo, hi] (the masked gathers below load a clamped row and
+// multiply its term by 0 when the row is outside: no branch around the load)
+__device__ __forceinline__ int clampi(int y, int lo, int hi) { return y < lo ? lo : (y > hi ? hi : y); }
+
 // periodic column: the stencils here reach at most 2 columns and the
 // adjoint requires nz >= 4, so one add or subtract wraps
 __device__ __forceinline__ int wrapz(int z, int nz) {
@@ -373,8 +377,15 @@ __device__ double iso_transpose_real_t(const double* src, int z, int e, int nz, 
         const int c = along_r ? lbm::cr(i) : lbm::cz(i);
         if (c == 0) continue;
         const int y1 = e - lbm::cr(i), y2 = e - 2 * lbm::cr(i);
-        if (kAll || (y1 >= 0 && y1 < nr)) s += 8.0 * c * src[(long long)y1 * nz + wrapz(z - lbm::cz(i), nz)];
-        if (kAll || (y2 >= 0 && y2 < nr)) s -= c * src[(long long)y2 * nz + wrapz(z - 2 * lbm::cz(i), nz)];
+        if (kAll) {
+            s += 8.0 * c * src[(long long)y1 * nz + wrapz(z - lbm::cz(i), nz)];
+            s -= c * src[(long long)y2 * nz + wrapz(z - 2 * lbm::cz(i), nz)];
+        } else {
+            // masked: a row outside the lattice contributes 0 x (a real value)
+            const double m1 = (y1 >= 0 && y1 < nr) ? 1.0 : 0.0, m2 = (y2 >= 0 && y2 < nr) ? 1.0 : 0.0;
+            s += 8.0 * c * m1 * src[(long long)clampi(y1, 0, nr - 1) * nz + wrapz(z - lbm::cz(i), nz)];
+            s -= c * m2 * src[(long long)clampi(y2, 0, nr - 1) * nz + wrapz(z - 2 * lbm::cz(i), nz)];
+        }
     }
     return s / 36.0;
 }
@@ -486,29 +497,29 @@ __device__ __forceinline__ void rev_dr_at(const AdjArgs& a, const long long gid)
 
 __device__ __forceinline__ long long global_id() { return (long long)blockIdx.x * blockDim.x + threadIdx.x; }
 
-__global__ __launch_bounds__(kAdjBlock) void fwd_moments(AdjArgs a) { fwd_moments_at(a, global_id()); }
-__global__ __launch_bounds__(kAdjBlock) void fwd_dr(AdjArgs a) { fwd_dr_at(a, global_id()); }
-__global__ __launch_bounds__(kAdjBlock) void fwd_force(AdjArgs a) { fwd_force_at(a, global_id()); }
-__global__ __launch_bounds__(kAdjBlock) void rev_collision(AdjArgs a) { rev_collision_at(a, global_id()); }
-__global__ __launch_bounds__(kAdjBlock) void rev_velocity_force(AdjArgs a) { rev_velocity_force_at(a, global_id()); }
-__global__ __launch_bounds__(kAdjBlock) void rev_dr(AdjArgs a) { rev_dr_at(a, global_id()); }
+__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void fwd_moments(AdjArgs a) { fwd_moments_at(a, global_id()); }
+__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void fwd_dr(AdjArgs a) { fwd_dr_at(a, global_id()); }
+__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void fwd_force(AdjArgs a) { fwd_force_at(a, global_id()); }
+__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void rev_collision(AdjArgs a) { rev_collision_at(a, global_id()); }
+__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void rev_velocity_force(AdjArgs a) { rev_velocity_force_at(a, global_id()); }
+__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void rev_dr(AdjArgs a) { rev_dr_at(a, global_id()); }
 
 // In a run, the reverse kernels of step t share their launches with the
 // recomputation of step t - 1, whose fields go to the other forward block:
 // the two parts of a launch touch no common field.  (Giving the two parts
 // separate workgroups of one launch, or issuing the recomputation's loads
 // ahead of the reverse part, was no faster.)
-__global__ __launch_bounds__(kAdjBlock) void rev_collision_fwd_moments(AdjArgs ar, AdjArgs af, int fwd) {
+__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void rev_collision_fwd_moments(AdjArgs ar, AdjArgs af, int fwd) {
     const long long g = global_id();
     rev_collision_at(ar, g);
     if (fwd) fwd_moments_at(af, g);
 }
-__global__ __launch_bounds__(kAdjBlock) void rev_velocity_force_fwd_dr(AdjArgs ar, AdjArgs af, int fwd) {
+__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void rev_velocity_force_fwd_dr(AdjArgs ar, AdjArgs af, int fwd) {
     const long long g = global_id();
     rev_velocity_force_at(ar, g);
     if (fwd) fwd_dr_at(af, g);
 }
-__global__ __launch_bounds__(kAdjBlock) void rev_dr_fwd_force(AdjArgs ar, AdjArgs af, int fwd) {
+__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void rev_dr_fwd_force(AdjArgs ar, AdjArgs af, int fwd) {
     const long long g = global_id();
     rev_dr_at(ar, g);
     if (fwd) fwd_force_at(af, g);
@@ -528,17 +539,26 @@ __device__ double psi_ext_adjoint_t(const AdjArgs& a, int z, int e) {
     for (int i = 1; i < lbm::kQ; ++i) {
         const int c = lbm::cr(i);
         if (c == 0) continue;
+        // every tap row lies inside the extended field (|e| reaches at most 4
+        // beyond the lattice, the field 6), whose rows outside -2 .. nr+1
+        // hold zeros: no test is needed
         const int y1 = e - lbm::cr(i), y2 = e - 2 * lbm::cr(i);
-        if (kAll || (y1 >= -2 && y1 < nr + 2)) s += (8.0 * c / 36.0) * drb[eidx(y1, wrapz(z - lbm::cz(i), nz), nz)];
-        if (kAll || (y2 >= -2 && y2 < nr + 2)) s -= (c / 36.0) * drb[eidx(y2, wrapz(z - 2 * lbm::cz(i), nz), nz)];
+        s += (8.0 * c / 36.0) * drb[eidx(y1, wrapz(z - lbm::cz(i), nz), nz)];
+        s -= (c / 36.0) * drb[eidx(y2, wrapz(z - 2 * lbm::cz(i), nz), nz)];
     }
     // 1D d_r psi on real rows: (-p(y+2) + 8 p(y+1) - 8 p(y-1) + p(y-2)) / 12
     const double* d1b = fptr(a, S_D1B);
     const int ys[4] = {e - 2, e - 1, e + 1, e + 2};
     const double cf[4] = {-1.0, 8.0, -8.0, 1.0};
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-        if (kAll || (ys[k] >= 0 && ys[k] < nr)) s += (cf[k] / 12.0) * d1b[(long long)ys[k] * nz + z];
+    for (int k = 0; k < 4; ++k) {
+        if (kAll) {
+            s += (cf[k] / 12.0) * d1b[(long long)ys[k] * nz + z];
+        } else {
+            const double m = (ys[k] >= 0 && ys[k] < nr) ? 1.0 : 0.0;
+            s += (cf[k] / 12.0) * m * d1b[(long long)clampi(ys[k], 0, nr - 1) * nz + z];
+        }
+    }
     // Shan–Chen force: F^SC(x) = -G psi(x) sum_i W_i psi(x + c_i) c_i
     const double* fzb = fptr(a, S_FSCZB);
     const double* frb = fptr(a, S_FSCRB);
@@ -546,9 +566,9 @@ __device__ double psi_ext_adjoint_t(const AdjArgs& a, int z, int e) {
 #pragma unroll
     for (int i = 1; i < lbm::kQ; ++i) {
         const int ysrc = e - lbm::cr(i);
-        if (!kAll && (ysrc < 0 || ysrc >= nr)) continue;
-        const long long xs = (long long)ysrc * nz + wrapz(z - lbm::cz(i), nz);
-        s += -a.G * psi[xs] * lbm::weight(i) * (fzb[xs] * lbm::cz(i) + frb[xs] * lbm::cr(i));
+        const double m = (kAll || (ysrc >= 0 && ysrc < nr)) ? 1.0 : 0.0;
+        const long long xs = (long long)(kAll ? ysrc : clampi(ysrc, 0, nr - 1)) * nz + wrapz(z - lbm::cz(i), nz);
+        s += -a.G * psi[xs] * lbm::weight(i) * m * (fzb[xs] * lbm::cz(i) + frb[xs] * lbm::cr(i));
     }
     return s;
 }
@@ -560,7 +580,7 @@ __device__ double psi_ext_adjoint(const AdjArgs& a, int z, int e) {
 // Last reverse kernel: lam = f-bar + rho-bar + c . j-bar, and the block's
 // partial sums of the node contributions to dL/dG and dL/dtau (a fixed
 // tree order, so the result does not depend on scheduling).
-__global__ __launch_bounds__(kAdjBlock) void rev_psi_final(AdjArgs a) {
+__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void rev_psi_final(AdjArgs a) {
     const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double* w = a.w;
     const long long n = a.n;
