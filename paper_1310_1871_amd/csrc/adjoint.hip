@@ -235,27 +235,6 @@ __device__ __forceinline__ void fwd_force_at(const AdjArgs& a, const long long g
 
 // ------------------------------------------------------------ reverse ----
 
-// push target of (node (z, r), direction i) under the boundary rules
-__device__ __forceinline__ void push_target(int z, int r, int i, int nz, int nr, int wall, int& tz, int& tr,
-                                            int& d) {
-    tz = z + lbm::cz(i);
-    tr = r + lbm::cr(i);
-    d = i;
-    if (tr < 0) {
-        tr = 0;
-        d = lbm::mirror_r(i);
-    } else if (tr >= nr) {
-        if (wall == 0) {
-            tz = z;
-            tr = r;
-            d = lbm::opposite(i);
-        } else {
-            tr = nr - 1;
-            d = lbm::mirror_r(i);
-        }
-    }
-    tz = wrapz(tz, nz);
-}
 
 // steps 2-3: streaming transpose, BGK / equilibrium / source reversed.
 // kIn: a row with no boundary link (1 <= r <= nr - 2), whose push targets
@@ -293,7 +272,14 @@ __device__ __forceinline__ void rev_collision_node(const AdjArgs& a, const long 
             tr = r + lbm::cr(i);
             d = i;
         } else {
-            push_target(z, r, i, a.nz, a.nr, a.wall, tz, tr, d);
+            // the push target under the boundary rules (Sec. II.E: the
+            // specular axis, the no-slip or free-slip wall), as selects so
+            // that no branch separates the loads
+            const int ty = r + lbm::cr(i);
+            const bool below = ty < 0, above = ty >= a.nr, back = above && a.wall == 0;
+            tz = wrapz(back ? z : z + lbm::cz(i), a.nz);
+            tr = below ? 0 : (above ? (a.wall == 0 ? r : a.nr - 1) : ty);
+            d = below ? lbm::mirror_r(i) : (above ? (a.wall == 0 ? lbm::opposite(i) : lbm::mirror_r(i)) : i);
         }
         nus[i] = a.lam_next[d * n + (long long)tr * a.nz + tz];
         fis[i] = a.f[i * n + x];
