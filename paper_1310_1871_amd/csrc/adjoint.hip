@@ -239,7 +239,9 @@ __device__ __forceinline__ void fwd_force_at(const AdjArgs& a, const long long g
 // steps 2-3: streaming transpose, BGK / equilibrium / source reversed.
 // kIn: a row with no boundary link (1 <= r <= nr - 2), whose push targets
 // need no boundary rule, so the loop's loads carry no branches.
-template <bool kIn>
+// kAxi: the axisymmetric terms (a.axisym), a template flag so that no branch
+// separates the velocity-stencil loads from the others
+template <bool kIn, bool kAxi>
 __device__ __forceinline__ void rev_collision_node(const AdjArgs& a, const long long x, const int r, const int z) {
     double* w = a.w;
     const long long n = a.n;
@@ -255,7 +257,7 @@ __device__ __forceinline__ void rev_collision_node(const AdjArgs& a, const long 
     // every load first: the f-bar stores below could alias them for all the
     // compiler knows, and would otherwise make each load wait in turn
     double druz = 0, dzur = 0, drur = 0;
-    if (a.axisym) {
+    if (kAxi) {
         const double* uzE = eptr(a, E_UZ);
         const double* urE = eptr(a, E_UR);
         druz = d_iso_e(uzE, z, r, a.nz, true);
@@ -304,7 +306,7 @@ __device__ __forceinline__ void rev_collision_node(const AdjArgs& a, const long 
         hrb += 3.0 * wi * lbm::cr(i) * nu;
     }
     double uzb = 0, urb = 0, druzb = 0, dzurb = 0, drurb = 0;
-    if (a.axisym) {
+    if (kAxi) {
         const double mu = rho * (tau - 0.5) / 3.0;
         // mass = -rho u_r / r
         rhob += -massb * ur / rr;
@@ -344,10 +346,18 @@ __device__ __forceinline__ void rev_collision_node(const AdjArgs& a, const long 
 }
 __device__ __forceinline__ void rev_collision_at(const AdjArgs& a, const long long gid) {
     NODE_LOOP(a)
-    if (r >= 1 && r <= a.nr - 2)
-        rev_collision_node<true>(a, x, r, z);
-    else
-        rev_collision_node<false>(a, x, r, z);
+    const bool in = r >= 1 && r <= a.nr - 2;
+    if (a.axisym) {
+        if (in)
+            rev_collision_node<true, true>(a, x, r, z);
+        else
+            rev_collision_node<false, true>(a, x, r, z);
+    } else {
+        if (in)
+            rev_collision_node<true, false>(a, x, r, z);
+        else
+            rev_collision_node<false, false>(a, x, r, z);
+    }
 }
 
 // transposed isotropic stencil: sum over taps o of coef(o) * src(e - o),
