@@ -101,8 +101,8 @@ typedef struct lbm_axi_params {
 typedef struct lbm_axi_ctx* lbm_axi_t;
 
 /* Bytes of device workspace lbm_axi_create needs for these parameters (two
- * population buffers plus reduction scratch).  0 if the parameters are
- * invalid. */
+ * population buffers, each plane padded by 8 KiB inside the library, plus
+ * reduction scratch).  0 if the parameters are invalid. */
 size_t lbm_axi_workspace_bytes(const lbm_axi_params* p);
 
 /* Validate p, bind the caller's workspace and stream, and initialise the
@@ -195,19 +195,20 @@ int lbm_axi_set_open(lbm_axi_t h, int32_t in_row, double rho_in, const double* d
 int lbm_axi_drops(lbm_axi_t h, double rho_mid, int32_t max_drops, int32_t* h_count, double* h_volume,
                   double* h_centre);
 
-/* Size in bytes of the population state (9 nz nr values of the storage
- * type, in the library's structure-of-arrays layout [9][nr][nz]). */
+/* Size in bytes of the population state as the caller sees it: 9 nz nr
+ * values of the storage type, structure of arrays [9][nr][nz] with no
+ * padding between the planes (the library's own buffers pad them). */
 size_t lbm_axi_state_bytes(lbm_axi_t h);
 
 /* Device-to-device copy of the current state into d_dst / from d_src
- * (lbm_axi_state_bytes bytes, the library's layout).  Checkpoint/resume.
- * Asynchronous. */
+ * (lbm_axi_state_bytes bytes, the plain [9][nr][nz] layout).
+ * Checkpoint/resume.  Asynchronous. */
 int lbm_axi_get_state(lbm_axi_t h, void* d_dst);
 int lbm_axi_set_state(lbm_axi_t h, const void* d_src);
 
 /* Record a trajectory segment: with the handle at state f^t, writes
  * f^t, f^{t+1}, ..., f^{t+n-1} to d_states (n consecutive blocks of
- * lbm_axi_state_bytes bytes each, the library's layout) and leaves the
+ * lbm_axi_state_bytes bytes each, the plain [9][nr][nz] layout) and leaves the
  * handle at f^{t+n-1} (n - 1 steps).  n >= 1.  For checkpointed reverse
  * sweeps, which need every state of a segment.  Asynchronous. */
 int lbm_axi_record(lbm_axi_t h, int64_t n, void* d_states);

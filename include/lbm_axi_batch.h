@@ -55,7 +55,8 @@ int lbm_axi_batch_step_per_instance(lbm_axi_batch_t b, int64_t n);
 int lbm_axi_batch_moments(lbm_axi_batch_t b, int32_t k, double* d_rho, double* d_uz, double* d_ur);
 
 /* Device-to-device copy of instance k's populations (its lbm_axi_params'
- * storage type, layout [9][nr][nz]) into d_dst. */
+ * storage type, plain layout [9][nr][nz]: 9 nz nr values, no padding
+ * between the planes, which the batch's own buffers have) into d_dst. */
 int lbm_axi_batch_get_state(lbm_axi_batch_t b, int32_t k, void* d_dst);
 
 /* Number of kernel configurations compiled for the batch's precision, and
