@@ -362,9 +362,10 @@ __device__ __forceinline__ void rev_collision_at(const AdjArgs& a, const long lo
 
 // transposed isotropic stencil: sum over taps o of coef(o) * src(e - o),
 // src living on real rows of a plain field.  kAll: every tap row is a real
-// row, so the loads carry no bounds checks and a thread issues them all
-// before waiting on any (a check around each load makes each wait for the
-// previous one); the sum is the same either way.
+// row and the taps are summed as they are; otherwise a tap outside the
+// lattice loads a clamped row and is multiplied by 0.  Either way no branch
+// surrounds a load, so a thread issues them all before waiting on any (a
+// check around each load makes each wait for the previous one).
 template <bool kAll>
 __device__ double iso_transpose_real_t(const double* src, int z, int e, int nz, int nr, bool along_r) {
     double s = 0.0;
