@@ -603,28 +603,25 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2)
 #pragma unroll
         for (int i = 0; i < lbm::kQ; ++i) a.lam[i * n + x] = fb[i] + rhob + lbm::cz(i) * jzb + lbm::cr(i) * jrb;
     }
-    __shared__ double s[2][kAdjBlock];
+    // the workgroup is one wave: a tree of lane shuffles, lane 0 adding
+    // lane k's value for k = 32, 16, ..., 1 (a fixed order)
+    static_assert(kAdjBlock == 64, "one wave per workgroup");
     const int t = threadIdx.x;
-    s[0][t] = g;
-    s[1][t] = q;
-    __syncthreads();
+#pragma unroll
     for (int k = kAdjBlock / 2; k > 0; k >>= 1) {
-        if (t < k) {
-            s[0][t] += s[0][t + k];
-            s[1][t] += s[1][t + k];
-        }
-        __syncthreads();
+        g += __shfl_down(g, k, 64);
+        q += __shfl_down(q, k, 64);
     }
     if (t == 0) {
         // one step: this step's partials; a run: the block's running sums
         // over its steps, in step order
         const size_t o = (a.accumulate ? run_off(n, a.ne) : part_off(n, a.ne)) + 2 * (size_t)blockIdx.x;
         if (a.accumulate) {
-            w[o] += s[0][0];
-            w[o + 1] += s[1][0];
+            w[o] += g;
+            w[o + 1] += q;
         } else {
-            w[o] = s[0][0];
-            w[o + 1] = s[1][0];
+            w[o] = g;
+            w[o + 1] = q;
         }
     }
 }
