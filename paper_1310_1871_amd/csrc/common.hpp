@@ -44,15 +44,16 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 inline size_t storage_size(int precision) { return precision == LBM_AXI_FP64 ? sizeof(double) : sizeof(float); }
 
-// padding, in bytes, of each population plane in the single-lattice
-// library's own buffers (see lbm_axi.hip)
+// padding, in bytes, of each population plane in the library's own
+// buffers (single lattices and batch instances): planes exactly 2^k bytes
+// apart put the same node of every plane on the same memory channels
 constexpr long long kPlanePadBytes = 8192;
 
 inline int check_params(const lbm_axi_params* p) {
     if (!p) return fail(LBM_AXI_EINVAL, "params is NULL");
     if (p->nz < 1) return fail(LBM_AXI_EINVAL, "nz must be >= 1 (got %d)", p->nz);
     if (p->nr < 6) return fail(LBM_AXI_EINVAL, "nr must be >= 6 for the derivative stencils (got %d)", p->nr);
-    // (with room for the padding of the single-lattice buffers' planes)
+    // (with room for the padding of the buffers' planes)
     if (9.0 * ((double)p->nz * (double)p->nr * (p->precision == LBM_AXI_FP64 ? 8.0 : 4.0) + (double)kPlanePadBytes) >=
         4294967296.0)
         return fail(LBM_AXI_EINVAL, "grid too large: the population state must stay below 4 GiB");

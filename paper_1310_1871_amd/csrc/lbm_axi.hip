@@ -23,8 +23,9 @@ using namespace lbm_host;
 // Tile shapes of the fused kernel (chosen by timing on MI355X, with the two
 // state buffers alternating as in a run).  Large lattices use 64 x 16 tiles
 // of 512 threads, two or more workgroups per compute unit.  In FP64 each XCD
-// takes runs of whole tile rows (4096 x 512: 82 us per step, against 89-94
-// us for 64 x 32 tiles of 1024 threads in r-fastest order).  In FP32 each XCD
+// takes runs of whole tile rows (4096 x 512 on unpadded planes: 82 us per
+// step, against 89-94 us for 64 x 32 tiles of 1024 threads in r-fastest
+// order; 76 us with the padded planes below).  In FP32 each XCD
 // takes a slab of tile columns, and the stores are written through L2 to the
 // memory-side cache, which holds both FP32 buffers (35 us, against 40 us
 // with row runs and cached stores; neither helps FP64, whose two buffers do
