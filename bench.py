@@ -201,8 +201,8 @@ def main():
                     help="also run a plain copy kernel of known size (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see the design notes "
-              "on z-slab sharding); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (a lattice would be "
+              "split into z slabs with a halo exchange per step); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
