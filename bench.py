@@ -96,16 +96,17 @@ def copy_calibration():
     torch.cuda.synchronize()
 
 
-def adjoint_ratio():
+def adjoint_ratio(nz=256, nr=128, steps=2000):
     """(forward + backward) / forward time of the checkpointed adjoint on the
     adjoint workload: 256 x 128 drop (R = 40), 2000 steps, interface radius
     sampled every 50 steps on 16 rays, checkpoints every 100 steps,
-    gradients for a_2..a_6 (through rho0), G and tau."""
+    gradients for a_2..a_6 (through rho0), G and tau.  Other lattices keep
+    the drop radius at 0.3125 nr."""
     import numpy as np
     import torch
     from lbm_inputs import adjoint_coeffs, coexistence_densities, drop_density
     from paper_1310_1871_amd import adjoint as A
-    nz, nr, R, Gc, tauc, steps, every, ck = 256, 128, 40.0, -5.5, 0.8, 2000, 50, 100
+    R, Gc, tauc, every, ck = 0.3125 * nr, -5.5, 0.8, 50, 100
     rg, rl = coexistence_densities(Gc)
     probe = A.RayProbe(nz, nr, nz / 2.0, A.default_thetas(16), rl, rg)
     rho_t = torch.from_numpy(drop_density(nz, nr, nz / 2.0, R, rl, rg, 2.0, adjoint_coeffs(11, R))).cuda()
@@ -127,7 +128,8 @@ def adjoint_ratio():
         times = {"fwd_s": t1 - t0, "bwd_s": t2 - t1, "loss": float(loss.item()),
                  "dL_dG": float(G.grad.item()), "dL_dtau": float(tau.grad.item())}
     times["fwd_bwd_over_fwd"] = round((times["fwd_s"] + times["bwd_s"]) / times["fwd_s"], 3)
-    times["workload"] = "drop 256x128 R=40, 2000 steps, 16 rays every 50 steps, checkpoint every 100, FP64"
+    times["workload"] = (f"drop {nz}x{nr} R={R:g}, {steps} steps, 16 rays every {every} steps, "
+                         f"checkpoint every {ck}, FP64")
     return times
 
 
@@ -196,6 +198,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
     ap.add_argument("--skip-fp32", action="store_true")
     ap.add_argument("--skip-adjoint", action="store_true")
+    ap.add_argument("--adjoint-lattice", type=int, nargs=3, metavar=("NZ", "NR", "STEPS"), default=(256, 128, 2000),
+                    help="lattice and step count of the adjoint leg (default: the 256 x 128 drop, 2000 steps)")
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain copy kernel of known size (for counter calibration)")
@@ -246,8 +250,9 @@ def main():
                                "mass_3d_rel_diff_vs_f64": abs(diag32[0] - diag64[0]) / diag64[0]}
     out["adjoint"] = None
     if not args.skip_adjoint:
-        print("bench: adjoint (fwd+bwd)/fwd on the 256x128 drop", file=sys.stderr, flush=True)
-        out["adjoint"] = adjoint_ratio()
+        anz, anr, asteps = args.adjoint_lattice
+        print(f"bench: adjoint (fwd+bwd)/fwd on the {anz}x{anr} drop", file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_ratio(anz, anr, asteps)
     if not args.skip_batch:
         print("bench: batched ensemble of 256 instances", file=sys.stderr, flush=True)
         out["batch"] = batch_throughput()
