@@ -111,8 +111,9 @@ typedef struct {
  * h_i(y) = W_i (mass(y) + 3 c_i . H(y)) from the fields at y.  Across the
  * axis y is the mirror node with H_r reversed (H_z and the mass source are
  * even there, H_r odd); across the outer wall the mirror node's values are
- * used as they are (every field is even there).  Periodic z and no open
- * rows only. */
+ * used as they are (every field is even there).  Periodic z only; with open
+ * rows the far end of a link may be an open row's node, whose fields are
+ * used as they are. */
 #define ORACLE_FLAG_MIDLINK 16
 
 /* Open boundaries (Sec. II.E: a prescribed velocity or pressure is imposed
@@ -526,7 +527,7 @@ int API(check)(const or_params* p) {
     if (p->nz < 1 || p->nr < NG) return -1;
     if ((p->flags & ~(ORACLE_FLAG_GUO | ORACLE_FLAG_NO_WALL_DERIV | ORACLE_FLAG_ZWALLS | ORACLE_FLAG_MIDLINK)) != 0)
         return -1;
-    if ((p->flags & ORACLE_FLAG_MIDLINK) && ((p->flags & ORACLE_FLAG_ZWALLS) || p->in_row >= 0 || p->out_row >= 0))
+    if ((p->flags & ORACLE_FLAG_MIDLINK) && (p->flags & ORACLE_FLAG_ZWALLS))
         return -1;
     if (p->in_row < -1 || p->in_row >= p->nr || p->out_row < -1 || p->out_row >= p->nr) return -1;
     if (p->in_row >= 0 && (!p->uz_in || !p->ur_in)) return -1;

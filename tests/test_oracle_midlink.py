@@ -44,9 +44,9 @@ def test_hagen_poiseuille_with_midlink_source(golden):
     assert np.abs(ur).max() < 1e-3 * U1
 
 
-def test_midlink_rejects_closed_ends_and_open_rows():
+def test_midlink_rejects_closed_ends():
     one = np.ones((12, 16))
-    for kw in (dict(flags=O.FLAG_MIDLINK | O.FLAG_ZWALLS), dict(flags=O.FLAG_MIDLINK, out_row=10)):
+    for kw in (dict(flags=O.FLAG_MIDLINK | O.FLAG_ZWALLS),):
         p = O.make_params(16, 12, G=0.0, **kw)
         with pytest.raises(ValueError):
             O.run(p, O.equilibrium(p, one, 0 * one, 0 * one), 1)

@@ -1,8 +1,9 @@
 """Physics pins of the oracle against values the paper prints and against
 textbook solutions the paper's validations rely on (Sec. III and IV):
 viscous shear-wave decay (planar cosine and axisymmetric Bessel mode),
-Hagen–Poiseuille pipe flow, coexistence densities, Table I surface tension,
-the Laplace law and the l = 2 drop-oscillation frequency."""
+Hagen–Poiseuille pipe flow, coexistence densities, Table I surface tension
+and the l = 2 drop-oscillation frequency (the Laplace sweep is in
+test_oracle_laplace.py)."""
 import numpy as np
 import pytest
 from scipy.optimize import curve_fit
@@ -137,83 +138,53 @@ def test_table1_surface_tension(golden, k):
     assert abs(ga - g2) / g2 < 0.003
 
 
-def _laplace(G, nz, nr, R, axisym, rho_l, rho_g, steps=3000, tau=1.0):
-    rho = drop_density(nz, nr, nz / 2.0, R, rho_l, rho_g, 2.0)
-    p = O.make_params(nz, nr, G=G, tau=tau, wall=0, axisym=axisym)
-    f = O.run(p, O.equilibrium(p, rho, 0 * rho, 0 * rho), steps)
-    rr, _, _ = O.moments(p, f)
-    rin, rout = rr[0, nz // 2], rr[-1, 0]
-    mid = 0.5 * (rin + rout)
-    a_r = D.axis_intercept(rr, nz // 2, mid)
-    row = rr[0]
-    k = np.nonzero(row >= mid)[0][-1]
-    a_z = k + (row[k] - mid) / (row[k] - row[k + 1]) - nz / 2.0
-    dp = D.pressure(rin, G) - D.pressure(rout, G)
-    return dp, 0.5 * (a_r + a_z)
-
-
-def test_laplace_law(golden):
-    """Sec. IV.A, Laplace test (static drop 64 x 32, R = 10, rho 2.0/0.15,
-    G = -5.5, tau = 1, no-slip wall).  The planar scheme gives the 2D law
-    dp = gamma/R; the axisymmetric scheme must add the azimuthal curvature,
-    dp ~ 2 gamma/R, with the SC-forcing error the paper reports (at most
-    20%; this reading of the scheme gives ~25%: the tau-correction part of
-    the surface tension acts on the in-plane curvature only).  The
-    ratio of the two pins the extra force F^{gamma,sym}: without it the
-    ratio would be 1, with the wrong sign well below 1."""
-    G = -5.5
-    gam = D.surface_tension_sc(*[_flat_interface(G, axisym=0)[n] for n in ("rho", "f_r")], G, 1.0)[0]
-    dp2, R2 = _laplace(G, 64, 32, 10.0, 0, 2.0, 0.15)
-    dpa, Ra = _laplace(G, 64, 32, 10.0, 1, 2.0, 0.15)
-    assert dp2 * R2 == pytest.approx(gam, rel=0.05)
-    err = abs(dpa * Ra - 2 * gam) / (2 * gam)
-    assert err < golden["laplace_sc_max_rel_error"]["value"] + 0.07
-    assert 1.35 < (dpa * Ra) / (dp2 * R2) < 1.9
-
-
 @pytest.mark.slow
-@pytest.mark.parametrize("flags", [0, O.FLAG_MIDLINK])
-def test_drop_oscillation_frequency(golden, flags):
-    """Sec. IV.B: an ellipsoidal drop (G = -6, rho 2.65/0.075, tau = 1,
-    free-slip wall) oscillates in the l = 2 mode; A(t) fitted with
-    g(t) = R_D + a exp(-b t) sin(w t + d) gives w close to Miller and
-    Scriven's w_2 (Eq. freq-drop-miller) with the measured surface tension.
-    The paper reports ~1%; this reading gives 2-4% on the small 160 x 80
-    lattice used here (-2.4 % with the node source, -2.3 % with the
-    mid-link source), and the tolerance is set to 6%.  The paper gives no
-    damping figure; the fitted rate is only checked to be of the size of
-    Lamb's (l-1)(2l+1) nu / R^2 (within 25%)."""
-    G, tau = -6.0, 1.0
+def test_drop_oscillation_frequency(golden):
+    """Sec. IV.B on the paper's lattice: 320 x 128, G = -6, an ellipsoid
+    (z/R_a)^2 + (r/R_b)^2 = 1 centred on the axis at z = 160 with the printed
+    densities 2.65 / 0.075 inside and outside, tau = 1, free-slip wall,
+    periodic z.  A(t), the intercept on the r axis at the centre column
+    (R15), sampled every 40 steps up to 8000 and fitted over t > 1000 with
+    g(t) = R_D + a exp(-b t) sin(w t + d), gives w against Miller and
+    Scriven's w_2 (Eq. freq-drop-miller) at the fitted R_D, with the surface
+    tension of Eq. stc measured on a flat interface and the measured bulk
+    densities.  The paper reports a maximum error of about 1 %: with
+    R_a = 56, R_b = 48 this gives -0.49 % (R_D = 50.2; R_a = 52, R_b = 44
+    gives -0.75 %), tolerance 1 %, the paper's figure.  (Smaller drops damp out within two periods and
+    their fitted frequency depends on the window.)
+    The damping rate is of the size of Lamb's (l-1)(2l+1) nu / R^2 (within
+    40 %; the paper gives no figure)."""
+    G, tau, Ra, Rb = -6.0, 1.0, 56.0, 48.0
     fl = _flat_interface(G, axisym=0)
     gam, _, _ = D.surface_tension_sc(fl["rho"], fl["f_r"], G, tau)
-    rl, rg = fl["rho"][0, 0], fl["rho"][-1, 0]
-    nz, nr, Ra, Rb = 160, 80, 36.0, 28.0
+    nz, nr = 320, 128
     z, r = node_coords(nz, nr)
     req = (Ra * Rb * Rb) ** (1.0 / 3.0)
     s = np.sqrt(((z - nz / 2) / Ra) ** 2 + (r / Rb) ** 2)
-    rho = tanh_profile(s * req, req, rl, rg, 2.0)
-    p = O.make_params(nz, nr, G=G, tau=tau, wall=1, axisym=1, flags=flags)
+    rho = tanh_profile(s * req, req, golden["coexistence_G6"]["rho_l"], golden["coexistence_G6"]["rho_v"], 2.0)
+    p = O.make_params(nz, nr, G=G, tau=tau, wall=1, axisym=1)
     f = O.equilibrium(p, rho, 0 * rho, 0 * rho)
     ts, A = [], []
-    for k in range(250):
-        f = O.run(p, f, 20)
+    for k in range(200):
+        f = O.run(p, f, 40)
         rr, _, _ = O.moments(p, f)
-        ts.append((k + 1) * 20.0)
-        A.append(D.axis_intercept(rr, nz // 2, 0.5 * (rl + rg)))
+        rin, rout = rr[0, nz // 2], rr[-1, 0]
+        ts.append((k + 1) * 40.0)
+        A.append(D.axis_intercept(rr, nz // 2, 0.5 * (rin + rout)))
     ts, A = np.array(ts), np.array(A)
     nu = (tau - 0.5) / 3.0
 
     def ms(R):
-        w0 = np.sqrt(24 * gam / (R ** 3 * (2 * rg + 3 * rl)))
-        al = 25 * nu * rl * rg / (np.sqrt(2) * R * (2 * rg + 3 * rl) * (np.sqrt(nu) * (rl + rg)))
+        w0 = np.sqrt(24 * gam / (R ** 3 * (2 * rout + 3 * rin)))
+        al = 25 * nu * rin * rout / (np.sqrt(2) * R * (2 * rout + 3 * rin) * (np.sqrt(nu) * (rin + rout)))
         return w0 - 0.5 * al * np.sqrt(w0) + 0.25 * al * al
 
     g = lambda t, R0, a, b, w, d: R0 + a * np.exp(-b * t) * np.sin(w * t + d)
-    m = ts > 500
-    popt, _ = curve_fit(g, ts[m], A[m], p0=[A[-1], 2.0, 1e-3, ms(req), 1.5], maxfev=50000)
+    m = ts > 1000
+    popt, _ = curve_fit(g, ts[m], A[m], p0=[A[-1], 2.0, 5e-4, ms(req), 1.5], maxfev=50000)
     R0, w, b = popt[0], abs(popt[3]), popt[2]
-    assert w == pytest.approx(ms(R0), rel=0.06)
-    assert b == pytest.approx(5.0 * nu / R0 ** 2, rel=0.25)
+    assert w == pytest.approx(ms(R0), rel=golden["oscillation_max_rel_error"]["value"])
+    assert b == pytest.approx(5.0 * nu / R0 ** 2, rel=0.4)
 
 
 def test_low_tau_diverges_at_G55():
@@ -231,3 +202,23 @@ def test_low_tau_diverges_at_G55():
         f = O.run(p, O.equilibrium(p, rho, 0 * rho, 0 * rho), 500)
         res[tau] = bool(np.isfinite(f).all())
     assert res == {0.6: False, 0.8: True}
+
+
+def test_thread_diverges_at_tau07():
+    """The Rayleigh-Plateau thread workload (radius 64, 0.1 R cos(2 pi z /
+    nz) perturbation, G = -5.5, free-slip wall, G = -5.5 coexistence
+    densities) on a reduced 512 x 256 lattice: at the workload's nominal
+    tau = 0.7 the populations go non-finite within 300 steps, at tau = 0.8
+    they stay finite.  This is why the thread benchmark runs at tau = 0.8
+    (tau does not change the work per node)."""
+    from lbm_inputs import thread_density
+    G = -5.5
+    rg, rl = coexistence_densities(G)
+    nz, nr = 512, 256
+    rho = thread_density(nz, nr, 64.0, rl, rg, 2.0, 0.1, 1)
+    res = {}
+    for tau in (0.7, 0.8):
+        p = O.make_params(nz, nr, G=G, tau=tau, wall=1, axisym=1)
+        f = O.run(p, O.equilibrium(p, rho, 0 * rho, 0 * rho), 300)
+        res[tau] = bool(np.isfinite(f).all())
+    assert res == {0.7: False, 0.8: True}
