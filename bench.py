@@ -3,8 +3,9 @@
 Workload: Rayleigh–Plateau liquid thread on a 4096 x 512 (z, r) lattice,
 thread radius 64 with a 0.1 R cos(2 pi z / nz) perturbation, G = -5.5,
 free-slip outer wall, tau = 0.8 (the scheme diverges at tau = 0.7 for this
-G; tau does not change the work per node).  Synthetic, seeded inputs resident
-in HBM before the timed region.
+G; tau does not change the work per node), started at the scheme's own
+coexistence densities for (G, tau).  Synthetic inputs resident in HBM before
+the timed region.
 
 One step = one launch of the fused kernel over all 2,097,152 nodes.  Prints
 one JSON line: FP64 MLUPS as ``value``, the FP32-shifted-storage MLUPS (shift
@@ -60,16 +61,17 @@ def measured_traffic(tag):
 
 
 def workload_density():
-    from lbm_inputs import coexistence_densities, thread_density
-    rg, rl = coexistence_densities(G)
+    from lbm_inputs import scheme_coexistence, thread_density
+    rg, rl = scheme_coexistence(G, TAU)
     return thread_density(NZ, NR, RADIUS, rl, rg, 2.0, EPS, 1), rl, rg
 
 
-def time_gpu(precision, rho, rho_ref, steps, warmup):
+def time_gpu(precision, rho, rho_ref, steps, warmup, kernel="tile", strip_rows=43):
     import torch
     from paper_1310_1871_amd import lbm_axi as L
     p = L.make_params(NZ, NR, G=G, tau=TAU, wall=L.WALL_FREESLIP, axisym=1, precision=precision, rho_ref=rho_ref)
     sim = L.AxiLBM(p, torch.from_numpy(rho).cuda())
+    sim.set_kernel(L.KERNEL_STRIP if kernel == "strip" else L.KERNEL_TILE, strip_rows)
     sim.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -160,34 +162,75 @@ def batch_throughput(steps=200):
         b.synchronize()
         ms = e0.elapsed_time(e1) / steps
         out[name] = {"ms_per_step": round(ms, 5), "MLUPS": round(nodes / (ms * 1e-3) / 1e6, 1)}
+        if name == "persistent_graph":
+            # algorithmic bytes of one step of every instance (FP32 storage:
+            # 72 B per node), over the launch time; the ensemble's two buffers
+            # (2 x 462 MB) exceed the 256 MB memory-side cache
+            gbs = BYTES_PER_LU["f32"] * nodes / (ms * 1e-3) / 1e9
+            out[name]["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
     out["speedup_persistent_vs_per_instance"] = round(out["per_instance_launches"]["ms_per_step"] /
                                                       out["persistent_graph"]["ms_per_step"], 3)
     b.close()
     return out
 
 
-def cpu_baseline(rho, budget_s=30.0):
-    """The oracle as it stands, on the host cores, over whole steps of the
-    same 4096 x 512 workload until about budget_s seconds have elapsed."""
+def _omp_threads():
     import ctypes
+    try:
+        return int(ctypes.CDLL("libgomp.so.1").omp_get_max_threads())
+    except OSError:
+        return os.cpu_count()
+
+
+def _oracle_rate(p, f, budget_s):
+    """MLUPS of the oracle as it stands on whole steps of (p, f), over about
+    budget_s seconds (at least one step after a start-up step)."""
+    import oracle as O
+    f = O.run(p, f, 1)  # start-up (thread pool, first touch) outside the sample
+    t0 = time.perf_counter()
+    f = O.run(p, f, 2)
+    t1 = (time.perf_counter() - t0) / 2
+    steps = max(1, int(budget_s / max(t1, 1e-4)))
+    t0 = time.perf_counter()
+    O.run(p, f, steps)
+    el = time.perf_counter() - t0
+    return p.nz * p.nr * steps / el / 1e6, steps, el
+
+
+def cpu_baseline(rho, budget_s=12.0):
+    """The oracle as it stands, timed on the host: the 4096 x 512 thread
+    workload (the benchmarked one) on every host thread and on one, and the
+    64 x 32 static drop and the 256 x 128 oscillating drop on every thread,
+    each over a bounded sample of whole steps (about budget_s seconds of
+    CPU work each, 2000-step runs where they fit)."""
     import numpy as np
     import oracle as O
+    from lbm_inputs import oscillating_drop, static_drop
+    threads = _omp_threads()
     p = O.make_params(NZ, NR, G=G, tau=TAU, wall=O.WALL_FREESLIP, axisym=1)
     f = O.equilibrium(p, rho, np.zeros_like(rho), np.zeros_like(rho))
-    f = O.run(p, f, 1)  # start-up (thread pool, first touch) outside the sample
-    t_start = time.perf_counter()
-    f = O.run(p, f, 3)  # three steps size the sample
-    t1 = (time.perf_counter() - t_start) / 3
-    steps = max(1, int(budget_s / max(t1, 1e-3)))
-    t_start = time.perf_counter()
-    f = O.run(p, f, steps)
-    el = time.perf_counter() - t_start
+    v_all, n_all, t_all = _oracle_rate(p, f, budget_s)
+    O.set_threads(1)
     try:
-        cores = ctypes.CDLL("libgomp.so.1").omp_get_max_threads()
-    except OSError:
-        cores = os.cpu_count()
-    return {"value": NZ * NR * steps / el / 1e6, "unit": "MLUPS", "cores": int(cores), "kind": "oracle",
-            "sample": f"{steps} full steps of the 4096x512 thread workload (FP64 C oracle, OpenMP), {el:.1f} s"}
+        v_one, n_one, t_one = _oracle_rate(p, f, budget_s / 2)
+    finally:
+        O.set_threads(threads)
+    others = {}
+    for case in (static_drop(), oscillating_drop(tau=0.8)):
+        q = O.make_params(case.nz, case.nr, G=case.G, tau=case.tau, wall=case.wall, axisym=1)
+        fc = O.equilibrium(q, case.rho, case.uz, case.ur)
+        t0 = time.perf_counter()
+        n = 2000
+        O.run(q, fc, n)
+        el = time.perf_counter() - t0
+        others[f"{case.nz}x{case.nr}"] = {"MLUPS": round(case.nz * case.nr * n / el / 1e6, 2), "steps": n,
+                                          "seconds": round(el, 2), "cores": threads}
+    return {"value": v_all, "unit": "MLUPS", "cores": int(threads), "kind": "oracle",
+            "sample": (f"{n_all} full steps of the 4096x512 thread workload (FP64 C oracle, OpenMP), "
+                       f"{t_all:.1f} s"),
+            "one_core": {"value": v_one, "unit": "MLUPS", "cores": 1, "steps": n_one, "seconds": round(t_one, 2)},
+            "other_workloads": others}
 
 
 def main():
@@ -203,6 +246,9 @@ def main():
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain copy kernel of known size (for counter calibration)")
+    ap.add_argument("--kernel", choices=("tile", "strip"), default="tile",
+                    help="step kernel of the FP64 and FP32 legs (lbm_axi_set_kernel); tile is the library default")
+    ap.add_argument("--strip-rows", type=int, default=43, help="chunk height of the strip kernel")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (a lattice would be "
@@ -212,7 +258,7 @@ def main():
     import numpy as np
     rho, rl, rg = workload_density()
     print(f"bench: thread {NZ}x{NR} FP64 {args.steps} steps (+{args.warmup} warm-up)", file=sys.stderr, flush=True)
-    ms64, diag64 = time_gpu(0, rho, 0.0, args.steps, args.warmup)
+    ms64, diag64 = time_gpu(0, rho, 0.0, args.steps, args.warmup, args.kernel, args.strip_rows)
     lups = NZ * NR
     mlups64 = lups / (ms64 * 1e-3) / 1e6
     achieved = BYTES_PER_LU["f64"] * lups / (ms64 * 1e-3) / 1e9
@@ -233,20 +279,21 @@ def main():
                    "wall": "free-slip", "thread_radius": RADIUS, "perturbation": "0.1 R cos(2 pi z / nz)",
                    "rho_l": round(rl, 5), "rho_g": round(rg, 5), "bytes_per_lu": BYTES_PER_LU["f64"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("f64"),
-                     "kernel": "axi_tile_kernel<FP64>"},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("f64") if args.kernel == "tile" else None,
+                     "kernel": f"axi_{args.kernel}_kernel<FP64>"},
         "diagnostics_f64": {"mass_3d": diag64[0], "kinetic_energy": diag64[2]},
     }
     if not args.skip_fp32:
         print(f"bench: thread {NZ}x{NR} FP32-shifted storage", file=sys.stderr, flush=True)
-        ms32, diag32 = time_gpu(1, rho, rg, args.steps, args.warmup)
+        ms32, diag32 = time_gpu(1, rho, rg, args.steps, args.warmup, args.kernel, args.strip_rows)
         mlups32 = lups / (ms32 * 1e-3) / 1e6
         ach32 = BYTES_PER_LU["f32"] * lups / (ms32 * 1e-3) / 1e9
         out["fp32_storage"] = {"value": round(mlups32, 2), "unit": "MLUPS", "ms_per_step": round(ms32, 6),
                                "speedup_vs_f64": round(ms64 / ms32, 3), "rho_ref": round(rg, 5),
                                "roofline": {"bound": "hbm", "achieved": round(ach32, 1), "peak": HBM_PEAK_GBS,
                                             "unit": "GB/s", "frac": round(ach32 / HBM_PEAK_GBS, 4),
-                                            "traffic": measured_traffic("f32")},
+                                            "traffic": measured_traffic("f32") if args.kernel == "tile" else None},
                                "mass_3d_rel_diff_vs_f64": abs(diag32[0] - diag64[0]) / diag64[0]}
     out["adjoint"] = None
     if not args.skip_adjoint:

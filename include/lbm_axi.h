@@ -37,6 +37,9 @@ extern "C" {
 #define LBM_AXI_EHIP (-3)       /* HIP runtime error (message in last_error) */
 #define LBM_AXI_ENONFINITE (-4) /* a reduced diagnostic is NaN or Inf */
 #define LBM_AXI_EUNSUP (-5)     /* combination not supported */
+/* Positive return: success with a warning (the call took effect; the
+ * message is in lbm_axi_last_error()). */
+#define LBM_AXI_WARN_STABILITY 1 /* G < -6: outside the stability rule of thumb of Sec. II.D */
 
 #define LBM_AXI_WALL_NOSLIP 0   /* mid-grid bounce-back */
 #define LBM_AXI_WALL_FREESLIP 1 /* mid-grid specular reflection */
@@ -100,6 +103,13 @@ typedef struct lbm_axi_params {
 
 typedef struct lbm_axi_ctx* lbm_axi_t;
 
+/* Validate p without touching a device (the checks create makes).  Returns
+ * LBM_AXI_OK, a negative error code, or LBM_AXI_WARN_STABILITY when
+ * G < -6: Sec. II.D gives as a rule of thumb that the scheme stays stable
+ * up to a liquid/vapour density ratio of about 35, reached at G = -6;
+ * stronger coupling is allowed but may diverge. */
+int lbm_axi_check_params(const lbm_axi_params* p);
+
 /* Bytes of device workspace lbm_axi_create needs for these parameters (two
  * population buffers, each plane padded by 8 KiB inside the library, plus
  * reduction scratch).  0 if the parameters are invalid. */
@@ -111,7 +121,9 @@ size_t lbm_axi_workspace_bytes(const lbm_axi_params* p);
  * d_uz0 and d_ur0 may be NULL (zero velocity).  The workspace must be at
  * least lbm_axi_workspace_bytes(p) bytes and 256-byte aligned and stays owned
  * by the caller; it must outlive the handle.  hip_stream is a hipStream_t
- * (NULL: the null stream).  On success *out receives the handle. */
+ * (NULL: the null stream).  On success *out receives the handle; the
+ * return value is LBM_AXI_OK, or LBM_AXI_WARN_STABILITY when G < -6 (see
+ * lbm_axi_check_params; the handle is valid). */
 int lbm_axi_create(const lbm_axi_params* p, const double* d_rho0, const double* d_uz0,
                    const double* d_ur0, void* d_workspace, size_t ws_bytes, void* hip_stream,
                    lbm_axi_t* out);
@@ -195,6 +207,12 @@ int lbm_axi_set_open(lbm_axi_t h, int32_t in_row, double rho_in, const double* d
 int lbm_axi_drops(lbm_axi_t h, double rho_mid, int32_t max_drops, int32_t* h_count, double* h_volume,
                   double* h_centre);
 
+/* The current populations f_i as FP64, into the device array
+ * double[9][nr][nz] (d_f, 72 nz nr bytes): the stored values, plus
+ * W_i rho_ref in FP32 shifted storage (the decode is done on the device, in
+ * double).  Asynchronous. */
+int lbm_axi_populations(lbm_axi_t h, double* d_f);
+
 /* Size in bytes of the population state as the caller sees it: 9 nz nr
  * values of the storage type, structure of arrays [9][nr][nz] with no
  * padding between the planes (the library's own buffers pad them). */
@@ -213,10 +231,24 @@ int lbm_axi_set_state(lbm_axi_t h, const void* d_src);
  * sweeps, which need every state of a segment.  Asynchronous. */
 int lbm_axi_record(lbm_axi_t h, int64_t n, void* d_states);
 
+/* Step kernel selection (the arithmetic is the same; the organisation of
+ * the work differs).  LBM_AXI_KERNEL_TILE: one workgroup per tile of nodes,
+ * every tile recomputing a 6-node halo.  LBM_AXI_KERNEL_STRIP: each
+ * workgroup walks a band of 64 columns up a chunk of chunk_rows rows,
+ * keeping the halo rows it has computed (needs nz >= 70; the Guo and
+ * wall-derivative options only, no open rows).  create selects the tile
+ * kernel, the faster of the two on MI355X (4096 x 512 FP64: 77 us per step
+ * against 93 us for the strip with chunks of 43 rows); set_open goes back to
+ * the tile kernel.  Returns LBM_AXI_EUNSUP when the strip does not apply. */
+#define LBM_AXI_KERNEL_TILE 0
+#define LBM_AXI_KERNEL_STRIP 1
+int lbm_axi_set_kernel(lbm_axi_t h, int32_t kind, int32_t chunk_rows);
+
 /* Rebind the stream later calls are issued on. */
 int lbm_axi_set_stream(lbm_axi_t h, void* hip_stream);
 
-/* Replace G and tau of an existing handle (same validation as create). */
+/* Replace G and tau of an existing handle (same validation as create,
+ * including the LBM_AXI_WARN_STABILITY return). */
 int lbm_axi_set_coupling(lbm_axi_t h, double G, double tau);
 
 /* Release the handle (not the caller's workspace).  NULL is ignored. */

@@ -38,7 +38,8 @@ size_t lbm_axi_batch_workspace_bytes(const lbm_axi_params* ps, int32_t n_inst);
 /* Create the batch: validates ps, binds the workspace and stream, and
  * initialises instance k to f^eq(rho0[k], 0) from the device field
  * h_d_rho0[k] (a host array of n_inst device pointers to double[nr][nz]).
- * The stream must outlive the handle. */
+ * The stream must outlive the handle.  Returns LBM_AXI_WARN_STABILITY (the
+ * batch is created) when an instance has G < -6 (lbm_axi_check_params). */
 int lbm_axi_batch_create(const lbm_axi_params* ps, int32_t n_inst, const double* const* h_d_rho0,
                          void* d_workspace, size_t ws_bytes, void* hip_stream, lbm_axi_batch_t* out);
 
@@ -58,6 +59,11 @@ int lbm_axi_batch_moments(lbm_axi_batch_t b, int32_t k, double* d_rho, double* d
  * storage type, plain layout [9][nr][nz]: 9 nz nr values, no padding
  * between the planes, which the batch's own buffers have) into d_dst. */
 int lbm_axi_batch_get_state(lbm_axi_batch_t b, int32_t k, void* d_dst);
+
+/* Instance k's populations f_i as FP64 into the device array
+ * double[9][nr_k][nz_k]: the stored values, plus W_i rho_ref in FP32
+ * shifted storage (decoded on the device, in double).  Asynchronous. */
+int lbm_axi_batch_populations(lbm_axi_batch_t b, int32_t k, double* d_f);
 
 /* Number of kernel configurations compiled for the batch's precision, and
  * the tile shape (z, r) and workgroup size of configuration c. */

@@ -115,6 +115,43 @@ def coexistence_densities(G, rho0=1.0):
     return float(np.exp(sol[0])), float(np.exp(sol[1]))
 
 
+@lru_cache(maxsize=1)
+def _tau_table():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "coexistence_tau.json")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def scheme_coexistence(G, tau):
+    """(rho_gas, rho_liquid) at which a flat interface settles under the
+    velocity-shift scheme at coupling G and relaxation time tau: bilinear
+    interpolation of the table coexistence_tau.json (flat-interface runs,
+    G in [-6, -5] by 0.1, tau in [0.6, 1] by 0.05; see the script that
+    writes it, tests/golden/make_coexistence_table.py).  The velocity shift
+    makes these depend on tau; at tau = 1 they are close to the
+    mechanical-stability values of coexistence_densities.  Raises
+    ValueError outside the table or next to a (G, tau) whose interface does
+    not stay finite."""
+    t = _tau_table()
+    gs, ts = np.array(t["G"]), np.array(t["tau"])
+    if not (gs[0] - 1e-12 <= G <= gs[-1] + 1e-12 and ts[0] - 1e-12 <= tau <= ts[-1] + 1e-12):
+        raise ValueError(f"(G, tau) = ({G}, {tau}) outside the coexistence table")
+    i = int(min(max(np.searchsorted(gs, G) - 1, 0), len(gs) - 2))
+    j = int(min(max(np.searchsorted(ts, tau) - 1, 0), len(ts) - 2))
+    a = (G - gs[i]) / (gs[i + 1] - gs[i])
+    b = (tau - ts[j]) / (ts[j + 1] - ts[j])
+    out = []
+    for key in ("rho_g", "rho_l"):
+        v = t[key]
+        c = [v[i][j], v[i][j + 1], v[i + 1][j], v[i + 1][j + 1]]
+        if any(x is None for x in c):
+            raise ValueError(f"(G, tau) = ({G}, {tau}) next to an unstable table entry")
+        out.append((1 - a) * ((1 - b) * c[0] + b * c[1]) + a * ((1 - b) * c[2] + b * c[3]))
+    return float(out[0]), float(out[1])
+
+
 # ------------------------------------------------------------ workloads --
 
 
@@ -148,8 +185,9 @@ def static_drop(nz=64, nr=32, radius=10.0, rho_l=2.0, rho_g=0.15, G=-5.5, tau=1.
 def oscillating_drop(nz=256, nr=128, radius=40.0, G=-5.5, tau=0.8, wall=0, seed=2024, steps=20000,
                      amp=0.05, noise=1e-4):
     """Drop with a P2 shape perturbation of amplitude amp*R plus seeded
-    uniform noise on rho (configuration 'drop oscillation 256 x 128')."""
-    rho_g, rho_l = coexistence_densities(G)
+    uniform noise on rho (configuration 'drop oscillation 256 x 128'),
+    started at the scheme's coexistence densities for (G, tau)."""
+    rho_g, rho_l = scheme_coexistence(G, tau)
     rho = drop_density(nz, nr, nz / 2.0, radius, rho_l, rho_g, 2.0, {2: amp * radius})
     rho = rho + uniform_noise(seed, rho.shape, noise)
     z = np.zeros_like(rho)
@@ -157,10 +195,13 @@ def oscillating_drop(nz=256, nr=128, radius=40.0, G=-5.5, tau=0.8, wall=0, seed=
                 {"zc": nz / 2.0, "radius": radius, "a2": amp * radius})
 
 
-def rp_thread(nz=4096, nr=512, radius=64.0, eps=0.1, mode=1, G=-5.5, tau=0.7, wall=1, steps=50000):
+def rp_thread(nz=4096, nr=512, radius=64.0, eps=0.1, mode=1, G=-5.5, tau=0.8, wall=1, steps=50000):
     """Liquid thread with a cos(2 pi z / nz) radius perturbation of amplitude
-    eps*R (configuration 'Rayleigh–Plateau 4096 x 512')."""
-    rho_g, rho_l = coexistence_densities(G)
+    eps*R (configuration 'Rayleigh–Plateau 4096 x 512'), started at the
+    scheme's coexistence densities for (G, tau).  tau = 0.8: at the nominal
+    0.7 the thread diverges within a few hundred steps (the tau does not
+    change the work per node)."""
+    rho_g, rho_l = scheme_coexistence(G, tau)
     rho = thread_density(nz, nr, radius, rho_l, rho_g, 2.0, eps, mode)
     z = np.zeros_like(rho)
     return Case("rp_thread", nz, nr, G, tau, wall, rho, z, z.copy(), steps, rho_l, rho_g,
@@ -201,7 +242,8 @@ def ensemble(n=256, seed=7, sizes=((64, 32), (128, 64), (256, 128), (512, 256)))
     (configuration 'batched ensemble').  G ~ U[-6, -5]; tau ~ U[tau_min(G),
     1.0], where tau_min(G) is the scheme's stability limit (the workload's
     nominal range U[0.55, 1.0] diverges for most G in [-6, -5]); free-slip
-    wall; each instance starts at its own coexistence densities."""
+    wall; each instance starts at the scheme's coexistence densities for its
+    (G, tau)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     cases = []
     for k in range(n):
@@ -210,7 +252,7 @@ def ensemble(n=256, seed=7, sizes=((64, 32), (128, 64), (256, 128), (512, 256)))
         u = float(rng.uniform(0.0, 1.0))
         tau = stable_tau_min(G) + u * (1.0 - stable_tau_min(G))
         kind = int(rng.integers(2))
-        rho_g, rho_l = coexistence_densities(round(G, 6))
+        rho_g, rho_l = scheme_coexistence(G, tau)
         if kind == 0:
             rho = drop_density(nz, nr, nz / 2.0, 0.3 * nr, rho_l, rho_g, 2.0)
         else:

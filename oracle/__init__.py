@@ -121,6 +121,12 @@ def _pick(complex_step):
     return (libc, "orc_", np.complex128) if complex_step else (lib, "or_", np.float64)
 
 
+def set_threads(n):
+    """Number of OpenMP threads the oracle's loops use from now on (in this
+    process); the default is every host thread."""
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
 def lattice():
     """(cz, cr, w) as the oracle holds them."""
     lib, _ = _load()

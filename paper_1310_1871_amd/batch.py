@@ -21,6 +21,7 @@ _sigs = {
     "lbm_axi_batch_step_per_instance": (ctypes.c_int, [_vp, ctypes.c_int64]),
     "lbm_axi_batch_moments": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp]),
     "lbm_axi_batch_get_state": (ctypes.c_int, [_vp, _i32, _vp]),
+    "lbm_axi_batch_populations": (ctypes.c_int, [_vp, _i32, _vp]),
     "lbm_axi_batch_num_configs": (_i32, [_vp]),
     "lbm_axi_batch_config_info": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                                  ctypes.POINTER(_i32)]),
@@ -105,18 +106,15 @@ class AxiBatch:
         return rho, uz, ur
 
     def populations(self, k):
-        """Instance k's populations as float64 [9, nr, nz] (shift added back
-        in FP32 storage)."""
+        """Instance k's populations f_i as float64 [9, nr, nz], decoded by
+        the library (lbm_axi_batch_populations: the shift is added back in
+        FP32 storage)."""
         p = self.params[k]
-        esz = 8 if p.precision == L.FP64 else 4
         with torch.cuda.stream(self.stream):
-            raw = torch.empty(9 * p.nr * p.nz * esz, dtype=torch.uint8, device=self.device)
-        L.check(_lib.lbm_axi_batch_get_state(self._h, int(k), _vp(raw.data_ptr())))
+            out = torch.empty((9, p.nr, p.nz), dtype=torch.float64, device=self.device)
+        L.check(_lib.lbm_axi_batch_populations(self._h, int(k), _vp(out.data_ptr())))
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
-        if p.precision == L.FP64:
-            return raw.view(torch.float64).reshape(9, p.nr, p.nz).clone()
-        w = torch.tensor([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, dtype=torch.float64, device=self.device)
-        return raw.view(torch.float32).reshape(9, p.nr, p.nz).to(torch.float64) + w[:, None, None] * p.rho_ref
+        return out
 
     def synchronize(self):
         self.stream.synchronize()

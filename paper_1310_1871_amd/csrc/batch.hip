@@ -289,6 +289,8 @@ int lbm_axi_batch_create(const lbm_axi_params* ps, int32_t n_inst, const double*
         return rc;
     }
     *out = b;
+    for (int k = 0; k < n_inst; ++k)
+        if (ps[k].G < -6.0) return stability_warning(ps[k].G);
     return LBM_AXI_OK;
 }
 
@@ -333,6 +335,21 @@ int lbm_axi_batch_moments(lbm_axi_batch_t b, int32_t k, double* d_rho, double* d
     const TileFn fn = b->precision == LBM_AXI_FP64 ? kMom64[b->any_guo][b->cfg] : kMom32[b->any_guo][b->cfg];
     fn(dim3(tiles_of(b->p[k], b->config())), b->stream, a);
     HIP_TRY(hipGetLastError(), "moments launch");
+    return LBM_AXI_OK;
+}
+
+int lbm_axi_batch_populations(lbm_axi_batch_t b, int32_t k, double* d_f) {
+    if (!b || k < 0 || k >= (int)b->p.size() || !d_f) return fail(LBM_AXI_EINVAL, "bad batch, instance or d_f");
+    const lbm_axi_params& q = b->p[k];
+    const long long n = (long long)q.nz * q.nr;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (b->precision == LBM_AXI_FP64)
+        hipLaunchKernelGGL(decode_populations_kernel<lbm::PrecF64>, grid, dim3(256), 0, b->stream,
+                           static_cast<const double*>(b->buf(k, b->parity)), b->pitch(k), n, 0.0, d_f);
+    else
+        hipLaunchKernelGGL(decode_populations_kernel<lbm::PrecF32S>, grid, dim3(256), 0, b->stream,
+                           static_cast<const float*>(b->buf(k, b->parity)), b->pitch(k), n, q.rho_ref, d_f);
+    HIP_TRY(hipGetLastError(), "populations kernel launch");
     return LBM_AXI_OK;
 }
 

@@ -80,6 +80,16 @@ inline int check_params(const lbm_axi_params* p) {
     return LBM_AXI_OK;
 }
 
+// Sec. II.D: as a rule of thumb the scheme stays stable up to a density
+// ratio of about 35, reached at G = -6; stronger coupling is accepted with a
+// warning.  Returns LBM_AXI_WARN_STABILITY (message set) or LBM_AXI_OK.
+inline int stability_warning(double G) {
+    if (G < -6.0)
+        return fail(LBM_AXI_WARN_STABILITY,
+                    "G = %g < -6: beyond the stability rule of thumb (density ratio <= 35 for G >= -6)", G);
+    return LBM_AXI_OK;
+}
+
 // kernel option bits of a validated flags field (1 Guo forcing, 2 no
 // derivative terms across the wall, 4 z walls, 16 mid-link source; 8, open
 // rows, is set by lbm_axi_set_open)
@@ -105,6 +115,20 @@ __global__ void init_equilibrium_kernel(typename P::S* f, const double* rho, con
         const double w = lbm::weight(i);
         double v = P::kShift ? w * ((r - rho_ref) + r * poly) : w * r * (1.0 + poly);
         f[(long long)i * pitch + x] = typename P::S(v);
+    }
+}
+
+// the stored populations as FP64 f_i (FP32 shifted storage: + W_i rho_ref,
+// in double), from the library's padded layout into [9][n]
+template <class P>
+__global__ void decode_populations_kernel(const typename P::S* __restrict__ f, long long pitch, long long n,
+                                          double rho_ref, double* __restrict__ out) {
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+#pragma unroll
+    for (int i = 0; i < lbm::kQ; ++i) {
+        const double v = double(f[(long long)i * pitch + x]);
+        out[(long long)i * n + x] = P::kShift ? v + lbm::weight(i) * rho_ref : v;
     }
 }
 

@@ -15,6 +15,7 @@
 #include "common.hpp"
 #include "lattice.hpp"
 #include "step_kernel.hpp"
+#include "strip_kernel.hpp"
 
 namespace {
 
@@ -235,6 +236,8 @@ __global__ void drops_scan_kernel(const double* __restrict__ radius, const doubl
 
 struct lbm_axi_ctx {
     lbm_axi_params p;
+    int strip_rows = 0;  // chunk height of the row-marching step kernel, 0: tile kernel
+    int alternate = 0;   // tile kernel: walk the tiles in reverse order on every other step
     char* ws;
     size_t ws_bytes;
     Layout L;
@@ -278,6 +281,22 @@ template <bool kMoments, int kOpt>
 void launch_shape(lbm_axi_ctx* h, const lbm::StepArgs& a) {
     const dim3 grid(h->L.nblocks);
     const bool f64 = h->p.precision == LBM_AXI_FP64;
+    if constexpr (!kMoments && kOpt >= 0) {
+        if (h->strip_rows > 0) {
+            lbm::StripArgs sa;
+            sa.chunk_rows = h->strip_rows;
+            sa.chunks = (h->p.nr + sa.chunk_rows - 1) / sa.chunk_rows;
+            const int bands = (h->p.nz + lbm::kStripW - 1) / lbm::kStripW;
+            const dim3 sgrid(bands * sa.chunks);
+            if (f64)
+                hipLaunchKernelGGL((lbm::axi_strip_kernel<lbm::PrecF64, kOpt, 0>), sgrid, dim3(lbm::kStripNT), 0,
+                                   h->stream, a, sa);
+            else
+                hipLaunchKernelGGL((lbm::axi_strip_kernel<lbm::PrecF32S, kOpt, 16>), sgrid, dim3(lbm::kStripNT), 0,
+                                   h->stream, a, sa);
+            return;
+        }
+    }
     if (h->L.cfg == 0) {
         if (f64)
             hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, 64, 16, kNT64, kMoments, kOpt>), grid, dim3(kNT64),
@@ -330,6 +349,12 @@ int step_into(lbm_axi_ctx* h, lbm::StepArgs a, const void* fin, void* fout) {
 
 extern "C" {
 
+int lbm_axi_check_params(const lbm_axi_params* p) {
+    const int rc = check_params(p);
+    if (rc != LBM_AXI_OK) return rc;
+    return stability_warning(p->G);
+}
+
 size_t lbm_axi_workspace_bytes(const lbm_axi_params* p) {
     if (check_params(p) != LBM_AXI_OK) return 0;
     return layout_of(p, 0).total;
@@ -371,14 +396,15 @@ int lbm_axi_create(const lbm_axi_params* p, const double* d_rho0, const double* 
         return hip_fail(e, "init kernel launch");
     }
     *out = h;
-    return LBM_AXI_OK;
+    return stability_warning(p->G);
 }
 
 int lbm_axi_step(lbm_axi_t h, int64_t n) {
     if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
     if (n < 0) return fail(LBM_AXI_EINVAL, "n must be >= 0");
-    const lbm::StepArgs a = make_args(h);
+    lbm::StepArgs a = make_args(h);
     for (int64_t s = 0; s < n; ++s) {
+        a.reverse = h->alternate ? h->cur : 0;
         const int rc = step_into(h, a, state_ptr(h, h->cur), state_ptr(h, 1 - h->cur));
         if (rc != LBM_AXI_OK) return rc;
         h->cur = 1 - h->cur;
@@ -470,6 +496,7 @@ int lbm_axi_set_open(lbm_axi_t h, int32_t in_row, double rho_in, const double* d
     }
     h->in_row = in_row;
     h->out_row = out_row;
+    if (in_row >= 0 || out_row >= 0) h->strip_rows = 0;  // open rows run on the tile kernel
     h->rho_in = rho_in;
     h->rho_out = rho_out;
     return LBM_AXI_OK;
@@ -513,6 +540,21 @@ int lbm_axi_drops(lbm_axi_t h, double rho_mid, int32_t max_drops, int32_t* h_cou
         h_volume[k] = host[1 + k];
         h_centre[k] = host[1 + max_drops + k];
     }
+    return LBM_AXI_OK;
+}
+
+int lbm_axi_populations(lbm_axi_t h, double* d_f) {
+    if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
+    if (!d_f) return fail(LBM_AXI_EINVAL, "d_f is NULL");
+    const long long n = (long long)h->p.nz * h->p.nr;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (h->p.precision == LBM_AXI_FP64)
+        hipLaunchKernelGGL(decode_populations_kernel<lbm::PrecF64>, grid, dim3(256), 0, h->stream,
+                           static_cast<const double*>(state_ptr(h, h->cur)), h->L.pitch, n, 0.0, d_f);
+    else
+        hipLaunchKernelGGL(decode_populations_kernel<lbm::PrecF32S>, grid, dim3(256), 0, h->stream,
+                           static_cast<const float*>(state_ptr(h, h->cur)), h->L.pitch, n, h->p.rho_ref, d_f);
+    HIP_TRY(hipGetLastError(), "populations kernel launch");
     return LBM_AXI_OK;
 }
 
@@ -562,6 +604,23 @@ int lbm_axi_record(lbm_axi_t h, int64_t n, void* d_states) {
     return LBM_AXI_OK;
 }
 
+int lbm_axi_set_kernel(lbm_axi_t h, int32_t kind, int32_t chunk_rows) {
+    if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
+    if (kind == LBM_AXI_KERNEL_TILE || kind == 2) {
+        h->strip_rows = 0;
+        h->alternate = kind == 2;
+        return LBM_AXI_OK;
+    }
+    if (kind != LBM_AXI_KERNEL_STRIP) return fail(LBM_AXI_EINVAL, "kind must be LBM_AXI_KERNEL_TILE or _STRIP");
+    if (chunk_rows < 1) return fail(LBM_AXI_EINVAL, "chunk_rows must be >= 1 (got %d)", chunk_rows);
+    if (h->p.nz < lbm::kStripW + 6)
+        return fail(LBM_AXI_EUNSUP, "the row-marching kernel needs nz >= %d (got %d)", lbm::kStripW + 6, h->p.nz);
+    if ((option_bits(h->p.flags) & ~3) != 0 || h->in_row >= 0 || h->out_row >= 0)
+        return fail(LBM_AXI_EUNSUP, "the row-marching kernel supports the Guo and wall-derivative options only");
+    h->strip_rows = chunk_rows;
+    return LBM_AXI_OK;
+}
+
 int lbm_axi_set_stream(lbm_axi_t h, void* hip_stream) {
     if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
     h->stream = static_cast<hipStream_t>(hip_stream);
@@ -576,7 +635,7 @@ int lbm_axi_set_coupling(lbm_axi_t h, double G, double tau) {
     int rc = check_params(&q);
     if (rc != LBM_AXI_OK) return rc;
     h->p = q;
-    return LBM_AXI_OK;
+    return stability_warning(G);
 }
 
 void lbm_axi_destroy(lbm_axi_t h) { delete h; }

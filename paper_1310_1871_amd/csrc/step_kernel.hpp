@@ -43,6 +43,7 @@ struct StepArgs {
     int nz, nr;
     int tiles_z;       // tiles along z (tile id = tr * tiles_z + tz: z fastest)
     int big_nz;        // 1 if nz >= TZ + 6: periodic wrap needs one add/sub
+    int reverse;       // 1: each XCD walks its run of tiles from the end
     int wall;          // 0 no-slip, 1 free-slip
     int axisym;        // 1 axisymmetric terms on
     int opts;          // option bits: 1 Guo forcing, 2 no derivative terms across the wall,
@@ -91,6 +92,14 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     const int q = nb >> 3, rem = nb & 7;
     const int x = b & 7, k = b >> 3;
     return x * q + (x < rem ? x : rem) + k;
+}
+
+// the same runs, each walked from its last tile to its first
+__device__ __forceinline__ int xcd_remap_rev(int b, int nb) {
+    const int q = nb >> 3, rem = nb & 7;
+    const int x = b & 7, k = b >> 3;
+    const int len = q + (x < rem ? 1 : 0);
+    return x * q + (x < rem ? x : rem) + (len - 1 - k);
 }
 
 __device__ __forceinline__ int wrap_z(int z, int nz, bool big) {
@@ -473,10 +482,23 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         };
 
         if constexpr (kMoments) {
+            // the moments and the global sums are formed in FP64 from the
+            // stored values (in FP32 storage the nine values and rho_ref are
+            // added in double; the force stays that of the FP32 step)
+            double rho_d = 0.0;
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) rho_d += double(f[k][i]);
+            if (P::kShift) rho_d += a.rho_ref;
+            auto dv = [&](int i) { return double(f[k][i]); };
+            const double jz_d = (dv(1) - dv(3)) + (dv(5) - dv(6)) + (dv(8) - dv(7));
+            const double jr_d = (dv(2) - dv(4)) + (dv(5) - dv(8)) + (dv(6) - dv(7));
+            const double inv_rho_d = dev_rcp(rho_d);
+            const double uz_d = (jz_d + 0.5 * double(Fz_t[k])) * inv_rho_d;
+            const double ur_d = (jr_d + 0.5 * double(Fr_t[k])) * inv_rho_d;
             const long long x = (long long)gr * nz + gz;
-            if (a.rho_out) a.rho_out[x] = double(rho);
-            if (a.uz_out) a.uz_out[x] = double(uz);
-            if (a.ur_out) a.ur_out[x] = double(ur);
+            if (a.rho_out) a.rho_out[x] = rho_d;
+            if (a.uz_out) a.uz_out[x] = uz_d;
+            if (a.ur_out) a.ur_out[x] = ur_d;
             if (a.h_out) {
                 C hz = C(0), hr = C(0), mass = C(0);
                 if (a.axisym) source_terms(hz, hr, mass);
@@ -486,10 +508,10 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
                 a.h_out[2 * hn + x] = double(mass);
             }
             const double two_pi_r = 6.283185307179586 * double(rr);
-            part[0] += two_pi_r * double(rho);
-            part[1] += two_pi_r * double(rho) * double(uz);
-            part[2] += 0.5 * two_pi_r * double(rho) * (double(uz) * double(uz) + double(ur) * double(ur));
-            part[3] += double(rho);
+            part[0] += two_pi_r * rho_d;
+            part[1] += two_pi_r * rho_d * uz_d;
+            part[2] += 0.5 * two_pi_r * rho_d * (uz_d * uz_d + ur_d * ur_d);
+            part[3] += rho_d;
         } else {
             const C Fz = Fz_t[k], Fr = Fr_t[k];
             C hz = C(0), hr = C(0), mass = C(0);
@@ -659,7 +681,8 @@ __device__ __forceinline__ int slab_tile(int b, int nb, int tiles_z) {
 // kSlab: slab order (slab_tile) instead of runs of tile rows (xcd_remap)
 template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt = 0, bool kSlab = false, int kStoreAux = 0>
 __global__ __launch_bounds__(NT) void axi_tile_kernel(const StepArgs a) {
-    const int tile = kSlab ? slab_tile(blockIdx.x, gridDim.x, a.tiles_z) : xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = kSlab ? slab_tile(blockIdx.x, gridDim.x, a.tiles_z)
+                           : (a.reverse ? xcd_remap_rev(blockIdx.x, gridDim.x) : xcd_remap(blockIdx.x, gridDim.x));
     tile_body<P, TZ, TR, NT, kMoments, kOpt, kStoreAux>(a, tile, blockIdx.x);
 }
 

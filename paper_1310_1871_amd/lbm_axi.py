@@ -7,6 +7,7 @@ CPU fallback.
 """
 import ctypes
 import os
+import warnings
 
 import torch
 
@@ -19,6 +20,7 @@ ENOMEM = -2
 EHIP = -3
 ENONFINITE = -4
 EUNSUP = -5
+WARN_STABILITY = 1  # success with a warning: G < -6 (Sec. II.D stability rule of thumb)
 
 WALL_NOSLIP = 0
 WALL_FREESLIP = 1
@@ -31,6 +33,8 @@ FLAG_MIDLINK = 16  # source h_i averaged over each link instead of the node valu
 NREDUCE = 4
 NINTERFACE = 7
 MAX_DROPS = 64
+KERNEL_TILE = 0
+KERNEL_STRIP = 1
 
 
 class Params(ctypes.Structure):
@@ -63,6 +67,7 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     vp, P = ctypes.c_void_p, ctypes.POINTER(Params)
     sigs = {
+        "lbm_axi_check_params": (ctypes.c_int, [P]),
         "lbm_axi_workspace_bytes": (ctypes.c_size_t, [P]),
         "lbm_axi_create": (ctypes.c_int, [P, vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
         "lbm_axi_step": (ctypes.c_int, [vp, ctypes.c_int64]),
@@ -73,10 +78,12 @@ def _load():
                                             ctypes.c_double]),
         "lbm_axi_drops": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+        "lbm_axi_populations": (ctypes.c_int, [vp, vp]),
         "lbm_axi_state_bytes": (ctypes.c_size_t, [vp]),
         "lbm_axi_get_state": (ctypes.c_int, [vp, vp]),
         "lbm_axi_set_state": (ctypes.c_int, [vp, vp]),
         "lbm_axi_record": (ctypes.c_int, [vp, ctypes.c_int64, vp]),
+        "lbm_axi_set_kernel": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32]),
         "lbm_axi_set_stream": (ctypes.c_int, [vp, vp]),
         "lbm_axi_set_coupling": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double]),
         "lbm_axi_destroy": (None, [vp]),
@@ -96,10 +103,23 @@ def last_error():
     return lib.lbm_axi_last_error().decode()
 
 
+class StabilityWarning(UserWarning):
+    """Parameters outside the stability rule of thumb of Sec. II.D."""
+
+
 def check(rc):
+    if rc > 0:
+        warnings.warn(last_error(), StabilityWarning, stacklevel=3)
+        return rc
     if rc != OK:
         raise LbmAxiError(rc, last_error())
     return rc
+
+
+def check_params(params):
+    """Validate parameters without a device (lbm_axi_check_params): OK or
+    WARN_STABILITY (with a warning), LbmAxiError otherwise."""
+    return check(lib.lbm_axi_check_params(ctypes.byref(params)))
 
 
 def _ptr(t):
@@ -259,14 +279,18 @@ class AxiLBM:
         check(lib.lbm_axi_record(self._h, int(n), _ptr(out)))
 
     def populations(self):
-        """Current populations as a float64 tensor [9, nr, nz] (the shift is
-        added back in FP32 storage)."""
-        raw = self.get_state()
-        if self.params.precision == FP64:
-            return raw.view(torch.float64).reshape(9, self.nr, self.nz).clone()
-        g = raw.view(torch.float32).reshape(9, self.nr, self.nz).to(torch.float64)
-        w = torch.tensor([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, dtype=torch.float64, device=self.device)
-        return g + w[:, None, None] * self.params.rho_ref
+        """Current populations f_i as a float64 tensor [9, nr, nz], decoded
+        by the library (lbm_axi_populations: the shift is added back in FP32
+        storage)."""
+        self._sync_stream()
+        out = torch.empty((9, self.nr, self.nz), dtype=torch.float64, device=self.device)
+        check(lib.lbm_axi_populations(self._h, _ptr(out)))
+        return out
+
+    def set_kernel(self, kind, chunk_rows=48):
+        """Step kernel: KERNEL_TILE or KERNEL_STRIP with chunks of
+        chunk_rows rows (include/lbm_axi.h, lbm_axi_set_kernel)."""
+        check(lib.lbm_axi_set_kernel(self._h, int(kind), int(chunk_rows)))
 
     def set_coupling(self, G, tau):
         check(lib.lbm_axi_set_coupling(self._h, float(G), float(tau)))

@@ -51,6 +51,29 @@ def test_parameter_validation():
     assert "MIDLINK" in L.last_error()
 
 
+def test_stability_rule_warning():
+    """Sec. II.D: a density ratio of about 35 (G >= -6) is the scheme's
+    stability limit as a rule of thumb.  check_params (no device) returns the
+    positive warning code LBM_AXI_WARN_STABILITY for G < -6, with a message,
+    and OK at G = -6; invalid parameters still return their error."""
+    import warnings
+    from paper_1310_1871_amd import lbm_axi as L
+    assert L.lib.lbm_axi_check_params(ctypes.byref(L.make_params(64, 32, G=-6.0))) == L.OK
+    assert L.lib.lbm_axi_check_params(ctypes.byref(L.make_params(64, 32, G=-5.5))) == L.OK
+    assert L.lib.lbm_axi_check_params(ctypes.byref(L.make_params(64, 32, G=-6.5))) == L.WARN_STABILITY
+    assert "-6.5" in L.last_error() and "stability" in L.last_error()
+    assert L.lib.lbm_axi_check_params(ctypes.byref(L.make_params(64, 32, G=-6.5, tau=0.4))) == L.EINVAL
+    assert L.lib.lbm_axi_check_params(None) == L.EINVAL
+    # the workspace size is unaffected, and the binding turns the code into a warning
+    assert L.workspace_bytes(L.make_params(64, 32, G=-6.5)) == L.workspace_bytes(L.make_params(64, 32))
+    with warnings.catch_warnings(record=True) as w:
+        warnings.simplefilter("always")
+        assert L.check_params(L.make_params(64, 32, G=-7.0)) == L.WARN_STABILITY
+    assert any(issubclass(x.category, L.StabilityWarning) for x in w)
+    with pytest.raises(L.LbmAxiError):
+        L.check_params(L.make_params(64, 5))
+
+
 def test_fp32_workspace_is_half():
     from paper_1310_1871_amd import lbm_axi as L
     a = L.workspace_bytes(L.make_params(4096, 512, precision=L.FP64))
@@ -74,6 +97,8 @@ def test_create_rejects_bad_pointers_without_device_work():
     n = ctypes.c_int32()
     assert L.lib.lbm_axi_drops(None, 1.0, 4, ctypes.byref(n), None, None) == L.EINVAL
     assert L.lib.lbm_axi_set_open(None, 9, 1.0, None, None, 20, 1.0) == L.EINVAL
+    assert L.lib.lbm_axi_populations(None, ctypes.c_void_p(4096)) == L.EINVAL
+    assert L.lib.lbm_axi_set_kernel(None, L.KERNEL_STRIP, 48) == L.EINVAL
     L.lib.lbm_axi_destroy(None)
 
 

@@ -275,3 +275,64 @@ def test_nonfinite_is_reported():
     with pytest.raises(L.LbmAxiError) as e:
         sim.reduce()
     assert e.value.code == L.ENONFINITE
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_populations_export_decodes_on_device(precision):
+    """lbm_axi_populations returns f_i in FP64: the stored state itself in
+    FP64 storage, and the FP32 values plus W_i rho_ref (added in double) in
+    shifted storage, equal to a decode of get_state done here."""
+    L = _lib()
+    rg, rl = coexistence_densities(-5.5)
+    rho = drop_density(96, 48, 48.0, 14.0, rl, rg, 2.0, {2: 1.0})
+    rref = 0.0 if precision == 0 else rg
+    sim = L.AxiLBM(L.make_params(96, 48, G=-5.5, tau=0.9, precision=precision, rho_ref=rref),
+                   torch.from_numpy(rho).cuda())
+    sim.step(20)
+    f = sim.populations().cpu().numpy()
+    raw = sim.get_state().cpu().numpy()
+    if precision == 0:
+        ref = raw.view(np.float64).reshape(9, 48, 96)
+    else:
+        w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+        ref = raw.view(np.float32).reshape(9, 48, 96).astype(np.float64) + w[:, None, None] * rref
+    assert np.array_equal(f, ref)
+    sim.close()
+
+
+def test_fp32_global_sums_are_fp64():
+    """In FP32 storage the 3D mass and 2D mass of lbm_axi_reduce are FP64
+    sums of the decoded populations: they equal a numpy FP64 sum of
+    lbm_axi_populations to summation-order round-off (1e-14)."""
+    L = _lib()
+    rg, rl = coexistence_densities(-5.5)
+    rho = drop_density(256, 128, 128.0, 40.0, rl, rg, 2.0, {2: 2.0})
+    sim = L.AxiLBM(L.make_params(256, 128, G=-5.5, tau=0.9, precision=L.FP32_SHIFTED, rho_ref=rg),
+                   torch.from_numpy(rho).cuda())
+    sim.step(50)
+    red = sim.reduce()
+    f = sim.populations().cpu().numpy()
+    dens = f.sum(axis=0)
+    r = np.arange(128)[:, None] + 0.5
+    m3 = float(np.sum(2.0 * np.pi * r * dens))
+    _say(f"FP32 3D mass: reduce {red[0]!r} numpy {m3!r}")
+    assert abs(red[0] - m3) <= 1e-14 * m3
+    assert abs(red[3] - float(dens.sum())) <= 1e-14 * float(dens.sum())
+    rg_, _, _ = (t.cpu().numpy() for t in sim.moments())
+    assert np.abs(rg_ - dens).max() <= 1e-14
+    sim.close()
+
+
+def test_stability_warning_on_create():
+    """G < -6 (outside the rule of thumb of Sec. II.D) creates the handle
+    with LBM_AXI_WARN_STABILITY, which the binding turns into a warning;
+    the lattice still steps."""
+    L = _lib()
+    rho = np.full((32, 64), 1.0)
+    with pytest.warns(L.StabilityWarning):
+        sim = L.AxiLBM(L.make_params(64, 32, G=-6.5, tau=1.0), torch.from_numpy(rho).cuda())
+    sim.step(5)
+    assert np.isfinite(sim.reduce()).all()
+    with pytest.warns(L.StabilityWarning):
+        sim.set_coupling(-6.2, 1.0)
+    sim.close()
