@@ -79,11 +79,13 @@ _libc = None
 def _load():
     global _lib, _libc
     if _lib is None:
-        path = os.path.join(_HERE, "liboracle.so")
-        cpath = os.path.join(_HERE, "liboracle_complex.so")
+        # ORACLE_LIB_SUFFIX=_san selects the sanitizer build (CPU sanitizer test)
+        suffix = os.environ.get("ORACLE_LIB_SUFFIX", "")
+        path = os.path.join(_HERE, f"liboracle{suffix}.so")
+        cpath = os.path.join(_HERE, f"liboracle_complex{suffix}.so")
         if not (os.path.exists(path) and os.path.exists(cpath)):
             from . import build as _b
-            _b.build()
+            _b.build(sanitize=suffix == "_san")
         _lib = ctypes.CDLL(path)
         _libc = ctypes.CDLL(cpath)
         P = ctypes.POINTER(Params)

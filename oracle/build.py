@@ -16,10 +16,20 @@ OUTPUTS = {
 }
 
 
-def build(verbose=False):
+# AddressSanitizer + UndefinedBehaviorSanitizer builds for the CPU sanitizer
+# test (clang, whose shared sanitizer runtime the HIP host code shares)
+SAN_CC = "/opt/rocm/llvm/bin/clang"
+SAN_FLAGS = ["-O1", "-g", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+             "-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-shared-libsan"]
+
+
+def build(verbose=False, sanitize=False):
     for name, extra in OUTPUTS.items():
-        out = os.path.join(HERE, name)
-        cmd = ["gcc", *FLAGS, *extra, "-o", out + ".tmp", SRC, "-lm"]
+        out = os.path.join(HERE, name.replace(".so", "_san.so") if sanitize else name)
+        if sanitize:
+            cmd = [SAN_CC, *SAN_FLAGS, *extra, "-o", out + ".tmp", SRC, "-lm"]
+        else:
+            cmd = ["gcc", *FLAGS, *extra, "-o", out + ".tmp", SRC, "-lm"]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

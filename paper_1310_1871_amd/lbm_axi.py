@@ -12,7 +12,9 @@ import warnings
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblbm_axi.so")
+# LBM_AXI_LIB names another build of the library (the host-sanitized one of
+# the CPU sanitizer test); the default is the in-tree HIP build
+LIB_PATH = os.environ.get("LBM_AXI_LIB", os.path.join(_HERE, "liblbm_axi.so"))
 
 OK = 0
 EINVAL = -1

@@ -222,12 +222,12 @@ def test_shape_loss_gradient_full_adjoint_workload():
     """The full adjoint workload: 256 x 128 drop of radius 40 (G = -5.5,
     tau = 0.8), 2000 steps, 16 rays sampled every 50 steps, checkpoints
     every 100 steps; target history from seeded Legendre coefficients
-    a_2..a_6 in [-0.05 R, 0.05 R] (seed 11), base point from seed 12.  The
-    7 adjoint gradients (a_2..a_6 through rho0, G, tau) agree with central
-    finite differences of the GPU loss (h = 1e-6) to 1e-6 relative, and the
-    GPU loss equals the oracle's to 1e-9.  (The oracle's complex-step
-    gradient is compared on the reduced workload above: at this size it
-    would take minutes.)"""
+    a_2..a_6 in [-0.05 R, 0.05 R] (seed 11, run by the oracle), base point
+    from seed 12.  The 7 adjoint gradients (a_2..a_6 through rho0, G, tau)
+    agree with the oracle's complex-step gradient and with central finite
+    differences of the GPU loss (h = 1e-6), both to 1e-6 relative, and the
+    GPU loss equals the oracle's to 1e-9.  (The complex-step oracle takes
+    about 40 s on 8 host threads here.)"""
     L, A = _libs()
     nz, nr, R, G, tau = 256, 128, 40.0, -5.5, 0.8
     rg, rl = coexistence_densities(G)
@@ -235,10 +235,18 @@ def test_shape_loss_gradient_full_adjoint_workload():
     steps, every, ck = 2000, 50, 100
     zc = nz / 2.0
     th = A.default_thetas(16)
-    _say("adjoint full workload 256x128, 2000 steps: GPU target history")
+    W = D.interface_radius_weights(nz, nr, zc, th)
+    p = O.make_params(nz, nr, G=G, tau=tau, wall=0)
+    _say("adjoint full workload 256x128, 2000 steps: oracle target history")
+    rho_t = drop_density(nz, nr, zc, R, rl, rg, 2.0, adjoint_coeffs(11, R))
+    f = O.equilibrium(p, rho_t, 0 * rho_t, 0 * rho_t)
+    targets = []
+    for _ in range(steps // every):
+        f = O.run(p, f, every)
+        targets.append(D.interface_radius(f.sum(0), W, rl, rg))
+    targets = np.array(targets)
     probe = A.RayProbe(nz, nr, zc, th, rl, rg)
-    tgt = A.radius_history(torch.from_numpy(drop_density(nz, nr, zc, R, rl, rg, 2.0, adjoint_coeffs(11, R))).cuda(),
-                           G, tau, probe, steps, every)
+    tgt = torch.from_numpy(targets).cuda()
     a_0 = adjoint_coeffs(12, R)
     rho0 = drop_density(nz, nr, zc, R, rl, rg, 2.0, a_0)
     J = drop_density_jacobian(nz, nr, zc, R, rl, rg, 2.0, a_0, ls)
@@ -252,11 +260,20 @@ def test_shape_loss_gradient_full_adjoint_workload():
     g_gpu = np.array([np.sum(g_rho * J[k]) for k in range(len(ls))] + [Gt.grad.item(), Tt.grad.item()])
     _say(f"  loss {loss.item():.12e} grad {g_gpu}")
     _say("  oracle loss")
-    W = D.interface_radius_weights(nz, nr, zc, th)
-    p = O.make_params(nz, nr, G=G, tau=tau, wall=0)
-    L0 = _oracle_loss(nz, nr, G, tau, O.equilibrium(p, rho0, 0 * rho0, 0 * rho0), W, tgt.cpu().numpy(), steps,
-                      every, rl, rg)
+    f0 = O.equilibrium(p, rho0, 0 * rho0, 0 * rho0)
+    L0 = _oracle_loss(nz, nr, G, tau, f0, W, targets, steps, every, rl, rg)
     assert abs(loss.item() - L0) <= 1e-9 * abs(L0)
+    w9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None]
+    g_or = []
+    for k in range(len(ls)):
+        _say(f"  oracle complex step a_{ls[k]}")
+        g_or.append(_oracle_loss(nz, nr, G, tau, f0 + 1j * H * w9 * J[k], W, targets, steps, every, rl, rg).imag / H)
+    _say("  oracle complex step G, tau")
+    g_or.append(_oracle_loss(nz, nr, G, tau, f0, W, targets, steps, every, rl, rg, G_im=H).imag / H)
+    g_or.append(_oracle_loss(nz, nr, G, tau, f0, W, targets, steps, every, rl, rg, tau_im=H).imag / H)
+    g_or = np.array(g_or)
+    _say(f"  oracle grad {g_or}  max rel diff {np.max(np.abs(g_gpu - g_or) / np.abs(g_or)):.3e}")
+    assert np.all(np.abs(g_gpu - g_or) <= 1e-6 * np.abs(g_or)), (g_gpu, g_or)
     _say("  GPU central differences")
     h = 1e-6
     fd = []
