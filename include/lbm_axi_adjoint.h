@@ -45,6 +45,24 @@ size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr);
 int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const double* d_lam_next, double* d_lam,
                          double* d_grad_acc, void* d_ws, size_t ws_bytes, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * reverse step as lbm_axi_adjoint_step, with its scratch in a static device
+ * array of LBM_AXI_NOALLOC_SCRATCH_BYTES (24 MiB) that the library holds on
+ * every GPU it runs on until the process ends, instead of a workspace
+ * argument.  Grids whose lbm_axi_adjoint_workspace_bytes exceed it (beyond
+ * about 300 x 150; the 256 x 128 drop needs 16.5 MiB) return
+ * LBM_AXI_ENOMEM with a message.  The caller passes inputs and outputs as
+ * for lbm_axi_adjoint_step.  Allocates nothing (no hipMalloc, hipFree or
+ * allocating library call); the first call on a device looks the array's
+ * address up.  Every call on one GPU uses that GPU's one array: calls that
+ * overlap on a GPU (other streams, other threads) race and must be
+ * serialised by the caller.  The array keeps the last call's contents; the
+ * step overwrites everything it reads. */
+#define LBM_AXI_NOALLOC_SCRATCH_BYTES (24u << 20)
+int lbm_axi_adjoint_step_noalloc(const lbm_axi_params* p, const double* d_f, const double* d_lam_next, double* d_lam,
+                                 double* d_grad_acc, void* hip_stream);
+
 /* k reverse steps over a recorded segment (lbm_axi_record, FP64):
  * d_states holds f^{t0}, ..., f^{t0+k-1} ([k][9][nr][nz]).  On entry d_lam
  * holds lam^{t0+k} = dL/df^{t0+k}; on return it holds lam^{t0}, the same

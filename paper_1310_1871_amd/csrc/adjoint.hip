@@ -27,11 +27,20 @@
 
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/lbm_axi.h"
 #include "../../include/lbm_axi_adjoint.h"
+#include "common.hpp"
 #include "lattice.hpp"
+
+// Scratch of the allocation-free reverse step (lbm_axi_adjoint_step_noalloc):
+// a file-scope device array, one per GPU the library runs on, held until the
+// process ends.  Host code reaches it only through the address
+// hipGetSymbolAddress gives on each device (the array's name is a host-side
+// stand-in there).
+static __device__ __align__(256) double scratch[LBM_AXI_NOALLOC_SCRATCH_BYTES / sizeof(double)];
 
 namespace {
 
@@ -783,9 +792,57 @@ int check_adjoint(const lbm_axi_params* p, size_t ws_bytes) {
     return LBM_AXI_OK;
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's scratch address, looked up once per device
+int noalloc_scratch(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return lbm_host::hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return lbm_host::fail(LBM_AXI_EUNSUP, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return lbm_host::hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return lbm_host::fail(LBM_AXI_EHIP, "hipGetSymbolAddress(scratch) gave a null address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_AXI_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int lbm_axi_adjoint_step_noalloc(const lbm_axi_params* p, const double* d_f, const double* d_lam_next, double* d_lam,
+                                 double* d_grad_acc, void* hip_stream) {
+    if (!p || !d_f || !d_lam_next || !d_lam) return lbm_host::fail(LBM_AXI_EINVAL, "NULL argument");
+    const size_t need = lbm_axi_adjoint_workspace_bytes(p->nz, p->nr);
+    if (need == 0) return lbm_host::fail(LBM_AXI_EINVAL, "invalid grid %d x %d for the adjoint", p->nz, p->nr);
+    if (need > (size_t)LBM_AXI_NOALLOC_SCRATCH_BYTES)
+        return lbm_host::fail(LBM_AXI_ENOMEM,
+                              "grid %d x %d needs %zu bytes of scratch; the static scratch holds %zu "
+                              "(use lbm_axi_adjoint_step with a workspace)",
+                              p->nz, p->nr, need, (size_t)LBM_AXI_NOALLOC_SCRATCH_BYTES);
+    const int rc = check_adjoint(p, need);
+    if (rc != LBM_AXI_OK) return lbm_host::fail(rc, "adjoint parameters rejected (FP64, flags 0, tau > 1/2)");
+    void* ws = nullptr;
+    const int rs = noalloc_scratch(&ws);
+    if (rs != LBM_AXI_OK) return rs;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    // the kernels overwrite every field and partial sum of one step before
+    // reading it, so nothing needs clearing
+    AdjArgs a = adjoint_args(p, ws, 0);
+    launch_reverse_step(a, d_f, d_lam_next, d_lam, s);
+    if (d_grad_acc)
+        hipLaunchKernelGGL(rev_reduce, dim3(1), dim3(256), 0, s, a.w + part_off(a.n, a.ne), nparts_of(a), d_grad_acc);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LBM_AXI_OK : lbm_host::hip_fail(e, "adjoint kernel launch");
+}
 
 size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr) {
     if (nz < 4 || nr < 6 || (long long)nz * (nr + 2 * NGA) > INT_MAX) return 0;
