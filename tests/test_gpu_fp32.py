@@ -43,7 +43,7 @@ def _sim(case, precision, rho_ref=0.0):
 
 def _fit_frequency(ts, A, t_min=3000.0):
     """Fit g(t) = R_D + a exp(-b t) sin(w t + d) (Sec. IV.B) to A(t) for
-    t > t_min (after the drop has condensed gas and settled near R_D ~ 47.7)
+    t > t_min (after the start-up transient; the drop settles near R_D ~ 40)
     from a few starting phases and periods; returns |w| of the best fit."""
     g = lambda t, R0, a, b, w, d: R0 + a * np.exp(-b * t) * np.sin(w * t + d)
     m = ts > t_min
@@ -133,10 +133,11 @@ def test_fp32_mass_drift_planar():
 
 def test_fp32_drop_frequency_vs_oracle():
     """l = 2 frequency of the oscillating drop (256 x 128, tau = 0.8, 20000
-    steps, A(t) every 10 steps, period about 4000 steps) from FP32 storage
+    steps, A(t) every 10 steps, period about 3100 steps) from FP32 storage
     (rho_ref = rho_g) vs the FP64 oracle's: relative difference <= 0.5 %.
     The GPU FP64 trace is also fitted and must reproduce the oracle's
-    frequency to 1e-6."""
+    frequency to 1e-6.  Both are compared with Miller and Scriven's
+    frequency (Sec. IV.B) at the fitted R_D: +2.1 % (bound 3 %)."""
     case = oscillating_drop()
     steps, every = 20000, 10
     mid = 0.5 * (case.rho_l + case.rho_g)
@@ -162,6 +163,35 @@ def test_fp32_drop_frequency_vs_oracle():
          f"max|dA| FP32 {np.max(np.abs(A32 - Ao)):.3e}")
     assert abs(w64 - w_o) / w_o < 1e-6
     assert err <= 5e-3
+    # the frequency against Miller and Scriven's w_2 (Eq. freq-drop-miller)
+    # at the fitted R_D, with the surface tension of Eq. stc from a flat
+    # interface at the same (G, tau) and the measured bulk densities
+    gam = _flat_surface_tension(case.G, case.tau)
+    rin, rout = float(rr[0, case.nz // 2]), float(rr[-1, 0])
+    nu = (case.tau - 0.5) / 3.0
+    for name, (t_, A_) in (("FP64", (t64, A64)), ("FP32", (t32, A32))):
+        w, popt = _fit_frequency(t_, A_)
+        R0 = popt[0]
+        w0 = np.sqrt(24 * gam / (R0 ** 3 * (2 * rout + 3 * rin)))
+        al = 25 * nu * rin * rout / (np.sqrt(2) * R0 * (2 * rout + 3 * rin) * (np.sqrt(nu) * (rin + rout)))
+        ms = w0 - 0.5 * al * np.sqrt(w0) + 0.25 * al * al
+        _say(f"  {name}: R_D {R0:.3f}  omega {w:.6e}  Miller-Scriven {ms:.6e}  rel err {w / ms - 1:+.4f}")
+        # the paper reports about 1 % at G = -6, tau = 1 on 320 x 128 (the
+        # oracle pin reproduces that); this drop (G = -5.5, tau = 0.8,
+        # R = 40) is 2.1 % fast
+        assert abs(w / ms - 1.0) < 0.03
+
+
+def _flat_surface_tension(G, tau):
+    """gamma-tilde (Eq. stc) of a flat interface on 1 x 64 at (G, tau),
+    from the oracle (Table I's set-up)."""
+    from lbm_inputs import node_coords, scheme_coexistence, tanh_profile
+    rg, rl = scheme_coexistence(G, tau)
+    p = O.make_params(1, 64, G=G, tau=tau, wall=1, axisym=0)
+    _, r = node_coords(1, 64)
+    rho = tanh_profile(r, 32.0, rl, rg, 2.0)
+    fl = O.fields(p, O.run(p, O.equilibrium(p, rho, 0 * rho, 0 * rho), 20000))
+    return D.surface_tension_sc(fl["rho"], fl["f_r"], G, tau)[0]
 
 
 # bulk densities the scheme settles to at G = -5.5, tau = 0.8 (measured on a
