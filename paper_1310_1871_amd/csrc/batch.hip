@@ -12,7 +12,7 @@
 #include "../../include/lbm_axi.h"
 #include "../../include/lbm_axi_batch.h"
 #include "common.hpp"
-#include "step_kernel.hpp"
+#include "batch_kernel.hpp"
 
 using namespace lbm_host;
 
@@ -199,8 +199,11 @@ int rebuild(lbm_axi_batch* b) {
     return LBM_AXI_OK;
 }
 
+// a multiple of 8 workgroups, at least 8: the batch kernel splits the work
+// list into one contiguous range per XCD
 int grid_size(lbm_axi_batch* b) {
-    return std::max(1, std::min(b->n_items, b->grid_per_cu * b->cus));
+    const int g = std::max(1, std::min(b->n_items, b->grid_per_cu * b->cus));
+    return (g + 7) / 8 * 8;
 }
 
 int launch_once(lbm_axi_batch* b, hipStream_t s, int parity) {

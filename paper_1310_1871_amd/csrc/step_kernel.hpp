@@ -686,30 +686,4 @@ __global__ __launch_bounds__(NT) void axi_tile_kernel(const StepArgs a) {
     tile_body<P, TZ, TR, NT, kMoments, kOpt, kStoreAux>(a, tile, blockIdx.x);
 }
 
-// Batched ensemble: many independent lattices (each with its own size,
-// parameters and buffers) advanced by one persistent launch.  Work item k is
-// (instance, tile); workgroups stride over the work list, so one launch
-// covers every instance whatever their sizes.  `parity` selects which of an
-// instance's two buffers is read.
-struct BatchInstance {
-    StepArgs args[2];  // [parity]: fin/fout swapped
-};
-
-template <class P, int TZ, int TR, int NT, int kOpt = 0>
-__global__ __launch_bounds__(NT) void axi_batch_kernel(const BatchInstance* __restrict__ insts,
-                                                      const int2* __restrict__ items, int n_items, int parity) {
-    for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
-        // the work item is uniform over the workgroup: keep it (and the
-        // instance arguments it selects) in scalar registers
-        const int2 w = items[k];
-        const int inst = __builtin_amdgcn_readfirstlane(w.x);
-        const int tile = __builtin_amdgcn_readfirstlane(w.y);
-        const StepArgs a = insts[inst].args[parity];
-        // FP32 stores device scope, as on a single large lattice (41.4 ->
-        // 42.1 GLUPS on a 256-instance ensemble)
-        tile_body<P, TZ, TR, NT, false, kOpt, sizeof(typename P::S) == 4 ? 16 : 0>(a, tile, 0);
-        __syncthreads();  // the next item reuses the LDS windows
-    }
-}
-
 }  // namespace lbm

@@ -84,9 +84,9 @@ def test_strip_ragged_random_fields_body_force():
     _parity(200, 37, rho, 300, 37, uz=uz, ur=ur, G=-4.0, tau=0.8, wall=1, axisym=0)
 
 
-def test_strip_large_ragged_default_path():
-    """4100 x 515 uses the strip by default (chunks of 48 rows): 3 steps
-    against the oracle on full fields."""
+def test_strip_large_ragged():
+    """A ragged 4100 x 515 lattice through the row-marching kernel (chunks
+    of 48 rows): 3 steps against the oracle on full fields."""
     rho, uz, ur = random_state_fields(4100515, 4100, 515, rho_lo=0.3, rho_hi=2.0, u_amp=0.01)
     _parity(4100, 515, rho, 3, 48, uz=uz, ur=ur, G=-5.0, tau=0.9, wall=1)
 
