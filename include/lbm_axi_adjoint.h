@@ -29,11 +29,15 @@ extern "C" {
 #endif
 
 /* Bytes of FP64 scratch lbm_axi_adjoint_step and lbm_axi_adjoint_run need
- * for an nz x nr grid (two blocks of recomputed forward fields, used by
- * alternate steps of a run, and the adjoint fields); 0 if the size is
- * invalid.  The adjoint needs nz >= 4 and nr >= 6 (its stencils wrap at most
- * two columns) and nz (nr + 12) < 2^31; other sizes give 0 here and
- * LBM_AXI_EINVAL from the calls. */
+ * for an nz x nr grid: four node fields that pass between the two kernels of
+ * a reverse step (the part of the density adjoint that goes through the psi
+ * stencils, F-bar scaled by -G psi in two components, exp(-rho/rho0)) and
+ * two sums per tile for dL/dG and dL/dtau (32 B per node and 32 B per tile
+ * of 32 x 16 nodes, or 16 x 8 on grids with fewer than 512 of the larger
+ * tiles); 0 if the size is invalid.  The adjoint needs nz >= 4 and nr >= 6
+ * (the psi window mirrors up to six rows at the axis and the wall) and
+ * nz (nr + 12) < 2^31; other sizes give 0 here and LBM_AXI_EINVAL from the
+ * calls. */
 size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr);
 
 /* One reverse step.  With f' = step(f; G, tau) (post-streaming states,
@@ -51,7 +55,7 @@ int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const doubl
  * array of LBM_AXI_NOALLOC_SCRATCH_BYTES (24 MiB) that the library holds on
  * every GPU it runs on until the process ends, instead of a workspace
  * argument.  Grids whose lbm_axi_adjoint_workspace_bytes exceed it (beyond
- * about 300 x 150; the 256 x 128 drop needs 16.5 MiB) return
+ * about 780 000 nodes, e.g. 1024 x 768; the 256 x 128 drop needs 1.1 MB) return
  * LBM_AXI_ENOMEM with a message.  The caller passes inputs and outputs as
  * for lbm_axi_adjoint_step.  Allocates nothing (no hipMalloc, hipFree or
  * allocating library call); the first call on a device looks the array's
@@ -69,9 +73,11 @@ int lbm_axi_adjoint_step_noalloc(const lbm_axi_params* p, const double* d_f, con
  * values as k calls of lbm_axi_adjoint_step from the last state back to the
  * first.  d_tmp: scratch of 9 nz nr doubles (not aliasing d_lam).
  * d_grad_acc (may be NULL) accumulates dL/dG, dL/dtau over the k steps:
- * the per-block partial sums run over the steps in the workspace and are
+ * the per-tile partial sums run over the steps in the workspace and are
  * reduced once at the end, so these two values equal those of the single
- * steps up to the order of the additions.  k >= 0 (0 leaves d_lam
+ * steps up to the order of the additions.  Between steps lam stays split
+ * in two parts (in d_tmp or d_lam, and in the workspace), which the next
+ * step's gathers add; the last step adds them.  k >= 0 (0 leaves d_lam
  * unchanged). */
 int lbm_axi_adjoint_run(const lbm_axi_params* p, const double* d_states, int32_t k, double* d_lam, double* d_tmp,
                         double* d_grad_acc, void* d_ws, size_t ws_bytes, void* hip_stream);

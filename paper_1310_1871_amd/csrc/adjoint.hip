@@ -7,20 +7,35 @@
 // kernels below produce lam = (df_next/df)^T lam_next and accumulate
 // dL/dG and dL/dtau.
 //
-// The reverse pass follows the forward data flow backwards:
-//   1. forward intermediates at the current state are recomputed into
-//      FP64 fields (rho, j, psi, d_r psi on the ghost-extended rows, d_rr,
-//      the 1D d_r and d_zr, force, u, u^eq, velocity derivatives);
-//   2. nu = S^T lam_next is gathered (S is a permutation);
-//   3. the collision, equilibrium and source terms are reversed node by
-//      node;
-//   4. every stencil is transposed into a gather: the adjoint of a ghost
-//      (mirrored) value is added back onto the real node it mirrors, with
-//      the same parity sign the forward extension used;
-//   5. psi-bar becomes rho-bar through psi'(rho) = exp(-rho/rho0), and
-//      lam_i = f-bar_i + rho-bar + c_i . j-bar.
-// Every kernel is one thread per node; no atomics, so results are
-// deterministic.
+// The reverse step is two tile kernels.  In the forward data flow, psi
+// feeds the force through the Shan–Chen neighbour sum and the derivative
+// stencils (reach 1, 4 and 2 + 2), the force feeds the velocity, and the
+// velocity feeds the source through its own stencils (reach 2).  Reversed:
+//
+//   A (adj_tile_a), one workgroup per tile, one thread per tile node:
+//     1. loads f on the tile and a 6-node ring and recomputes rho, j, psi,
+//        d_r psi, the 1D d_r psi, the force and the velocity on the tile and
+//        a 2-node ring, as the forward kernel does;
+//     2. gathers nu = S^T lam_next on the tile and the 2-node ring (the
+//        adjoints of the velocity stencils at a node depend only on nu and
+//        rho there), and keeps those adjoints in LDS;
+//     3. reverses collision, equilibrium and source at each tile node, folds
+//        the velocity-stencil adjoints of its neighbours onto it (with the
+//        mirror images at the axis and the wall), then reverses the velocity
+//        and the force;
+//     4. writes lam_p = f-bar + rho-bar + c . j-bar with every term of
+//        rho-bar except the part that passes through the psi stencils of
+//        other nodes, and for kernel B P = -G psi F-bar (two components) and
+//        E = exp(-rho / rho0);
+//   B (adj_tile_b): transposes the psi stencils from P (their adjoints are
+//     P / (18 r) and -P_r / (18 r^2)), folds the ghost rows onto the rows
+//     they mirror, and gives rho-bar_B = psi-bar_B E.
+// lam = lam_p + rho-bar_B in every direction.  A single step adds the two in
+// place (B's last form); a run keeps lam in the split form between steps
+// and the next step's kernel A adds rho-bar_B in its gathers.
+//
+// Each workgroup sums its nodes' dL/dG and dL/dtau terms in a fixed order
+// into its own slot; no atomics, so results are deterministic.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -44,596 +59,706 @@ static __device__ __align__(256) double scratch[LBM_AXI_NOALLOC_SCRATCH_BYTES / 
 
 namespace {
 
-constexpr int NGA = 6;  // ghost rows kept on extended adjoint fields
-// workgroup size of the per-node adjoint kernels: one wave per workgroup: a small lattice still spreads over every CU; the
-// kernels declare it as their launch bound, which lets a thread keep all the
-// loads of a gather in flight in registers
-constexpr int kAdjBlock = 64;
-
-struct AdjArgs {
+struct TileArgs {
     int nz, nr;
-    long long n;    // nz * nr
-    long long ne;   // nz * (nr + 2 NGA)
+    long long n;  // nz * nr
     double G, tau, rho0, gz;
-    int wall, axisym;
-    const double* f;         // [9][n] state f^t
-    const double* lam_next;  // [9][n]
-    double* lam;             // [9][n]
-    double* fw;              // forward fields of the step (recomputed)
-    double* w;               // adjoint fields, f-bar, partial sums
-    int accumulate;          // 1: add the block partials of dL/dG, dL/dtau to running sums
+    int wall;
+    int tiles_z;               // tiles along z (tile id = row of tiles * tiles_z + column)
+    const double* f;           // [9][n] state f^t
+    const double* lam_p;       // [9][n] lam^{t+1}, less rho-bar_B
+    const double* rhob_in;     // [n] rho-bar_B of lam^{t+1}; NULL: lam_p is all of lam^{t+1}
+    double* lam_out;           // [9][n] A: lam_p of lam^t; final B: lam^t (lam_p plus rho-bar_B, in place)
+    double* pz;                // [n] P_z = -G psi F-bar_z
+    double* pr;                // [n] P_r = -G psi F-bar_r
+    double* ex;                // [n] E = exp(-rho / rho0)
+    double* rhob_out;          // [n] B: rho-bar_B of lam^t
+    double* part;              // [tiles][2] dL/dG, dL/dtau of each tile
+    int accumulate;            // 1: add to part (the running sums of a run), 0: overwrite
 };
 
-// field slots (each n doubles): the forward ones (S_RHO .. S_QR) in a
-// forward block, the adjoint ones (S_RHOB ..) in the adjoint block
-enum Slot {
-    S_RHO, S_JZ, S_JR, S_PSI, S_DRR, S_DZR, S_FZ, S_FR, S_SCZ, S_SCR, S_UZ, S_UR, S_QZ, S_QR,
-    // adjoints
-    S_RHOB, S_JZB, S_JRB, S_UZB_H, S_URB_H, S_FZB, S_FRB, S_DRUZB, S_DZURB, S_DRURB,
-    S_PSIB_LOC, S_DZRB, S_DRRB, S_DRB_REAL, S_D1B, S_FSCZB, S_FSCRB, S_GB, S_TAUB,
-    S_NSLOT
+// tile geometry: TZ x TR nodes, one thread per node; window offsets are
+// relative to the tile's first node
+template <int TZ, int TR>
+struct Tile {
+    static constexpr int NT = TZ * TR;
+    static constexpr int PW = TZ + 12, PH = TR + 12;  // psi: columns and rows [-6, T + 6)
+    static constexpr int DW = TZ + 8, DH = TR + 8;    // isotropic d_r psi: [-4, T + 4)
+    static constexpr int EW = TZ + 8, EH = TR + 4;    // 1D d_r psi: columns [-4, TZ + 4), rows [-2, TR + 2)
+    static constexpr int UW = TZ + 4, UH = TR + 4;    // u and the velocity-stencil adjoints: [-2, T + 2)
+    static constexpr int R2N = 4 * (TZ + 4) + 4 * TR;          // ring nodes within 2 of the tile
+    static constexpr int OUTN = 8 * (TZ + 12) + 8 * (TR + 4);  // ring nodes 3 to 6 away
+    static constexpr int RS = (R2N + OUTN + NT - 1) / NT;      // ring slots per thread
+    static_assert(R2N <= NT, "the first ring slot holds every ring node within 2 of the tile");
+    static_assert(NT % 64 == 0, "whole waves");
 };
-// extended slots (ne doubles each), after the plain ones of their block
-// (E_PSI .. E_UR forward, E_DRB adjoint)
-enum SlotE { E_PSI, E_DR, E_UZ, E_UR, E_DRB, E_NSLOT };
-constexpr int kFwdSlots = S_RHOB, kFwdESlots = E_DRB;
-// doubles in one forward block
-__host__ __device__ inline size_t fwd_block(long long n, long long ne) {
-    return (size_t)kFwdSlots * n + (size_t)kFwdESlots * ne;
-}
-// a slot's field inside its block
-__device__ __forceinline__ double* fptr(const AdjArgs& a, int s) {
-    return s < kFwdSlots ? a.fw + (size_t)s * a.n : a.w + (size_t)(s - kFwdSlots) * a.n;
-}
-__device__ __forceinline__ double* eptr(const AdjArgs& a, int s) {
-    return s < kFwdESlots ? a.fw + (size_t)kFwdSlots * a.n + (size_t)s * a.ne
-                          : a.w + (size_t)(S_NSLOT - kFwdSlots) * a.n + (size_t)(s - kFwdESlots) * a.ne;
-}
-// in the adjoint block, after its extended slot: the partial f-bar, a
-// population-sized field
-__host__ __device__ inline size_t fbar_off(long long n, long long ne) {
-    return (size_t)(S_NSLOT - kFwdSlots) * n + (size_t)(E_NSLOT - kFwdESlots) * ne;
-}
-// after f-bar: per-block partial sums of dL/dG and dL/dtau ([block][2])
-__host__ __device__ inline size_t part_off(long long n, long long ne) { return fbar_off(n, ne) + 9 * (size_t)n; }
-// running per-block sums of a multi-step run, after the step partials
-__host__ __device__ inline size_t run_off(long long n, long long ne) {
-    return part_off(n, ne) + 2 * (size_t)((n + kAdjBlock - 1) / kAdjBlock);
-}
 
-// row clamped into [lo, hi] (the masked gathers below load a clamped row and
-// multiply its term by 0 when the row is outside: no branch around the load)
-__device__ __forceinline__ int clampi(int y, int lo, int hi) { return y < lo ? lo : (y > hi ? hi : y); }
-
-// periodic column: the stencils here reach at most 2 columns and the
-// adjoint requires nz >= 4, so one add or subtract wraps
-__device__ __forceinline__ int wrapz(int z, int nz) {
-    z = z < 0 ? z + nz : z;
-    return z >= nz ? z - nz : z;
-}
-__device__ __forceinline__ int mirror_src(int y, int nr, double& sgn, double axis_sign) {
-    sgn = 1.0;
-    if (y < 0) {
-        sgn = axis_sign;
-        return -1 - y;
-    }
-    if (y >= nr) return 2 * nr - 1 - y;
-    return y;
-}
-// extended-field index of row y (-NGA <= y < nr + NGA), column z
-__device__ __forceinline__ long long eidx(int y, int z, int nz) { return (long long)(y + NGA) * nz + z; }
-
-#define NODE_LOOP(a)                                                 \
-    const long long x = gid;                                         \
-    if (x >= (a).n) return;                                          \
-    const int r = (int)x / (a).nz, z = (int)x - r * (a).nz;
-
-// isotropic first derivative at (z, y) of an extended field (Sec. II.D)
-__device__ double d_iso_e(const double* E, int z, int y, int nz, bool along_r) {
-    double s = 0.0;
-#pragma unroll
-    for (int i = 1; i < lbm::kQ; ++i) {
-        const int c = along_r ? lbm::cr(i) : lbm::cz(i);
-        if (c == 0) continue;
-        const double t = 8.0 * E[eidx(y + lbm::cr(i), wrapz(z + lbm::cz(i), nz), nz)] -
-                         E[eidx(y + 2 * lbm::cr(i), wrapz(z + 2 * lbm::cz(i), nz), nz)];
-        s += c * t;
-    }
-    return s / 36.0;
-}
-
-// ------------------------------------------------------------ forward ----
-
-// rho, j, psi on the real rows and psi on the extended rows -6 .. nr+5
-// (a ghost row takes the value of its mirror row: psi is even at the axis
-// and at the wall)
-__device__ __forceinline__ void fwd_moments_at(const AdjArgs& a, const long long gid) {
-    const long long e = gid;
-    if (e >= a.ne) return;
-    const int y = (int)e / a.nz - NGA, z = (int)e - (y + NGA) * a.nz;
-    double sgn;
-    const int ys = mirror_src(y, a.nr, sgn, 1.0);
-    double* w = a.w;
-    const long long n = a.n;
-    const long long x = (long long)ys * a.nz + z;
-    double rho = 0, jz = 0, jr = 0;
-#pragma unroll
-    for (int i = 0; i < lbm::kQ; ++i) {
-        const double fi = a.f[i * n + x];
-        rho += fi;
-        jz += lbm::cz(i) * fi;
-        jr += lbm::cr(i) * fi;
-    }
-    const double psi = a.rho0 * (1.0 - exp(-rho / a.rho0));
-    if (y == ys) {
-        fptr(a, S_RHO)[x] = rho;
-        fptr(a, S_JZ)[x] = jz;
-        fptr(a, S_JR)[x] = jr;
-        fptr(a, S_PSI)[x] = psi;
-    }
-    eptr(a, E_PSI)[e] = psi;
-}
-
-// isotropic d_r psi on extended rows -4 .. nr+3 (zero elsewhere)
-__device__ __forceinline__ void fwd_dr_at(const AdjArgs& a, const long long gid) {
-    const long long e = gid;
-    if (e >= a.ne) return;
-    const int y = (int)e / a.nz - NGA, z = (int)e - (y + NGA) * a.nz;
-    const double* psiE = eptr(a, E_PSI);
-    double v = 0.0;
-    if (y >= -4 && y < a.nr + 4) v = d_iso_e(psiE, z, y, a.nz, true);
-    eptr(a, E_DR)[e] = v;
-}
-
-// forces, hydrodynamic and equilibrium velocities on the real rows, and the
-// velocity on the extended rows (a ghost row recomputes its mirror row's
-// value: u_z even, u_r odd at the axis and even at the wall)
-__device__ __forceinline__ void fwd_force_at(const AdjArgs& a, const long long gid) {
-    const long long e = gid;
-    if (e >= a.ne) return;
-    const int y = (int)e / a.nz - NGA, z = (int)e - (y + NGA) * a.nz;
-    double sgn;
-    const int r = mirror_src(y, a.nr, sgn, -1.0);
-    double* w = a.w;
-    const long long n = a.n;
-    const int nz = a.nz;
-    const long long x = (long long)r * nz + z;
-    const double* psiE = eptr(a, E_PSI);
-    const double* drE = eptr(a, E_DR);
-    // 1D fourth-order d_z of the 1D fourth-order d_r (Sec. II.D)
-    auto d1 = [&](int zz) {
-        zz = wrapz(zz, nz);
-        return (-psiE[eidx(r + 2, zz, nz)] + 8.0 * psiE[eidx(r + 1, zz, nz)] - 8.0 * psiE[eidx(r - 1, zz, nz)] +
-                psiE[eidx(r - 2, zz, nz)]) / 12.0;
-    };
-    const double dzr = (-d1(z + 2) + 8.0 * d1(z + 1) - 8.0 * d1(z - 1) + d1(z - 2)) / 12.0;
-    const double drr = d_iso_e(drE, z, r, nz, true);
-    double sz = 0, sr = 0;
-#pragma unroll
-    for (int i = 1; i < lbm::kQ; ++i) {
-        const double ps = psiE[eidx(r + lbm::cr(i), wrapz(z + lbm::cz(i), nz), nz)];
-        sz += lbm::weight(i) * ps * lbm::cz(i);
-        sr += lbm::weight(i) * ps * lbm::cr(i);
-    }
-    const double psi = fptr(a, S_PSI)[x], rho = fptr(a, S_RHO)[x];
-    double Fz = -a.G * psi * sz, Fr = -a.G * psi * sr;
-    if (a.axisym) {
-        const double rr = r + 0.5;
-        const double dr1 = drE[eidx(r, z, nz)];
-        Fz += -(a.G / 18.0) * psi * dzr / rr;
-        Fr += -(a.G / 18.0) * psi * (drr / rr - dr1 / (rr * rr));
-    }
-    Fz += rho * a.gz;
-    const double jz = fptr(a, S_JZ)[x], jr = fptr(a, S_JR)[x];
-    const double uz = (jz + 0.5 * Fz) / rho, ur = (jr + 0.5 * Fr) / rho;
-    if (y == r) {
-        fptr(a, S_DZR)[x] = dzr;
-        fptr(a, S_DRR)[x] = drr;
-        fptr(a, S_SCZ)[x] = sz;
-        fptr(a, S_SCR)[x] = sr;
-        fptr(a, S_FZ)[x] = Fz;
-        fptr(a, S_FR)[x] = Fr;
-        fptr(a, S_UZ)[x] = uz;
-        fptr(a, S_UR)[x] = ur;
-        fptr(a, S_QZ)[x] = (jz + a.tau * Fz) / rho;
-        fptr(a, S_QR)[x] = (jr + a.tau * Fr) / rho;
-    }
-    eptr(a, E_UZ)[e] = uz;
-    eptr(a, E_UR)[e] = sgn * ur;
-}
-
-// ------------------------------------------------------------ reverse ----
-
-
-// steps 2-3: streaming transpose, BGK / equilibrium / source reversed.
-// kIn: a row with no boundary link (1 <= r <= nr - 2), whose push targets
-// need no boundary rule, so the loop's loads carry no branches.
-// kAxi: the axisymmetric terms (a.axisym), a template flag so that no branch
-// separates the velocity-stencil loads from the others
-template <bool kIn, bool kAxi>
-__device__ __forceinline__ void rev_collision_node(const AdjArgs& a, const long long x, const int r, const int z) {
-    double* w = a.w;
-    const long long n = a.n;
-    const double tau = a.tau, inv_tau = 1.0 / tau;
-    const double rho = fptr(a, S_RHO)[x];
-    const double qz = fptr(a, S_QZ)[x], qr = fptr(a, S_QR)[x];
-    const double uz = fptr(a, S_UZ)[x], ur = fptr(a, S_UR)[x];
-    const double rr = r + 0.5;
-    double* fbar = w + fbar_off(n, a.ne);
-
-    double rhob = 0, qzb = 0, qrb = 0, taub = 0, massb = 0, hzb = 0, hrb = 0;
-    const double qq = 1.5 * (qz * qz + qr * qr);
-    // every load first: the f-bar stores below could alias them for all the
-    // compiler knows, and would otherwise make each load wait in turn
-    double druz = 0, dzur = 0, drur = 0;
-    if (kAxi) {
-        const double* uzE = eptr(a, E_UZ);
-        const double* urE = eptr(a, E_UR);
-        druz = d_iso_e(uzE, z, r, a.nz, true);
-        dzur = d_iso_e(urE, z, r, a.nz, false);
-        drur = d_iso_e(urE, z, r, a.nz, true);
-    }
-    const double Fz = fptr(a, S_FZ)[x], Fr = fptr(a, S_FR)[x];
-    double nus[lbm::kQ], fis[lbm::kQ];
-#pragma unroll
-    for (int i = 0; i < lbm::kQ; ++i) {
-        int tz, tr, d;
-        if (kIn) {
-            tz = wrapz(z + lbm::cz(i), a.nz);
-            tr = r + lbm::cr(i);
-            d = i;
-        } else {
-            // the push target under the boundary rules (Sec. II.E: the
-            // specular axis, the no-slip or free-slip wall), as selects so
-            // that no branch separates the loads
-            const int ty = r + lbm::cr(i);
-            const bool below = ty < 0, above = ty >= a.nr, back = above && a.wall == 0;
-            tz = wrapz(back ? z : z + lbm::cz(i), a.nz);
-            tr = below ? 0 : (above ? (a.wall == 0 ? r : a.nr - 1) : ty);
-            d = below ? lbm::mirror_r(i) : (above ? (a.wall == 0 ? lbm::opposite(i) : lbm::mirror_r(i)) : i);
-        }
-        nus[i] = a.lam_next[d * n + (long long)tr * a.nz + tz];
-        fis[i] = a.f[i * n + x];
-    }
-#pragma unroll
-    for (int i = 0; i < lbm::kQ; ++i) {
-        const double nu = nus[i];
-        const double wi = lbm::weight(i);
-        const double cu = lbm::cz(i) * qz + lbm::cr(i) * qr;
-        const double poly = 3.0 * cu + 4.5 * cu * cu - qq;
-        const double feq = wi * rho * (1.0 + poly);
-        const double fi = fis[i];
-        fbar[i * n + x] = nu * (1.0 - inv_tau);
-        taub += nu * (fi - feq) * inv_tau * inv_tau;
-        const double feqb = nu * inv_tau;
-        rhob += feqb * wi * (1.0 + poly);
-        const double dpoly = wi * rho * feqb * (3.0 + 9.0 * cu);  // d feq / d cu
-        qzb += dpoly * lbm::cz(i) - feqb * wi * rho * 3.0 * qz;
-        qrb += dpoly * lbm::cr(i) - feqb * wi * rho * 3.0 * qr;
-        massb += wi * nu;
-        hzb += 3.0 * wi * lbm::cz(i) * nu;
-        hrb += 3.0 * wi * lbm::cr(i) * nu;
-    }
-    double uzb = 0, urb = 0, druzb = 0, dzurb = 0, drurb = 0;
-    if (kAxi) {
-        const double mu = rho * (tau - 0.5) / 3.0;
-        // mass = -rho u_r / r
-        rhob += -massb * ur / rr;
-        urb += -massb * rho / rr;
-        // H_z = (mu (d_r u_z + d_z u_r) - rho u_r u_z) / r
-        double mub = hzb * (druz + dzur) / rr;
-        druzb += hzb * mu / rr;
-        dzurb += hzb * mu / rr;
-        rhob += -hzb * ur * uz / rr;
-        urb += -hzb * rho * uz / rr;
-        uzb += -hzb * rho * ur / rr;
-        // H_r = (2 mu (d_r u_r - u_r / r) - rho u_r^2) / r
-        mub += hrb * 2.0 * (drur - ur / rr) / rr;
-        drurb += hrb * 2.0 * mu / rr;
-        urb += hrb * (-2.0 * mu / (rr * rr) - 2.0 * rho * ur / rr);
-        rhob += -hrb * ur * ur / rr;
-        // mu = rho (tau - 1/2) / 3
-        rhob += mub * (tau - 0.5) / 3.0;
-        taub += mub * rho / 3.0;
-    }
-    // u^eq = (j + tau F) / rho
-    const double jzb = qzb / rho, jrb = qrb / rho;
-    const double Fzb = tau * qzb / rho, Frb = tau * qrb / rho;
-    taub += (qzb * Fz + qrb * Fr) / rho;
-    rhob += -(qzb * qz + qrb * qr) / rho;
-    fptr(a, S_RHOB)[x] = rhob;
-    fptr(a, S_JZB)[x] = jzb;
-    fptr(a, S_JRB)[x] = jrb;
-    fptr(a, S_FZB)[x] = Fzb;
-    fptr(a, S_FRB)[x] = Frb;
-    fptr(a, S_UZB_H)[x] = uzb;
-    fptr(a, S_URB_H)[x] = urb;
-    fptr(a, S_DRUZB)[x] = druzb;
-    fptr(a, S_DZURB)[x] = dzurb;
-    fptr(a, S_DRURB)[x] = drurb;
-    fptr(a, S_TAUB)[x] = taub;
-}
-__device__ __forceinline__ void rev_collision_at(const AdjArgs& a, const long long gid) {
-    NODE_LOOP(a)
-    const bool in = r >= 1 && r <= a.nr - 2;
-    if (a.axisym) {
-        if (in)
-            rev_collision_node<true, true>(a, x, r, z);
-        else
-            rev_collision_node<false, true>(a, x, r, z);
+// ring node k of the window: first the nodes within 2 of the tile (rows
+// -2, -1, then TR, TR + 1, then columns -2, -1, TZ, TZ + 1 of the tile
+// rows), then the nodes 3 to 6 away
+template <int TZ, int TR>
+__device__ __forceinline__ void ring_pos(int k, int& c, int& y) {
+    constexpr int W2 = TZ + 4, W6 = TZ + 12, R2N = Tile<TZ, TR>::R2N;
+    if (k < 2 * W2) {
+        y = -2 + k / W2;
+        c = -2 + k % W2;
+    } else if (k < 4 * W2) {
+        const int j = k - 2 * W2;
+        y = TR + j / W2;
+        c = -2 + j % W2;
+    } else if (k < R2N) {
+        const int j = k - 4 * W2, q = j & 3;
+        y = j >> 2;
+        c = q < 2 ? q - 2 : TZ + q - 2;
     } else {
-        if (in)
-            rev_collision_node<true, false>(a, x, r, z);
-        else
-            rev_collision_node<false, false>(a, x, r, z);
-    }
-}
-
-// transposed isotropic stencil: sum over taps o of coef(o) * src(e - o),
-// src living on real rows of a plain field.  kAll: every tap row is a real
-// row and the taps are summed as they are; otherwise a tap outside the
-// lattice loads a clamped row and is multiplied by 0.  Either way no branch
-// surrounds a load, so a thread issues them all before waiting on any (a
-// check around each load makes each wait for the previous one).
-template <bool kAll>
-__device__ double iso_transpose_real_t(const double* src, int z, int e, int nz, int nr, bool along_r) {
-    double s = 0.0;
-#pragma unroll
-    for (int i = 1; i < lbm::kQ; ++i) {
-        const int c = along_r ? lbm::cr(i) : lbm::cz(i);
-        if (c == 0) continue;
-        const int y1 = e - lbm::cr(i), y2 = e - 2 * lbm::cr(i);
-        if (kAll) {
-            s += 8.0 * c * src[(long long)y1 * nz + wrapz(z - lbm::cz(i), nz)];
-            s -= c * src[(long long)y2 * nz + wrapz(z - 2 * lbm::cz(i), nz)];
+        const int j = k - R2N;
+        if (j < 4 * W6) {
+            y = -6 + j / W6;
+            c = -6 + j % W6;
+        } else if (j < 8 * W6) {
+            const int i = j - 4 * W6;
+            y = TR + 2 + i / W6;
+            c = -6 + i % W6;
         } else {
-            // masked: a row outside the lattice contributes 0 x (a real value)
-            const double m1 = (y1 >= 0 && y1 < nr) ? 1.0 : 0.0, m2 = (y2 >= 0 && y2 < nr) ? 1.0 : 0.0;
-            s += 8.0 * c * m1 * src[(long long)clampi(y1, 0, nr - 1) * nz + wrapz(z - lbm::cz(i), nz)];
-            s -= c * m2 * src[(long long)clampi(y2, 0, nr - 1) * nz + wrapz(z - 2 * lbm::cz(i), nz)];
+            const int i = j - 8 * W6, q = i & 7;
+            y = -2 + (i >> 3);
+            c = q < 4 ? q - 6 : TZ + 2 + (q - 4);
         }
     }
-    return s / 36.0;
-}
-__device__ double iso_transpose_real(const double* src, int z, int e, int nz, int nr, bool along_r) {
-    return (e >= 2 && e <= nr - 3) ? iso_transpose_real_t<true>(src, z, e, nz, nr, along_r)
-                                   : iso_transpose_real_t<false>(src, z, e, nz, nr, along_r);
 }
 
-// step 4 for the velocities, then u = (j + F/2)/rho and the force reversed
-__device__ __forceinline__ void rev_velocity_force_at(const AdjArgs& a, const long long gid) {
-    NODE_LOOP(a)
-    double* w = a.w;
-    const long long n = a.n;
+// periodic column (any offset)
+__device__ __forceinline__ int wrap_col(int z, int nz) {
+    z %= nz;
+    return z < 0 ? z + nz : z;
+}
+
+// the row whose populations a window row reads: rows below the axis and
+// beyond the wall take their mirror row (psi is even at both); rows further
+// out than one mirror occur only on the last tile of a short lattice, are
+// never read by a tile node, and are clamped into the lattice
+__device__ __forceinline__ int mirror_even(int y, int nr) {
+    if (y < 0) y = -1 - y;
+    if (y >= nr) y = 2 * nr - 1 - y;
+    return y < 0 ? 0 : (y >= nr ? nr - 1 : y);
+}
+
+// tiles in runs of whole tile rows per XCD (workgroup b runs on XCD b mod 8)
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb >> 3, rem = nb & 7, x = b & 7, k = b >> 3;
+    return x * q + (x < rem ? x : rem) + k;
+}
+
+// Buffer-resource loads and stores: 32-bit byte offsets (one VGPR per
+// address instead of a 64-bit pointer pair), the plane of a state or adjoint
+// in the scalar offset.  Every buffer here is below 4 GiB (the adjoint takes
+// at most 2^32 / 72 nodes); the hardware returns 0 for a load past the
+// buffer's end.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ Rsrc rsrc_of(const void* base, size_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)(unsigned)bytes, 0x00020000);
+}
+__device__ __forceinline__ double ld(Rsrc r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void st(Rsrc r, unsigned voff, unsigned soff, double v) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 0);
+}
+
+// the push target of direction i from real node (z, r) under the boundary
+// rules of Sec. II.E (specular axis; no-slip bounce-back or free-slip
+// specular wall): its node index, and in d the direction it arrives in
+__device__ __forceinline__ int push_target(int i, int z, int r, int nz, int nr, int wall, int& d) {
+    const int ty = r + lbm::cr(i);
+    const bool below = ty < 0, above = ty >= nr, back = above && wall == 0;
+    int tz = back ? z : z + lbm::cz(i);
+    tz = tz < 0 ? tz + nz : (tz >= nz ? tz - nz : tz);
+    const int tr = below ? 0 : (above ? (wall == 0 ? r : nr - 1) : ty);
+    d = below ? lbm::mirror_r(i) : (above ? (wall == 0 ? lbm::opposite(i) : lbm::mirror_r(i)) : i);
+    return tr * nz + tz;
+}
+
+// the buffers kernel A reads and writes
+struct Bufs {
+    Rsrc f, lam, rhob, out, pz, pr, ex;
+    unsigned plane;  // bytes of one population plane
+};
+__device__ __forceinline__ Bufs bufs_of(const TileArgs& a) {
+    const size_t nb = (size_t)a.n * sizeof(double);
+    Bufs b;
+    b.f = rsrc_of(a.f, 9 * nb);
+    b.lam = rsrc_of(a.lam_p, 9 * nb);
+    b.rhob = rsrc_of(a.rhob_in, a.rhob_in ? nb : 0);
+    b.out = rsrc_of(a.lam_out, 9 * nb);
+    b.pz = rsrc_of(a.pz, nb);
+    b.pr = rsrc_of(a.pr, nb);
+    b.ex = rsrc_of(a.ex, nb);
+    b.plane = (unsigned)nb;
+    return b;
+}
+
+// nu_i = lam^{t+1}_d at the push target of direction i
+__device__ __forceinline__ double gather_nu(const TileArgs& a, const Bufs& b, int i, int z, int r) {
+    int d;
+    const unsigned x = (unsigned)push_target(i, z, r, a.nz, a.nr, a.wall, d);
+    const double v = ld(b.lam, (unsigned)d * b.plane + 8u * x, 0u);
+    return a.rhob_in ? v + ld(b.rhob, 8u * x, 0u) : v;
+}
+
+// the stencils' divisors as factors (a division by a constant that is not
+// a power of two is a full IEEE division sequence)
+constexpr double kI36 = 1.0 / 36.0, kI12 = 1.0 / 12.0, kI18 = 1.0 / 18.0;
+
+// Kernel A.  kAxi: the axisymmetric terms (source, F^{sym}, velocity
+// stencils) on; off, the plain 2D Shan–Chen step.
+template <int TZ, int TR, bool kAxi>
+__global__ __launch_bounds__(TZ * TR) __attribute__((amdgpu_waves_per_eu(TZ * TR >= 512 ? 4 : 1))) void adj_tile_a(const TileArgs a) {
+    using T = Tile<TZ, TR>;
+    constexpr int NT = T::NT;
+    __shared__ double s_psi[T::PH][T::PW];
+    __shared__ double s_dr[T::DH][T::DW];
+    __shared__ double s_d1[T::EH][T::EW];
+    __shared__ double s_uz[T::UH][T::UW];
+    __shared__ double s_ur[T::UH][T::UW];
+    // adjoints of the velocity stencils: s_hz of d_r u_z and of d_z u_r
+    // (equal), s_hr of d_r u_r
+    __shared__ double s_hz[T::UH][T::UW];
+    __shared__ double s_hr[T::UH][T::UW];
+    __shared__ double s_red[2][NT / 64];
+
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int z0 = (tile % a.tiles_z) * TZ, r0 = (tile / a.tiles_z) * TR;
     const int nz = a.nz, nr = a.nr;
-    double uzb = fptr(a, S_UZB_H)[x], urb = fptr(a, S_URB_H)[x];
-    // the node's own fields, loaded together with the gathers below
-    const double rho = fptr(a, S_RHO)[x];
-    const double uz = fptr(a, S_UZ)[x], ur = fptr(a, S_UR)[x];
-    const double jzb0 = fptr(a, S_JZB)[x], jrb0 = fptr(a, S_JRB)[x];
-    const double Fzb0 = fptr(a, S_FZB)[x], Frb0 = fptr(a, S_FRB)[x];
-    const double rhob0 = fptr(a, S_RHOB)[x];
-    const double psi = fptr(a, S_PSI)[x];
-    const double sz = fptr(a, S_SCZ)[x], sr = fptr(a, S_SCR)[x];
-    const double dzr = fptr(a, S_DZR)[x], drr = fptr(a, S_DRR)[x];
-    const double dr1 = eptr(a, E_DR)[eidx(r, z, nz)];
-    if (a.axisym) {
-        // images of row r in the extended velocity fields (reach 2)
-        const double* druzb = fptr(a, S_DRUZB);
-        const double* dzurb = fptr(a, S_DZURB);
-        const double* drurb = fptr(a, S_DRURB);
-        // one interior test for the three gathers of an image row, so that
-        // their loads go out together
-        auto gather = [&](int e, double sgn_r) {
-            if (e >= 2 && e <= nr - 3) {
-                uzb += iso_transpose_real_t<true>(druzb, z, e, nz, nr, true);
-                urb += sgn_r * (iso_transpose_real_t<true>(dzurb, z, e, nz, nr, false) +
-                                iso_transpose_real_t<true>(drurb, z, e, nz, nr, true));
-            } else {
-                uzb += iso_transpose_real_t<false>(druzb, z, e, nz, nr, true);
-                urb += sgn_r * (iso_transpose_real_t<false>(dzurb, z, e, nz, nr, false) +
-                                iso_transpose_real_t<false>(drurb, z, e, nz, nr, true));
+    const size_t n = (size_t)a.n;
+    const int t = threadIdx.x, tc = t % TZ, ty = t / TZ;
+    const double G = a.G, tau = a.tau, rho0 = a.rho0;
+    const double mu_f = (tau - 0.5) / 3.0, inv_rho0 = 1.0 / rho0;
+    const Bufs bf = bufs_of(a);
+
+    // ---- 1. loads: psi on the window; nu, and the velocity-stencil
+    // adjoints, within 2 of the tile
+    auto psi_of = [&](double rho) { return rho0 * (1.0 - exp(-rho * inv_rho0)); };
+    auto store_h = [&](int c, int y, bool real, double rho, double hz, double hr) {
+        if (kAxi) {
+            const double mu_r = rho * mu_f / (r0 + y + 0.5);
+            s_hz[y + 2][c + 2] = real ? hz * mu_r : 0.0;
+            s_hr[y + 2][c + 2] = real ? 2.0 * hr * mu_r : 0.0;
+        }
+    };
+    const int zt = wrap_col(z0 + tc, nz), rt = r0 + ty;
+    const bool real_t = rt < nr;
+    const bool active = real_t && z0 + tc < nz;
+    double nu[lbm::kQ];
+    double rho_t = 0, jz_t = 0, jr_t = 0;
+    const unsigned xt = 8u * (unsigned)(mirror_even(rt, nr) * nz + zt);
+    {
+        double fl[lbm::kQ];
+#pragma unroll
+        for (int i = 0; i < lbm::kQ; ++i) fl[i] = ld(bf.f, xt, i * bf.plane);
+        // a ghost row (last tile of a short lattice) gathers at the last
+        // row and discards the values: no branch around the loads
+        const int rg = real_t ? rt : nr - 1;
+#pragma unroll
+        for (int i = 0; i < lbm::kQ; ++i) {
+            const double v = gather_nu(a, bf, i, zt, rg);
+            nu[i] = real_t ? v : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < lbm::kQ; ++i) {
+            rho_t += fl[i];
+            jz_t += lbm::cz(i) * fl[i];
+            jr_t += lbm::cr(i) * fl[i];
+        }
+        s_psi[ty + 6][tc + 6] = psi_of(rho_t);
+        double hz = 0, hr = 0;
+#pragma unroll
+        for (int i = 0; i < lbm::kQ; ++i) {
+            hz += 3.0 * lbm::weight(i) * lbm::cz(i) * nu[i];
+            hr += 3.0 * lbm::weight(i) * lbm::cr(i) * nu[i];
+        }
+        store_h(tc, ty, real_t, rho_t, hz, hr);
+    }
+    // ring nodes; the first slot's node, when within 2 of the tile, keeps
+    // rho and j for its velocity
+    double rho_q = 0, jz_q = 0, jr_q = 0;
+    int cq = 0, yq = 0;
+    const bool ring2 = t < T::R2N;
+#pragma unroll
+    for (int s = 0; s < T::RS; ++s) {
+        const int k = t + s * NT;
+        // every slot loads (a slot past the ring reads some lattice node and
+        // stores nothing): no branch around the loads
+        int c, y;
+        ring_pos<TZ, TR>(k, c, y);
+        const int z = wrap_col(z0 + c, nz), yy = r0 + y;
+        const unsigned x = 8u * (unsigned)(mirror_even(yy, nr) * nz + z);
+        double fr[lbm::kQ];
+#pragma unroll
+        for (int i = 0; i < lbm::kQ; ++i) fr[i] = ld(bf.f, x, i * bf.plane);
+        if (k < T::R2N + T::OUTN) {
+            double rho = 0, jz = 0, jr = 0;
+#pragma unroll
+            for (int i = 0; i < lbm::kQ; ++i) {
+                rho += fr[i];
+                jz += lbm::cz(i) * fr[i];
+                jr += lbm::cr(i) * fr[i];
             }
-        };
-        gather(r, 1.0);
-        if (r <= 1) gather(-1 - r, -1.0);          // axis image: u_r odd
-        if (r >= nr - 2) gather(2 * nr - 1 - r, 1.0);  // wall image
-    }
-    double jzb = jzb0 + uzb / rho;
-    double jrb = jrb0 + urb / rho;
-    double Fzb = Fzb0 + 0.5 * uzb / rho;
-    double Frb = Frb0 + 0.5 * urb / rho;
-    double rhob = rhob0 - (uzb * uz + urb * ur) / rho;
-    // F = F^SC + F^sym + rho g z^
-    rhob += Fzb * a.gz;
-    double Gb = -psi * (Fzb * sz + Frb * sr);
-    double psib = -a.G * (Fzb * sz + Frb * sr);
-    double dzrb = 0, drrb = 0, dr1b = 0;
-    if (a.axisym) {
-        const double rr = r + 0.5;
-        const double g18 = a.G / 18.0;
-        // F^sym_z = -(G/18) psi d_zr / r
-        Gb += Fzb * (-psi * dzr / (18.0 * rr));
-        psib += Fzb * (-g18 * dzr / rr);
-        dzrb = Fzb * (-g18 * psi / rr);
-        // F^sym_r = -(G/18) psi (d_rr / r - d_r / r^2)
-        const double br = drr / rr - dr1 / (rr * rr);
-        Gb += Frb * (-psi * br / 18.0);
-        psib += Frb * (-g18 * br);
-        drrb = Frb * (-g18 * psi / rr);
-        dr1b = Frb * (g18 * psi / (rr * rr));
-    }
-    fptr(a, S_JZB)[x] = jzb;
-    fptr(a, S_JRB)[x] = jrb;
-    fptr(a, S_RHOB)[x] = rhob;
-    fptr(a, S_FSCZB)[x] = Fzb;  // adjoint of F^SC equals that of F
-    fptr(a, S_FSCRB)[x] = Frb;
-    fptr(a, S_PSIB_LOC)[x] = psib;
-    fptr(a, S_DZRB)[x] = dzrb;
-    fptr(a, S_DRRB)[x] = drrb;
-    fptr(a, S_DRB_REAL)[x] = dr1b;
-    fptr(a, S_GB)[x] = Gb;
-}
-
-// Two independent transposed stencils in one pass (both read only what
-// rev_velocity_force wrote):
-// - adjoint of d_r psi on extended rows -2 .. nr+1 (the rows d_rr reads):
-//   transposed d_rr plus the direct use of d_r on real rows;
-// - on real rows, d_zr = 1D d_z of the 1D d_r: transpose of the outer z
-//   difference.
-__device__ __forceinline__ void rev_dr_at(const AdjArgs& a, const long long gid) {
-    const long long e = gid;
-    if (e >= a.ne) return;
-    const int y = (int)e / a.nz - NGA, z = (int)e - (y + NGA) * a.nz;
-    const int nz = a.nz;
-    double v = 0.0;
-    if (y >= -2 && y < a.nr + 2) {
-        v = iso_transpose_real(fptr(a, S_DRRB), z, y, nz, a.nr, true);
-        if (y >= 0 && y < a.nr) v += fptr(a, S_DRB_REAL)[(long long)y * nz + z];
-    }
-    eptr(a, E_DRB)[e] = v;
-    if (y >= 0 && y < a.nr) {
-        const double* b = fptr(a, S_DZRB) + (long long)y * nz;
-        // forward: out(z) = (-in(z+2) + 8 in(z+1) - 8 in(z-1) + in(z-2)) / 12
-        fptr(a, S_D1B)[(long long)y * nz + z] =
-            (-b[wrapz(z - 2, nz)] + 8.0 * b[wrapz(z - 1, nz)] - 8.0 * b[wrapz(z + 1, nz)] + b[wrapz(z + 2, nz)]) /
-            12.0;
-    }
-}
-
-__device__ __forceinline__ long long global_id() { return (long long)blockIdx.x * blockDim.x + threadIdx.x; }
-
-__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void fwd_moments(AdjArgs a) { fwd_moments_at(a, global_id()); }
-__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void fwd_dr(AdjArgs a) { fwd_dr_at(a, global_id()); }
-__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void fwd_force(AdjArgs a) { fwd_force_at(a, global_id()); }
-__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void rev_collision(AdjArgs a) { rev_collision_at(a, global_id()); }
-__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void rev_velocity_force(AdjArgs a) { rev_velocity_force_at(a, global_id()); }
-__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void rev_dr(AdjArgs a) { rev_dr_at(a, global_id()); }
-
-// In a run, the reverse kernels of step t share their launches with the
-// recomputation of step t - 1, whose fields go to the other forward block:
-// the two parts of a launch touch no common field.  (Giving the two parts
-// separate workgroups of one launch, or issuing the recomputation's loads
-// ahead of the reverse part, was no faster.)
-__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void rev_collision_fwd_moments(AdjArgs ar, AdjArgs af, int fwd) {
-    const long long g = global_id();
-    rev_collision_at(ar, g);
-    if (fwd) fwd_moments_at(af, g);
-}
-__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void rev_velocity_force_fwd_dr(AdjArgs ar, AdjArgs af, int fwd) {
-    const long long g = global_id();
-    rev_velocity_force_at(ar, g);
-    if (fwd) fwd_dr_at(af, g);
-}
-__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void rev_dr_fwd_force(AdjArgs ar, AdjArgs af, int fwd) {
-    const long long g = global_id();
-    rev_dr_at(ar, g);
-    if (fwd) fwd_force_at(af, g);
-}
-
-// adjoint of extended psi at extended row e, column z (before folding);
-// kAll: 2 <= e <= nr - 3, every tap of the three gathers lies inside
-template <bool kAll>
-__device__ double psi_ext_adjoint_t(const AdjArgs& a, int z, int e) {
-    const double* w = a.w;
-    const long long n = a.n;
-    const int nz = a.nz, nr = a.nr;
-    double s = 0.0;
-    // d_r psi = iso_r(psi_ext) on rows -4..nr+3; only rows -2..nr+1 carry adjoint
-    const double* drb = eptr(a, E_DRB);
+            s_psi[y + 6][c + 6] = psi_of(rho);
+            if (s == 0 && ring2) {
+                rho_q = rho;
+                jz_q = jz;
+                jr_q = jr;
+                cq = c;
+                yq = y;
+                if (kAxi) {
+                    // ghost rows gather at a clamped row and store 0
+                    const bool real = yy >= 0 && yy < nr;
+                    const int yg = yy < 0 ? 0 : (yy >= nr ? nr - 1 : yy);
+                    double hz = 0, hr = 0;
 #pragma unroll
-    for (int i = 1; i < lbm::kQ; ++i) {
-        const int c = lbm::cr(i);
-        if (c == 0) continue;
-        // every tap row lies inside the extended field (|e| reaches at most 4
-        // beyond the lattice, the field 6), whose rows outside -2 .. nr+1
-        // hold zeros: no test is needed
-        const int y1 = e - lbm::cr(i), y2 = e - 2 * lbm::cr(i);
-        s += (8.0 * c / 36.0) * drb[eidx(y1, wrapz(z - lbm::cz(i), nz), nz)];
-        s -= (c / 36.0) * drb[eidx(y2, wrapz(z - 2 * lbm::cz(i), nz), nz)];
-    }
-    // 1D d_r psi on real rows: (-p(y+2) + 8 p(y+1) - 8 p(y-1) + p(y-2)) / 12
-    const double* d1b = fptr(a, S_D1B);
-    const int ys[4] = {e - 2, e - 1, e + 1, e + 2};
-    const double cf[4] = {-1.0, 8.0, -8.0, 1.0};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (kAll) {
-            s += (cf[k] / 12.0) * d1b[(long long)ys[k] * nz + z];
-        } else {
-            const double m = (ys[k] >= 0 && ys[k] < nr) ? 1.0 : 0.0;
-            s += (cf[k] / 12.0) * m * d1b[(long long)clampi(ys[k], 0, nr - 1) * nz + z];
+                    for (int i = 1; i < lbm::kQ; ++i) {
+                        const double v = gather_nu(a, bf, i, z, yg);
+                        hz += 3.0 * lbm::weight(i) * lbm::cz(i) * v;
+                        hr += 3.0 * lbm::weight(i) * lbm::cr(i) * v;
+                    }
+                    store_h(c, y, real, rho, hz, hr);
+                }
+            }
         }
     }
-    // Shan–Chen force: F^SC(x) = -G psi(x) sum_i W_i psi(x + c_i) c_i
-    const double* fzb = fptr(a, S_FSCZB);
-    const double* frb = fptr(a, S_FSCRB);
-    const double* psi = fptr(a, S_PSI);
-#pragma unroll
-    for (int i = 1; i < lbm::kQ; ++i) {
-        const int ysrc = e - lbm::cr(i);
-        const double m = (kAll || (ysrc >= 0 && ysrc < nr)) ? 1.0 : 0.0;
-        const long long xs = (long long)(kAll ? ysrc : clampi(ysrc, 0, nr - 1)) * nz + wrapz(z - lbm::cz(i), nz);
-        s += -a.G * psi[xs] * lbm::weight(i) * m * (fzb[xs] * lbm::cz(i) + frb[xs] * lbm::cr(i));
-    }
-    return s;
-}
-__device__ double psi_ext_adjoint(const AdjArgs& a, int z, int e) {
-    return (e >= 2 && e <= a.nr - 3) ? psi_ext_adjoint_t<true>(a, z, e) : psi_ext_adjoint_t<false>(a, z, e);
-}
+    __syncthreads();
 
-// step 4 for psi (fold every image of the row), step 5, write lam
-// Last reverse kernel: lam = f-bar + rho-bar + c . j-bar, and the block's
-// partial sums of the node contributions to dL/dG and dL/dtau (a fixed
-// tree order, so the result does not depend on scheduling).
-__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void rev_psi_final(AdjArgs a) {
-    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    double* w = a.w;
-    const long long n = a.n;
-    double g = 0.0, q = 0.0;
-    if (x < n) {
-        const int nr = a.nr;
-        const int r = (int)x / a.nz, z = (int)x - r * a.nz;
-        // the node's own fields first, so that no load waits behind the
-        // stores of lam (which could alias them for all the compiler knows)
-        const double psib_loc = fptr(a, S_PSIB_LOC)[x];
-        const double rho = fptr(a, S_RHO)[x], rhob_loc = fptr(a, S_RHOB)[x];
-        const double jzb = fptr(a, S_JZB)[x], jrb = fptr(a, S_JRB)[x];
-        const double* fbar = w + fbar_off(n, a.ne);
-        double fb[lbm::kQ];
+    // ---- 2. d_r psi (isotropic, on the extended rows as they come) and the
+    // 1D fourth-order d_r psi that d_zr differences along z (Sec. II.D)
+    auto P = [&](int c, int y) { return s_psi[y + 6][c + 6]; };
+    if (kAxi) {
+        for (int k = t; k < T::DH * T::DW; k += NT) {
+            const int y = k / T::DW - 4, c = k % T::DW - 4;
+            double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < lbm::kQ; ++i) fb[i] = fbar[i * n + x];
-        g = fptr(a, S_GB)[x];
-        q = fptr(a, S_TAUB)[x];
-        double psib = psib_loc + psi_ext_adjoint(a, z, r);
-        if (r <= 3) psib += psi_ext_adjoint(a, z, -1 - r);            // axis images (rows -4..-1)
-        if (r >= nr - 4) psib += psi_ext_adjoint(a, z, 2 * nr - 1 - r);  // wall images (rows nr..nr+3)
-        const double rhob = rhob_loc + psib * exp(-rho / a.rho0);
-#pragma unroll
-        for (int i = 0; i < lbm::kQ; ++i) a.lam[i * n + x] = fb[i] + rhob + lbm::cz(i) * jzb + lbm::cr(i) * jrb;
+            for (int i = 1; i < lbm::kQ; ++i) {
+                const int cr = lbm::cr(i), cz = lbm::cz(i);
+                if (cr == 0) continue;
+                s += cr * (8.0 * P(c + cz, y + cr) - P(c + 2 * cz, y + 2 * cr));
+            }
+            s_dr[y + 4][c + 4] = s * kI36;
+        }
+        for (int k = t; k < T::EH * T::EW; k += NT) {
+            const int y = k / T::EW - 2, c = k % T::EW - 4;
+            s_d1[y + 2][c + 4] = (-P(c, y + 2) + 8.0 * P(c, y + 1) - 8.0 * P(c, y - 1) + P(c, y - 2)) * kI12;
+        }
+        __syncthreads();
     }
-    // the workgroup is one wave: a tree of lane shuffles, lane 0 adding
-    // lane k's value for k = 32, 16, ..., 1 (a fixed order)
-    static_assert(kAdjBlock == 64, "one wave per workgroup");
-    const int t = threadIdx.x;
+
+    // ---- 3. force and velocity (Eqs. scforce, uhydro) at window node
+    // (c, y), a real node; ghost rows of the velocity window take their
+    // mirror node's velocity, u_r odd at the axis
+    struct Fwd {
+        double psi, sz, sr, dzr, drr, dr1, Fz, Fr, uz, ur;
+    };
+    auto forward_at = [&](int c, int y, double rho, double jz, double jr) {
+        Fwd o;
+        o.psi = P(c, y);
+        double sz = 0, sr = 0;
 #pragma unroll
-    for (int k = kAdjBlock / 2; k > 0; k >>= 1) {
-        g += __shfl_down(g, k, 64);
-        q += __shfl_down(q, k, 64);
+        for (int i = 1; i < lbm::kQ; ++i) {
+            const double ps = P(c + lbm::cz(i), y + lbm::cr(i));
+            sz += lbm::weight(i) * ps * lbm::cz(i);
+            sr += lbm::weight(i) * ps * lbm::cr(i);
+        }
+        o.sz = sz;
+        o.sr = sr;
+        double Fz = -G * o.psi * sz, Fr = -G * o.psi * sr;
+        o.dzr = o.drr = o.dr1 = 0.0;
+        if (kAxi) {
+            auto D1 = [&](int cc) { return s_d1[y + 2][cc + 4]; };
+            o.dzr = (-D1(c + 2) + 8.0 * D1(c + 1) - 8.0 * D1(c - 1) + D1(c - 2)) * kI12;
+            double s = 0.0;
+#pragma unroll
+            for (int i = 1; i < lbm::kQ; ++i) {
+                const int cr = lbm::cr(i), cz = lbm::cz(i);
+                if (cr == 0) continue;
+                s += cr * (8.0 * s_dr[y + cr + 4][c + cz + 4] - s_dr[y + 2 * cr + 4][c + 2 * cz + 4]);
+            }
+            o.drr = s * kI36;
+            o.dr1 = s_dr[y + 4][c + 4];
+            const double ir = 1.0 / (r0 + y + 0.5);
+            Fz += -(G * kI18) * o.psi * o.dzr * ir;
+            Fr += -(G * kI18) * o.psi * (o.drr - o.dr1 * ir) * ir;
+        }
+        Fz += rho * a.gz;
+        o.Fz = Fz;
+        o.Fr = Fr;
+        const double irho = 1.0 / rho;
+        o.uz = (jz + 0.5 * Fz) * irho;
+        o.ur = (jr + 0.5 * Fr) * irho;
+        return o;
+    };
+    // velocity of window node (c, y) of the velocity window into LDS: a real
+    // row computes its own; rows -2, -1 and nr, nr + 1 compute their mirror
+    // node's (whose populations the load read); rows further out are never
+    // read by a tile node
+    auto velocity_into_lds = [&](int c, int y, double rho, double jz, double jr) {
+        const int yy = r0 + y;
+        double uz = 0.0, ur = 0.0;
+        if (yy >= 0 && yy < nr) {
+            const Fwd o = forward_at(c, y, rho, jz, jr);
+            uz = o.uz;
+            ur = o.ur;
+        } else if (yy >= -2 && yy < nr + 2) {
+            const int ym = (yy < 0 ? -1 - yy : 2 * nr - 1 - yy) - r0;
+            const Fwd o = forward_at(c, ym, rho, jz, jr);
+            uz = o.uz;
+            ur = yy < 0 ? -o.ur : o.ur;
+        }
+        s_uz[y + 2][c + 2] = uz;
+        s_ur[y + 2][c + 2] = ur;
+    };
+    Fwd fw{};
+    if (real_t) fw = forward_at(tc, ty, rho_t, jz_t, jr_t);
+    if (kAxi) {
+        if (real_t) {
+            s_uz[ty + 2][tc + 2] = fw.uz;
+            s_ur[ty + 2][tc + 2] = fw.ur;
+        } else {
+            velocity_into_lds(tc, ty, rho_t, jz_t, jr_t);
+        }
+        if (ring2) velocity_into_lds(cq, yq, rho_q, jz_q, jr_q);
+        __syncthreads();
     }
+
+    // ---- 4. the tile node: collision, equilibrium and source reversed,
+    // the velocity-stencil adjoints of the neighbours folded in, velocity
+    // and force reversed
+    double g_node = 0.0, t_node = 0.0;
+    if (active) {
+        const int r = rt;
+        const double rho = rho_t, rr = r + 0.5, ir = 1.0 / rr, irho = 1.0 / rho;
+        const double inv_tau = 1.0 / tau;
+        const double uz = fw.uz, ur = fw.ur, Fz = fw.Fz, Fr = fw.Fr;
+        const double qz = (jz_t + tau * Fz) * irho, qr = (jr_t + tau * Fr) * irho;
+        // the transposed velocity stencils first (LDS reads only), then the
+        // velocity derivatives, each finished before the next part starts so
+        // that their LDS reads are not all in flight at once
+        double tz_b = 0.0, tr_b = 0.0;
+        if (kAxi) {
+            // transposed velocity stencils: the adjoints at the nodes whose
+            // stencils read this node's velocity, at its own row and at its
+            // ghost images (row -1 - r at the axis, u_r odd; row 2 nr - 1 - r
+            // at the wall), rows outside the lattice holding none
+            auto H = [&](const double (*s)[T::UW], int y, int dc) {
+                const int yy = r0 + y;
+                const double m = (yy >= 0 && yy < nr) ? 1.0 : 0.0;
+                const int yl = y < -2 ? -2 : (y > TR + 1 ? TR + 1 : y);
+                return m * s[yl + 2][tc + dc + 2];
+            };
+            auto gather = [&](int e, double sgn_r) {
+                const int y = e - r0;
+                double gz = 0, gzr = 0, grr = 0;
+#pragma unroll
+                for (int i = 1; i < lbm::kQ; ++i) {
+                    const int cz = lbm::cz(i), cr = lbm::cr(i);
+                    if (cr != 0) {
+                        gz += 8.0 * cr * H(s_hz, y - cr, -cz);
+                        gz -= cr * H(s_hz, y - 2 * cr, -2 * cz);
+                        grr += 8.0 * cr * H(s_hr, y - cr, -cz);
+                        grr -= cr * H(s_hr, y - 2 * cr, -2 * cz);
+                    }
+                    if (cz != 0) {
+                        gzr += 8.0 * cz * H(s_hz, y - cr, -cz);
+                        gzr -= cz * H(s_hz, y - 2 * cr, -2 * cz);
+                    }
+                }
+                tz_b += gz * kI36;
+                tr_b += sgn_r * (gzr + grr) * kI36;
+            };
+            gather(r, 1.0);
+            if (r <= 1) gather(-1 - r, -1.0);
+            if (r >= nr - 2) gather(2 * nr - 1 - r, 1.0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        double druz = 0, dzur = 0, drur = 0;
+        if (kAxi) {
+            auto U = [&](const double (*s)[T::UW], int dc, int dy) { return s[ty + dy + 2][tc + dc + 2]; };
+            double a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+            for (int i = 1; i < lbm::kQ; ++i) {
+                const int cz = lbm::cz(i), cr = lbm::cr(i);
+                if (cr != 0) {
+                    a1 += cr * (8.0 * U(s_uz, cz, cr) - U(s_uz, 2 * cz, 2 * cr));
+                    a3 += cr * (8.0 * U(s_ur, cz, cr) - U(s_ur, 2 * cz, 2 * cr));
+                }
+                if (cz != 0) a2 += cz * (8.0 * U(s_ur, cz, cr) - U(s_ur, 2 * cz, 2 * cr));
+            }
+            druz = a1 * kI36;
+            dzur = a2 * kI36;
+            drur = a3 * kI36;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // the node's populations again (from L2: this workgroup loaded them
+        // in step 1), rather than held in registers across three barriers
+        double fl[lbm::kQ];
+#pragma unroll
+        for (int i = 0; i < lbm::kQ; ++i) fl[i] = ld(bf.f, xt, i * bf.plane);
+        double rhob = 0, qzb = 0, qrb = 0, taub = 0, massb = 0, hzb = 0, hrb = 0;
+        const double qq = 1.5 * (qz * qz + qr * qr);
+#pragma unroll
+        for (int i = 0; i < lbm::kQ; ++i) {
+            const double v = nu[i];
+            const double wi = lbm::weight(i);
+            const double cu = lbm::cz(i) * qz + lbm::cr(i) * qr;
+            const double poly = 3.0 * cu + 4.5 * cu * cu - qq;
+            const double feq = wi * rho * (1.0 + poly);
+            taub += v * (fl[i] - feq) * inv_tau * inv_tau;
+            const double feqb = v * inv_tau;
+            rhob += feqb * wi * (1.0 + poly);
+            const double dpoly = wi * rho * feqb * (3.0 + 9.0 * cu);  // d feq / d cu
+            qzb += dpoly * lbm::cz(i) - feqb * wi * rho * 3.0 * qz;
+            qrb += dpoly * lbm::cr(i) - feqb * wi * rho * 3.0 * qr;
+            massb += wi * v;
+            hzb += 3.0 * wi * lbm::cz(i) * v;
+            hrb += 3.0 * wi * lbm::cr(i) * v;
+        }
+        double uzb = 0, urb = 0;
+        if (kAxi) {
+            const double mu = rho * (tau - 0.5) / 3.0;
+            // mass = -rho u_r / r
+            rhob += -massb * ur * ir;
+            urb += -massb * rho * ir;
+            // H_z = (mu (d_r u_z + d_z u_r) - rho u_r u_z) / r
+            double mub = hzb * (druz + dzur) * ir;
+            rhob += -hzb * ur * uz * ir;
+            urb += -hzb * rho * uz * ir;
+            uzb += -hzb * rho * ur * ir;
+            // H_r = (2 mu (d_r u_r - u_r / r) - rho u_r^2) / r
+            mub += hrb * 2.0 * (drur - ur * ir) * ir;
+            urb += hrb * (-2.0 * mu * ir * ir - 2.0 * rho * ur * ir);
+            rhob += -hrb * ur * ur * ir;
+            // mu = rho (tau - 1/2) / 3
+            rhob += mub * (tau - 0.5) / 3.0;
+            taub += mub * rho / 3.0;
+        }
+        // u^eq = (j + tau F) / rho
+        double jzb = qzb * irho, jrb = qrb * irho;
+        double Fzb = tau * qzb * irho, Frb = tau * qrb * irho;
+        taub += (qzb * Fz + qrb * Fr) * irho;
+        rhob += -(qzb * qz + qrb * qr) * irho;
+        if (kAxi) {
+            uzb += tz_b;
+            urb += tr_b;
+        }
+        // u = (j + F/2) / rho
+        jzb += uzb * irho;
+        jrb += urb * irho;
+        Fzb += 0.5 * uzb * irho;
+        Frb += 0.5 * urb * irho;
+        rhob += -(uzb * uz + urb * ur) * irho;
+        // F = F^SC + F^sym + rho g z^
+        rhob += Fzb * a.gz;
+        double Gb = -fw.psi * (Fzb * fw.sz + Frb * fw.sr);
+        double psib = -G * (Fzb * fw.sz + Frb * fw.sr);
+        if (kAxi) {
+            const double g18 = G * kI18;
+            // F^sym_z = -(G/18) psi d_zr / r
+            Gb += Fzb * (-fw.psi * fw.dzr * kI18 * ir);
+            psib += Fzb * (-g18 * fw.dzr * ir);
+            // F^sym_r = -(G/18) psi (d_rr / r - d_r / r^2)
+            const double br = (fw.drr - fw.dr1 * ir) * ir;
+            Gb += Frb * (-fw.psi * br * kI18);
+            psib += Frb * (-g18 * br);
+        }
+        // psi = rho0 (1 - exp(-rho / rho0)): the node's own psi-bar
+        const double e = exp(-rho * inv_rho0);
+        rhob += psib * e;
+        const unsigned x = 8u * (unsigned)(rt * nz + zt);
+#pragma unroll
+        for (int i = 0; i < lbm::kQ; ++i)
+            st(bf.out, x, i * bf.plane, nu[i] * (1.0 - inv_tau) + rhob + lbm::cz(i) * jzb + lbm::cr(i) * jrb);
+        st(bf.pz, x, 0u, -G * fw.psi * Fzb);
+        st(bf.pr, x, 0u, -G * fw.psi * Frb);
+        st(bf.ex, x, 0u, e);
+        g_node = Gb;
+        t_node = taub;
+    }
+    // the tile's dL/dG and dL/dtau: a tree of lane shuffles per wave, then
+    // the waves in order (a fixed order)
+#pragma unroll
+    for (int k = 32; k > 0; k >>= 1) {
+        g_node += __shfl_down(g_node, k, 64);
+        t_node += __shfl_down(t_node, k, 64);
+    }
+    if ((t & 63) == 0) {
+        s_red[0][t >> 6] = g_node;
+        s_red[1][t >> 6] = t_node;
+    }
+    __syncthreads();
     if (t == 0) {
-        // one step: this step's partials; a run: the block's running sums
-        // over its steps, in step order
-        const size_t o = (a.accumulate ? run_off(n, a.ne) : part_off(n, a.ne)) + 2 * (size_t)blockIdx.x;
+        double g = 0.0, q = 0.0;
+        for (int w = 0; w < NT / 64; ++w) {
+            g += s_red[0][w];
+            q += s_red[1][w];
+        }
+        double* o = a.part + 2 * (size_t)tile;
         if (a.accumulate) {
-            w[o] += g;
-            w[o + 1] += q;
+            o[0] += g;
+            o[1] += q;
         } else {
-            w[o] = g;
-            w[o + 1] = q;
+            o[0] = g;
+            o[1] = q;
         }
     }
 }
+
+// x y rounded on its own, never contracted into an addition that uses it
+__device__ __forceinline__ double mul_rounded(double x, double y) {
+#pragma clang fp contract(off)
+    return x * y;
+}
+
+// Kernel B: psi-bar from the psi stencils of the other nodes, through P.
+// kFinal: add rho-bar_B to lam_out in every direction (lam_out then holds
+// lam^t); otherwise write rho-bar_B.
+template <int TZ, int TR, bool kAxi, bool kFinal>
+__global__ __launch_bounds__(TZ * TR) void adj_tile_b(const TileArgs a) {
+    constexpr int NT = TZ * TR;
+    constexpr int QW = TZ + 8, QH = TR + 16;  // P: columns [-4, TZ + 4), rows [-8, TR + 8)
+    constexpr int GW = TZ + 4, GH = TR + 12;  // adjoint of d_r psi: columns [-2, TZ + 2), rows [-6, TR + 6)
+    constexpr int HH = TR + 12;               // adjoint of the 1D d_r psi: the tile's columns, rows [-6, TR + 6)
+    __shared__ double s_pz[QH][QW], s_pr[QH][QW];
+    // d_rr-bar = P_r / (18 r) on the same window (0 off the lattice)
+    __shared__ double s_qr[kAxi ? QH : 1][kAxi ? QW : 1];
+    __shared__ double s_g[kAxi ? GH : 1][kAxi ? GW : 1];
+    __shared__ double s_h[kAxi ? HH : 1][kAxi ? TZ : 1];
+    __shared__ double s_ir[QH];  // 1 / r of the window rows
+
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int z0 = (tile % a.tiles_z) * TZ, r0 = (tile / a.tiles_z) * TR;
+    const int nz = a.nz, nr = a.nr;
+    const size_t n = (size_t)a.n;
+    const int t = threadIdx.x, tc = t % TZ, ty = t / TZ;
+    auto real = [&](int y) { return r0 + y >= 0 && r0 + y < nr; };
+
+    // P on the window: every load issued before the first is used (rows
+    // outside the lattice read past the buffer's end, which gives 0, and are
+    // zeroed again below)
+    const size_t nb = (size_t)a.n * sizeof(double);
+    const Rsrc rpz = rsrc_of(a.pz, nb), rpr = rsrc_of(a.pr, nb);
+    constexpr int KQ = (QH * QW + NT - 1) / NT;
+    double vz[KQ], vr[KQ];
+#pragma unroll
+    for (int j = 0; j < KQ; ++j) {
+        const int k = t + j * NT, y = k / QW - 8, c = k % QW - 4;
+        const unsigned x = 8u * (unsigned)((r0 + y) * nz + wrap_col(z0 + c, nz));
+        vz[j] = ld(rpz, x, 0u);
+        vr[j] = ld(rpr, x, 0u);
+    }
+    if (t < QH) s_ir[t] = 1.0 / (r0 + t - 8 + 0.5);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < KQ; ++j) {
+        const int k = t + j * NT, y = k / QW - 8, c = k % QW - 4;
+        if (k < QH * QW) {
+            const double pr = real(y) ? vr[j] : 0.0;
+            s_pz[y + 8][c + 4] = real(y) ? vz[j] : 0.0;
+            s_pr[y + 8][c + 4] = pr;
+            if (kAxi) s_qr[y + 8][c + 4] = pr * kI18 * s_ir[y + 8];
+        }
+    }
+    __syncthreads();
+    if (kAxi) {
+        // adjoint of d_r psi on the extended rows -2 .. nr + 1 that d_rr
+        // reads: the transposed isotropic stencil of d_rr-bar = P_r / (18 r),
+        // plus the direct use of d_r psi on a real row, d_r-bar =
+        // -P_r / (18 r^2)
+        auto drrb = [&](int y, int c) { return s_qr[y + 8][c + 4]; };
+        for (int k = t; k < GH * GW; k += NT) {
+            const int y = k / GW - 6, c = k % GW - 2, yy = r0 + y;
+            double v = 0.0;
+            if (yy >= -2 && yy < nr + 2) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 1; i < lbm::kQ; ++i) {
+                    const int cr = lbm::cr(i), cz = lbm::cz(i);
+                    if (cr == 0) continue;
+                    s += 8.0 * cr * drrb(y - cr, c - cz);
+                    s -= cr * drrb(y - 2 * cr, c - 2 * cz);
+                }
+                v = s * kI36;
+                if (real(y)) v += -s_qr[y + 8][c + 4] * s_ir[y + 8];
+            }
+            s_g[y + 6][c + 2] = v;
+        }
+        // adjoint of the 1D d_r psi on real rows: the transposed z
+        // difference of d_zr-bar = P_z / (18 r)
+        for (int k = t; k < HH * TZ; k += NT) {
+            const int y = k / TZ - 6, c = k % TZ;
+            double v = 0.0;
+            if (real(y)) {
+                auto b = [&](int cc) { return s_pz[y + 8][cc + 4]; };
+                // forward: out(z) = (-in(z+2) + 8 in(z+1) - 8 in(z-1) + in(z-2)) / 12,
+                // here on d_zr-bar = P_z / (18 r)
+                v = (-b(c - 2) + 8.0 * b(c - 1) - 8.0 * b(c + 1) + b(c + 2)) * (kI12 * kI18) * s_ir[y + 8];
+            }
+            s_h[y + 6][c] = v;
+        }
+        __syncthreads();
+    }
+    const int r = r0 + ty;
+    if (r >= nr || z0 + tc >= nz) return;
+    // psi-bar of extended row e at this column (before folding)
+    auto ext = [&](int e) {
+        const int y = e - r0;
+        double s = 0.0;
+        if (kAxi) {
+            // d_r psi = isotropic d_r of the extended psi; only the rows
+            // -2 .. nr + 1 carry an adjoint
+#pragma unroll
+            for (int i = 1; i < lbm::kQ; ++i) {
+                const int cr = lbm::cr(i), cz = lbm::cz(i);
+                if (cr == 0) continue;
+                const int y1 = y - cr, y2 = y - 2 * cr;
+                if (r0 + y1 >= -2 && r0 + y1 < nr + 2) s += (8.0 * cr / 36.0) * s_g[y1 + 6][tc - cz + 2];
+                if (r0 + y2 >= -2 && r0 + y2 < nr + 2) s -= (cr / 36.0) * s_g[y2 + 6][tc - 2 * cz + 2];
+            }
+            // 1D d_r psi on real rows: (-p(y+2) + 8 p(y+1) - 8 p(y-1) + p(y-2)) / 12
+            const int ys[4] = {y - 2, y - 1, y + 1, y + 2};
+            const double cf[4] = {-1.0, 8.0, -8.0, 1.0};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (real(ys[k])) s += (cf[k] / 12.0) * s_h[ys[k] + 6][tc];
+        }
+        // Shan–Chen force: F^SC(x) = -G psi(x) sum_i W_i psi(x + c_i) c_i
+#pragma unroll
+        for (int i = 1; i < lbm::kQ; ++i) {
+            const int ysrc = y - lbm::cr(i), c = tc - lbm::cz(i);
+            if (real(ysrc))
+                s += lbm::weight(i) * (lbm::cz(i) * s_pz[ysrc + 8][c + 4] + lbm::cr(i) * s_pr[ysrc + 8][c + 4]);
+        }
+        return s;
+    };
+    double psib = ext(r);
+    if (r <= 3) psib += ext(-1 - r);            // axis images (rows -4 .. -1)
+    if (r >= nr - 4) psib += ext(2 * nr - 1 - r);  // wall images (rows nr .. nr + 3)
+    const unsigned x = 8u * (unsigned)(r * nz + z0 + tc);
+    // a rounded product, never fused into the additions below: a run adds
+    // the stored rho-bar_B in the next step's gathers, and its lam must equal
+    // that of single steps bit for bit
+    const double rhob = mul_rounded(psib, ld(rsrc_of(a.ex, nb), x, 0u));
+    if (kFinal) {
+        // every load before the first store (the compiler cannot tell that
+        // the stores do not alias them)
+        const Rsrc ro = rsrc_of(a.lam_out, 9 * nb);
+        double l[lbm::kQ];
+#pragma unroll
+        for (int i = 0; i < lbm::kQ; ++i) l[i] = ld(ro, x, i * (unsigned)nb);
+#pragma unroll
+        for (int i = 0; i < lbm::kQ; ++i) st(ro, x, i * (unsigned)nb, l[i] + rhob);
+    } else {
+        st(rsrc_of(a.rhob_out, nb), x, 0u, rhob);
+    }
+}
+
 // acc[0] += dL/dG, acc[1] += dL/dtau: the block partials (of one step, or
 // the running sums of a run) summed in a fixed order
 __global__ void rev_reduce(const double* __restrict__ part, int nparts, double* acc) {
@@ -742,54 +867,107 @@ __global__ void zero_kernel(double* p, long long n) {
     if (x < n) p[x] = 0.0;
 }
 
-// workspace: two forward blocks (a run recomputes step t - 1 into one while
-// step t is reversed from the other), then the adjoint block
-AdjArgs adjoint_args(const lbm_axi_params* p, void* d_ws, int accumulate, int parity = 0) {
-    AdjArgs a{};
+
+// tile shapes: 32 x 16 (512 threads) on lattices with enough of them to
+// fill the chip, 16 x 8 (128 threads) on smaller ones
+struct Shape {
+    int tz, tr;
+};
+Shape shape_of(int nz, int nr) {
+    const long long big = (long long)((nz + 31) / 32) * ((nr + 15) / 16);
+    return big >= 512 ? Shape{32, 16} : Shape{16, 8};
+}
+long long tiles_of(int nz, int nr) {
+    const Shape s = shape_of(nz, nr);
+    return (long long)((nz + s.tz - 1) / s.tz) * ((nr + s.tr - 1) / s.tr);
+}
+
+// workspace (doubles): rho-bar_B [n], P_z [n], P_r [n], E [n], the tiles'
+// partial sums of one step [tiles][2], the running sums of a run [tiles][2]
+struct Layout {
+    double *rhob, *pz, *pr, *ex, *part, *run;
+};
+Layout layout_of(void* ws, int nz, int nr) {
+    const size_t n = (size_t)nz * nr;
+    const size_t nt = (size_t)tiles_of(nz, nr);
+    double* b = static_cast<double*>(ws);
+    return Layout{b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, b + 4 * n + 2 * nt};
+}
+
+TileArgs tile_args(const lbm_axi_params* p, const Layout& w) {
+    TileArgs a{};
     a.nz = p->nz;
     a.nr = p->nr;
     a.n = (long long)p->nz * p->nr;
-    a.ne = (long long)p->nz * (p->nr + 2 * NGA);
     a.G = p->G;
     a.tau = p->tau;
     a.rho0 = p->psi_rho0;
     a.gz = p->gz;
     a.wall = p->wall;
-    a.axisym = p->axisym;
-    double* base = static_cast<double*>(d_ws);
-    a.fw = base + (size_t)parity * fwd_block(a.n, a.ne);
-    a.w = base + 2 * fwd_block(a.n, a.ne);
-    a.accumulate = accumulate;
+    a.tiles_z = (p->nz + shape_of(p->nz, p->nr).tz - 1) / shape_of(p->nz, p->nr).tz;
+    a.pz = w.pz;
+    a.pr = w.pr;
+    a.ex = w.ex;
     return a;
 }
 
-int nparts_of(const AdjArgs& a) { return (int)((a.n + kAdjBlock - 1) / kAdjBlock); }
+template <int TZ, int TR>
+void launch_a_t(const TileArgs& a, bool axi, int tiles, hipStream_t s) {
+    if (axi)
+        hipLaunchKernelGGL((adj_tile_a<TZ, TR, true>), dim3(tiles), dim3(TZ * TR), 0, s, a);
+    else
+        hipLaunchKernelGGL((adj_tile_a<TZ, TR, false>), dim3(tiles), dim3(TZ * TR), 0, s, a);
+}
+template <int TZ, int TR>
+void launch_b_t(const TileArgs& a, bool axi, bool final, int tiles, hipStream_t s) {
+    const dim3 g(tiles), b(TZ * TR);
+    if (axi && final) hipLaunchKernelGGL((adj_tile_b<TZ, TR, true, true>), g, b, 0, s, a);
+    if (axi && !final) hipLaunchKernelGGL((adj_tile_b<TZ, TR, true, false>), g, b, 0, s, a);
+    if (!axi && final) hipLaunchKernelGGL((adj_tile_b<TZ, TR, false, true>), g, b, 0, s, a);
+    if (!axi && !final) hipLaunchKernelGGL((adj_tile_b<TZ, TR, false, false>), g, b, 0, s, a);
+}
 
-// the kernels of one reverse step, in order
-void launch_reverse_step(AdjArgs a, const double* f, const double* lam_next, double* lam, hipStream_t s) {
-    a.f = f;
-    a.lam_next = lam_next;
-    a.lam = lam;
-    const dim3 b(kAdjBlock);
-    const int bn = nparts_of(a), be = (int)((a.ne + kAdjBlock - 1) / kAdjBlock);
-    hipLaunchKernelGGL(fwd_moments, dim3(be), b, 0, s, a);
-    hipLaunchKernelGGL(fwd_dr, dim3(be), b, 0, s, a);
-    hipLaunchKernelGGL(fwd_force, dim3(be), b, 0, s, a);
-    hipLaunchKernelGGL(rev_collision, dim3(bn), b, 0, s, a);
-    hipLaunchKernelGGL(rev_velocity_force, dim3(bn), b, 0, s, a);
-    hipLaunchKernelGGL(rev_dr, dim3(be), b, 0, s, a);
-    hipLaunchKernelGGL(rev_psi_final, dim3(bn), b, 0, s, a);
+// one reverse step: kernel A, then kernel B (final: lam^t complete in
+// a.lam_out; otherwise its rho-bar_B part in a.rhob_out)
+void launch_reverse_step(const TileArgs& a, bool axi, bool final, hipStream_t s) {
+    const int tiles = (int)tiles_of(a.nz, a.nr);
+    if (shape_of(a.nz, a.nr).tz == 32) {
+        launch_a_t<32, 16>(a, axi, tiles, s);
+        launch_b_t<32, 16>(a, axi, final, tiles, s);
+    } else {
+        launch_a_t<16, 8>(a, axi, tiles, s);
+        launch_b_t<16, 8>(a, axi, final, tiles, s);
+    }
 }
 
 int check_adjoint(const lbm_axi_params* p, size_t ws_bytes) {
     if (!p) return LBM_AXI_EINVAL;
     if (p->nz < 4 || p->nr < 6 || !(p->tau > 0.5) || !(p->psi_rho0 > 0.0)) return LBM_AXI_EINVAL;
-    // node indices are split with 32-bit arithmetic
-    if ((long long)p->nz * (p->nr + 2 * NGA) > INT_MAX) return LBM_AXI_EINVAL;
+    // node indices are 32-bit
+    if ((long long)p->nz * (p->nr + 12) > INT_MAX) return LBM_AXI_EINVAL;
     if (p->wall != 0 && p->wall != 1) return LBM_AXI_EINVAL;
     if (p->precision != LBM_AXI_FP64 || p->flags != 0) return LBM_AXI_EUNSUP;
     if (ws_bytes < lbm_axi_adjoint_workspace_bytes(p->nz, p->nr)) return LBM_AXI_ENOMEM;
     return LBM_AXI_OK;
+}
+
+// one reverse step into d_lam with the workspace at ws (both public single
+// steps)
+int reverse_step(const lbm_axi_params* p, const double* d_f, const double* d_lam_next, double* d_lam,
+                 double* d_grad_acc, void* ws, hipStream_t s) {
+    const Layout w = layout_of(ws, p->nz, p->nr);
+    TileArgs a = tile_args(p, w);
+    a.f = d_f;
+    a.lam_p = d_lam_next;
+    a.rhob_in = nullptr;
+    a.lam_out = d_lam;
+    a.part = w.part;
+    a.accumulate = 0;
+    launch_reverse_step(a, p->axisym != 0, true, s);
+    if (d_grad_acc)
+        hipLaunchKernelGGL(rev_reduce, dim3(1), dim3(256), 0, s, w.part, (int)tiles_of(p->nz, p->nr), d_grad_acc);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LBM_AXI_OK : lbm_host::hip_fail(e, "adjoint kernel launch");
 }
 
 constexpr int kMaxDevices = 64;
@@ -833,22 +1011,15 @@ int lbm_axi_adjoint_step_noalloc(const lbm_axi_params* p, const double* d_f, con
     void* ws = nullptr;
     const int rs = noalloc_scratch(&ws);
     if (rs != LBM_AXI_OK) return rs;
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    // the kernels overwrite every field and partial sum of one step before
+    // the kernels write every field and partial sum of one step before
     // reading it, so nothing needs clearing
-    AdjArgs a = adjoint_args(p, ws, 0);
-    launch_reverse_step(a, d_f, d_lam_next, d_lam, s);
-    if (d_grad_acc)
-        hipLaunchKernelGGL(rev_reduce, dim3(1), dim3(256), 0, s, a.w + part_off(a.n, a.ne), nparts_of(a), d_grad_acc);
-    const hipError_t e = hipGetLastError();
-    return e == hipSuccess ? LBM_AXI_OK : lbm_host::hip_fail(e, "adjoint kernel launch");
+    return reverse_step(p, d_f, d_lam_next, d_lam, d_grad_acc, ws, static_cast<hipStream_t>(hip_stream));
 }
 
 size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr) {
-    if (nz < 4 || nr < 6 || (long long)nz * (nr + 2 * NGA) > INT_MAX) return 0;
-    const long long n = (long long)nz * nr, ne = (long long)nz * (nr + 2 * NGA);
-    const size_t nparts = (size_t)((n + kAdjBlock - 1) / kAdjBlock);
-    return (2 * fwd_block(n, ne) + fbar_off(n, ne) + 9 * (size_t)n + 4 * nparts) * sizeof(double);
+    if (nz < 4 || nr < 6 || (long long)nz * (nr + 12) > INT_MAX) return 0;
+    const size_t n = (size_t)nz * nr;
+    return (4 * n + 4 * (size_t)tiles_of(nz, nr)) * sizeof(double);
 }
 
 int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const double* d_lam_next, double* d_lam,
@@ -856,12 +1027,7 @@ int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const doubl
     if (!p || !d_f || !d_lam_next || !d_lam || !d_ws) return LBM_AXI_EINVAL;
     const int rc = check_adjoint(p, ws_bytes);
     if (rc != LBM_AXI_OK) return rc;
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    AdjArgs a = adjoint_args(p, d_ws, 0);
-    launch_reverse_step(a, d_f, d_lam_next, d_lam, s);
-    if (d_grad_acc)
-        hipLaunchKernelGGL(rev_reduce, dim3(1), dim3(256), 0, s, a.w + part_off(a.n, a.ne), nparts_of(a), d_grad_acc);
-    return hipGetLastError() == hipSuccess ? LBM_AXI_OK : LBM_AXI_EHIP;
+    return reverse_step(p, d_f, d_lam_next, d_lam, d_grad_acc, d_ws, static_cast<hipStream_t>(hip_stream));
 }
 
 int lbm_axi_adjoint_run(const lbm_axi_params* p, const double* d_states, int32_t k, double* d_lam, double* d_tmp,
@@ -871,43 +1037,28 @@ int lbm_axi_adjoint_run(const lbm_axi_params* p, const double* d_states, int32_t
     if (rc != LBM_AXI_OK) return rc;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const size_t n9 = 9 * (size_t)p->nz * (size_t)p->nr;
-    AdjArgs a = adjoint_args(p, d_ws, 1);
-    double* run = a.w + run_off(a.n, a.ne);
-    const int nparts = nparts_of(a);
-    // the block sums of dL/dG, dL/dtau run over the k steps and are reduced
+    const Layout w = layout_of(d_ws, p->nz, p->nr);
+    const int tiles = (int)tiles_of(p->nz, p->nr);
+    // the tiles' sums of dL/dG, dL/dtau run over the k steps and are reduced
     // once at the end (a kernel, not a memset, clears them)
-    hipLaunchKernelGGL(zero_kernel, dim3(nblk(2 * (long long)nparts)), dim3(256), 0, s, run, 2 * (long long)nparts);
-    const dim3 b(kAdjBlock);
-    const int bn = nparts, be = (int)((a.ne + kAdjBlock - 1) / kAdjBlock);
-    double* cur = d_lam;  // holds lam^{t0+j+1} before step j
+    hipLaunchKernelGGL(zero_kernel, dim3(nblk(2 * (long long)tiles)), dim3(256), 0, s, w.run, 2 * (long long)tiles);
+    double* cur = d_lam;  // lam^{t0+j+1} before step j: all of it (j = k - 1), or its lam_p part
     double* nxt = d_tmp;
-    if (k > 0) {
-        // fields of the last state, into forward block 0
-        AdjArgs f0 = adjoint_args(p, d_ws, 1, 0);
-        f0.f = d_states + (size_t)(k - 1) * n9;
-        hipLaunchKernelGGL(fwd_moments, dim3(be), b, 0, s, f0);
-        hipLaunchKernelGGL(fwd_dr, dim3(be), b, 0, s, f0);
-        hipLaunchKernelGGL(fwd_force, dim3(be), b, 0, s, f0);
-    }
-    int par = 0;
     for (int32_t j = k - 1; j >= 0; --j) {
-        AdjArgs ar = adjoint_args(p, d_ws, 1, par);  // step j, fields in block par
-        ar.f = d_states + (size_t)j * n9;
-        ar.lam_next = cur;
-        ar.lam = nxt;
-        AdjArgs af = adjoint_args(p, d_ws, 1, 1 - par);  // step j - 1, into the other block
-        const int fwd = j > 0 ? 1 : 0;
-        af.f = fwd ? d_states + (size_t)(j - 1) * n9 : nullptr;
-        hipLaunchKernelGGL(rev_collision_fwd_moments, dim3(be), b, 0, s, ar, af, fwd);
-        hipLaunchKernelGGL(rev_velocity_force_fwd_dr, dim3(be), b, 0, s, ar, af, fwd);
-        hipLaunchKernelGGL(rev_dr_fwd_force, dim3(be), b, 0, s, ar, af, fwd);
-        hipLaunchKernelGGL(rev_psi_final, dim3(bn), b, 0, s, ar);
+        TileArgs a = tile_args(p, w);
+        a.f = d_states + (size_t)j * n9;
+        a.lam_p = cur;
+        a.rhob_in = j == k - 1 ? nullptr : w.rhob;
+        a.lam_out = nxt;
+        a.rhob_out = w.rhob;
+        a.part = w.run;
+        a.accumulate = 1;
+        launch_reverse_step(a, p->axisym != 0, j == 0, s);
         double* t = cur;
         cur = nxt;
         nxt = t;
-        par = 1 - par;
     }
-    if (d_grad_acc && k > 0) hipLaunchKernelGGL(rev_reduce, dim3(1), dim3(256), 0, s, run, nparts, d_grad_acc);
+    if (d_grad_acc && k > 0) hipLaunchKernelGGL(rev_reduce, dim3(1), dim3(256), 0, s, w.run, tiles, d_grad_acc);
     if (hipGetLastError() != hipSuccess) return LBM_AXI_EHIP;
     if (cur != d_lam && hipMemcpyAsync(d_lam, cur, n9 * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
         return LBM_AXI_EHIP;

@@ -145,9 +145,9 @@ def test_batch_rejects_midlink_source():
 
 
 def test_adjoint_size_limits():
-    """The adjoint's stencils wrap at most two columns: it takes nz >= 4 and
-    nr >= 6; smaller grids get no workspace size, and the calls return
-    LBM_AXI_EINVAL before any device work."""
+    """The adjoint takes nz >= 4 and nr >= 6 (its psi window mirrors up to
+    six rows at the axis and the wall); smaller grids get no workspace size,
+    and the calls return LBM_AXI_EINVAL before any device work."""
     from paper_1310_1871_amd import adjoint as A
     from paper_1310_1871_amd import lbm_axi as L
     ws = A._lib.lbm_axi_adjoint_workspace_bytes

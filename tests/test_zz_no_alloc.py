@@ -71,8 +71,8 @@ def _both(nz, nr, seed):
 
 
 def test_noalloc_adjoint_step_matches_workspace_step_twice():
-    _both(128, 64, 31)   # first call on this GPU: looks the scratch up
-    _both(64, 32, 32)    # a smaller grid in the same scratch
+    _both(1024, 512, 31)  # first call on this GPU: looks the scratch up (32 x 16 tiles)
+    _both(64, 32, 32)     # a smaller grid in the same scratch (16 x 8 tiles)
 
 
 def test_noalloc_rejects_grids_beyond_the_scratch():
@@ -80,7 +80,7 @@ def test_noalloc_rejects_grids_beyond_the_scratch():
     lib = A._lib
     lib.lbm_axi_adjoint_step_noalloc.restype = ctypes.c_int
     lib.lbm_axi_adjoint_step_noalloc.argtypes = [ctypes.POINTER(L.Params)] + [ctypes.c_void_p] * 5
-    p = L.make_params(512, 256, G=-5.5, tau=0.9)
+    p = L.make_params(2048, 1024, G=-5.5, tau=0.9)
     dummy = ctypes.c_void_p(256)
     rc = lib.lbm_axi_adjoint_step_noalloc(ctypes.byref(p), dummy, dummy, dummy, None, None)
     assert rc == L.ENOMEM
