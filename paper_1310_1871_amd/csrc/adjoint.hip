@@ -77,11 +77,13 @@ struct TileArgs {
     int accumulate;            // 1: add to part (the running sums of a run), 0: overwrite
 };
 
-// tile geometry: TZ x TR nodes, one thread per node; window offsets are
+// tile geometry: TZ x TR nodes, NTH threads (at least one per node: on small
+// lattices, where a kernel's time is the length of one workgroup's chain of
+// loads, spare threads share the window's loads); window offsets are
 // relative to the tile's first node
-template <int TZ, int TR>
+template <int TZ, int TR, int NTH = TZ * TR>
 struct Tile {
-    static constexpr int NT = TZ * TR;
+    static constexpr int NT = NTH, NTILE = TZ * TR;
     static constexpr int PW = TZ + 12, PH = TR + 12;  // psi: columns and rows [-6, T + 6)
     static constexpr int DW = TZ + 8, DH = TR + 8;    // isotropic d_r psi: [-4, T + 4)
     static constexpr int EW = TZ + 8, EH = TR + 4;    // 1D d_r psi: columns [-4, TZ + 4), rows [-2, TR + 2)
@@ -90,7 +92,7 @@ struct Tile {
     static constexpr int OUTN = 8 * (TZ + 12) + 8 * (TR + 4);  // ring nodes 3 to 6 away
     static constexpr int RS = (R2N + OUTN + NT - 1) / NT;      // ring slots per thread
     static_assert(R2N <= NT, "the first ring slot holds every ring node within 2 of the tile");
-    static_assert(NT % 64 == 0, "whole waves");
+    static_assert(NT % 64 == 0 && NTILE % 64 == 0 && NT >= NTILE, "whole waves, a thread per tile node");
 };
 
 // ring node k of the window: first the nodes within 2 of the tile (rows
@@ -98,7 +100,7 @@ struct Tile {
 // rows), then the nodes 3 to 6 away
 template <int TZ, int TR>
 __device__ __forceinline__ void ring_pos(int k, int& c, int& y) {
-    constexpr int W2 = TZ + 4, W6 = TZ + 12, R2N = Tile<TZ, TR>::R2N;
+    constexpr int W2 = TZ + 4, W6 = TZ + 12, R2N = 4 * W2 + 4 * TR;
     if (k < 2 * W2) {
         y = -2 + k / W2;
         c = -2 + k % W2;
@@ -212,10 +214,12 @@ constexpr double kI36 = 1.0 / 36.0, kI12 = 1.0 / 12.0, kI18 = 1.0 / 18.0;
 
 // Kernel A.  kAxi: the axisymmetric terms (source, F^{sym}, velocity
 // stencils) on; off, the plain 2D Shan–Chen step.
-template <int TZ, int TR, bool kAxi>
-__global__ __launch_bounds__(TZ * TR) __attribute__((amdgpu_waves_per_eu(TZ * TR >= 512 ? 4 : 1))) void adj_tile_a(const TileArgs a) {
-    using T = Tile<TZ, TR>;
-    constexpr int NT = T::NT;
+// The 32 x 16 instance is held to 128 VGPRs, so that two workgroups share a
+// CU and one's loads overlap the other's arithmetic (at 2048 x 1024: 229 us
+// per launch, against 344 us at 212 VGPRs and one workgroup per CU).
+template <int TZ, int TR, bool kAxi, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TZ * TR >= 512 ? 4 : 1))) void adj_tile_a(const TileArgs a) {
+    using T = Tile<TZ, TR, NT>;
     __shared__ double s_psi[T::PH][T::PW];
     __shared__ double s_dr[T::DH][T::DW];
     __shared__ double s_d1[T::EH][T::EW];
@@ -247,12 +251,13 @@ __global__ __launch_bounds__(TZ * TR) __attribute__((amdgpu_waves_per_eu(TZ * TR
         }
     };
     const int zt = wrap_col(z0 + tc, nz), rt = r0 + ty;
-    const bool real_t = rt < nr;
+    const bool has_tile = NT == T::NTILE || t < T::NTILE;  // a thread with a tile node
+    const bool real_t = has_tile && rt < nr;
     const bool active = real_t && z0 + tc < nz;
     double nu[lbm::kQ];
     double rho_t = 0, jz_t = 0, jr_t = 0;
     const unsigned xt = 8u * (unsigned)(mirror_even(rt, nr) * nz + zt);
-    {
+    if (has_tile) {
         double fl[lbm::kQ];
 #pragma unroll
         for (int i = 0; i < lbm::kQ; ++i) fl[i] = ld(bf.f, xt, i * bf.plane);
@@ -421,7 +426,7 @@ __global__ __launch_bounds__(TZ * TR) __attribute__((amdgpu_waves_per_eu(TZ * TR
         if (real_t) {
             s_uz[ty + 2][tc + 2] = fw.uz;
             s_ur[ty + 2][tc + 2] = fw.ur;
-        } else {
+        } else if (has_tile) {
             velocity_into_lds(tc, ty, rho_t, jz_t, jr_t);
         }
         if (ring2) velocity_into_lds(cq, yq, rho_q, jz_q, jr_q);
@@ -619,9 +624,8 @@ __device__ __forceinline__ double mul_rounded(double x, double y) {
 // Kernel B: psi-bar from the psi stencils of the other nodes, through P.
 // kFinal: add rho-bar_B to lam_out in every direction (lam_out then holds
 // lam^t); otherwise write rho-bar_B.
-template <int TZ, int TR, bool kAxi, bool kFinal>
-__global__ __launch_bounds__(TZ * TR) void adj_tile_b(const TileArgs a) {
-    constexpr int NT = TZ * TR;
+template <int TZ, int TR, bool kAxi, bool kFinal, int NT>
+__global__ __launch_bounds__(NT) void adj_tile_b(const TileArgs a) {
     constexpr int QW = TZ + 8, QH = TR + 16;  // P: columns [-4, TZ + 4), rows [-8, TR + 8)
     constexpr int GW = TZ + 4, GH = TR + 12;  // adjoint of d_r psi: columns [-2, TZ + 2), rows [-6, TR + 6)
     constexpr int HH = TR + 12;               // adjoint of the 1D d_r psi: the tile's columns, rows [-6, TR + 6)
@@ -705,7 +709,7 @@ __global__ __launch_bounds__(TZ * TR) void adj_tile_b(const TileArgs a) {
         __syncthreads();
     }
     const int r = r0 + ty;
-    if (r >= nr || z0 + tc >= nz) return;
+    if (t >= TZ * TR || r >= nr || z0 + tc >= nz) return;
     // psi-bar of extended row e at this column (before folding)
     auto ext = [&](int e) {
         const int y = e - r0;
@@ -868,14 +872,19 @@ __global__ void zero_kernel(double* p, long long n) {
 }
 
 
-// tile shapes: 32 x 16 (512 threads) on lattices with enough of them to
-// fill the chip, 16 x 8 (128 threads) on smaller ones
+// tile shapes: 32 x 16 nodes and 512 threads on lattices with at least 512
+// such tiles; 16 x 8 nodes with 512 threads on smaller ones, where a
+// kernel's time is one workgroup's chain of loads and the spare threads
+// share the window (at 256 x 128 the reverse step took 19.5 us with 128
+// threads, 18.8 with 256, 18.6 with 512; 16 x 4 and 8 x 8 tiles were no
+// faster with 256 threads and 25% slower with 512)
 struct Shape {
     int tz, tr;
 };
+constexpr int kSmallTZ = 16, kSmallTR = 8, kSmallNT = 512;
 Shape shape_of(int nz, int nr) {
     const long long big = (long long)((nz + 31) / 32) * ((nr + 15) / 16);
-    return big >= 512 ? Shape{32, 16} : Shape{16, 8};
+    return big >= 512 ? Shape{32, 16} : Shape{kSmallTZ, kSmallTR};
 }
 long long tiles_of(int nz, int nr) {
     const Shape s = shape_of(nz, nr);
@@ -911,20 +920,20 @@ TileArgs tile_args(const lbm_axi_params* p, const Layout& w) {
     return a;
 }
 
-template <int TZ, int TR>
+template <int TZ, int TR, int NT>
 void launch_a_t(const TileArgs& a, bool axi, int tiles, hipStream_t s) {
     if (axi)
-        hipLaunchKernelGGL((adj_tile_a<TZ, TR, true>), dim3(tiles), dim3(TZ * TR), 0, s, a);
+        hipLaunchKernelGGL((adj_tile_a<TZ, TR, true, NT>), dim3(tiles), dim3(NT), 0, s, a);
     else
-        hipLaunchKernelGGL((adj_tile_a<TZ, TR, false>), dim3(tiles), dim3(TZ * TR), 0, s, a);
+        hipLaunchKernelGGL((adj_tile_a<TZ, TR, false, NT>), dim3(tiles), dim3(NT), 0, s, a);
 }
-template <int TZ, int TR>
+template <int TZ, int TR, int NT>
 void launch_b_t(const TileArgs& a, bool axi, bool final, int tiles, hipStream_t s) {
-    const dim3 g(tiles), b(TZ * TR);
-    if (axi && final) hipLaunchKernelGGL((adj_tile_b<TZ, TR, true, true>), g, b, 0, s, a);
-    if (axi && !final) hipLaunchKernelGGL((adj_tile_b<TZ, TR, true, false>), g, b, 0, s, a);
-    if (!axi && final) hipLaunchKernelGGL((adj_tile_b<TZ, TR, false, true>), g, b, 0, s, a);
-    if (!axi && !final) hipLaunchKernelGGL((adj_tile_b<TZ, TR, false, false>), g, b, 0, s, a);
+    const dim3 g(tiles), b(NT);
+    if (axi && final) hipLaunchKernelGGL((adj_tile_b<TZ, TR, true, true, NT>), g, b, 0, s, a);
+    if (axi && !final) hipLaunchKernelGGL((adj_tile_b<TZ, TR, true, false, NT>), g, b, 0, s, a);
+    if (!axi && final) hipLaunchKernelGGL((adj_tile_b<TZ, TR, false, true, NT>), g, b, 0, s, a);
+    if (!axi && !final) hipLaunchKernelGGL((adj_tile_b<TZ, TR, false, false, NT>), g, b, 0, s, a);
 }
 
 // one reverse step: kernel A, then kernel B (final: lam^t complete in
@@ -932,11 +941,11 @@ void launch_b_t(const TileArgs& a, bool axi, bool final, int tiles, hipStream_t 
 void launch_reverse_step(const TileArgs& a, bool axi, bool final, hipStream_t s) {
     const int tiles = (int)tiles_of(a.nz, a.nr);
     if (shape_of(a.nz, a.nr).tz == 32) {
-        launch_a_t<32, 16>(a, axi, tiles, s);
-        launch_b_t<32, 16>(a, axi, final, tiles, s);
+        launch_a_t<32, 16, 512>(a, axi, tiles, s);
+        launch_b_t<32, 16, 512>(a, axi, final, tiles, s);
     } else {
-        launch_a_t<16, 8>(a, axi, tiles, s);
-        launch_b_t<16, 8>(a, axi, final, tiles, s);
+        launch_a_t<kSmallTZ, kSmallTR, kSmallNT>(a, axi, tiles, s);
+        launch_b_t<kSmallTZ, kSmallTR, kSmallNT>(a, axi, final, tiles, s);
     }
 }
 
