@@ -151,6 +151,19 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return x * q + (x < rem ? x : rem) + k;
 }
 
+// the same runs walked in blocks 8 tile columns wide spanning the XCD's
+// rows, when each run is whole tile rows and a row is a multiple of 8 tiles:
+// the workgroups resident on an XCD at one time (two per CU) then cover a
+// compact block, whose 6-node rings overlap in the XCD's L2, rather than a
+// whole row of tiles, whose windows do not fit it
+__device__ __forceinline__ int block_tile(int b, int nb, int tiles_z) {
+    const int q = nb >> 3, rem = nb & 7;
+    if (rem != 0 || q % tiles_z != 0 || (tiles_z & 7) != 0) return xcd_tile(b, nb);
+    const int x = b & 7, k = b >> 3, rows = q / tiles_z;
+    const int blk = k / (8 * rows), w = k % (8 * rows);
+    return x * q + (w >> 3) * tiles_z + blk * 8 + (w & 7);
+}
+
 // Buffer-resource loads and stores: 32-bit byte offsets (one VGPR per
 // address instead of a 64-bit pointer pair), the plane of a state or adjoint
 // in the scalar offset.  Every buffer here is below 4 GiB (the adjoint takes
@@ -204,8 +217,9 @@ __device__ __forceinline__ Bufs bufs_of(const TileArgs& a) {
 __device__ __forceinline__ double gather_nu(const TileArgs& a, const Bufs& b, int i, int z, int r) {
     int d;
     const unsigned x = (unsigned)push_target(i, z, r, a.nz, a.nr, a.wall, d);
-    const double v = ld(b.lam, (unsigned)d * b.plane + 8u * x, 0u);
-    return a.rhob_in ? v + ld(b.rhob, 8u * x, 0u) : v;
+    // without rho-bar_B (rhob_in NULL) its resource has no records and the
+    // load reads 0: no branch, which would make each gather wait for the last
+    return ld(b.lam, (unsigned)d * b.plane + 8u * x, 0u) + ld(b.rhob, 8u * x, 0u);
 }
 
 // the stencils' divisors as factors (a division by a constant that is not
@@ -214,11 +228,11 @@ constexpr double kI36 = 1.0 / 36.0, kI12 = 1.0 / 12.0, kI18 = 1.0 / 18.0;
 
 // Kernel A.  kAxi: the axisymmetric terms (source, F^{sym}, velocity
 // stencils) on; off, the plain 2D Shan–Chen step.
-// The 32 x 16 instance is held to 128 VGPRs, so that two workgroups share a
-// CU and one's loads overlap the other's arithmetic (at 2048 x 1024: 229 us
-// per launch, against 344 us at 212 VGPRs and one workgroup per CU).
+// The 256-thread instance is held to three waves per SIMD (168 VGPRs), so
+// that three workgroups share a CU and their loads overlap each other's
+// arithmetic.
 template <int TZ, int TR, bool kAxi, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TZ * TR >= 512 ? 4 : 1))) void adj_tile_a(const TileArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 3 : 1))) void adj_tile_a(const TileArgs a) {
     using T = Tile<TZ, TR, NT>;
     __shared__ double s_psi[T::PH][T::PW];
     __shared__ double s_dr[T::DH][T::DW];
@@ -231,7 +245,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TZ * TR >= 5
     __shared__ double s_hr[T::UH][T::UW];
     __shared__ double s_red[2][NT / 64];
 
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = block_tile(blockIdx.x, gridDim.x, a.tiles_z);
     const int z0 = (tile % a.tiles_z) * TZ, r0 = (tile / a.tiles_z) * TR;
     const int nz = a.nz, nr = a.nr;
     const size_t n = (size_t)a.n;
@@ -254,8 +268,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TZ * TR >= 5
     const bool has_tile = NT == T::NTILE || t < T::NTILE;  // a thread with a tile node
     const bool real_t = has_tile && rt < nr;
     const bool active = real_t && z0 + tc < nz;
-    double nu[lbm::kQ];
-    double rho_t = 0, jz_t = 0, jr_t = 0;
+    double rho_t = 0, jz_t = 0, jr_t = 0, nuf_t = 0;
     const unsigned xt = 8u * (unsigned)(mirror_even(rt, nr) * nz + zt);
     if (has_tile) {
         double fl[lbm::kQ];
@@ -264,6 +277,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TZ * TR >= 5
         // a ghost row (last tile of a short lattice) gathers at the last
         // row and discards the values: no branch around the loads
         const int rg = real_t ? rt : nr - 1;
+        double nu[lbm::kQ];
 #pragma unroll
         for (int i = 0; i < lbm::kQ; ++i) {
             const double v = gather_nu(a, bf, i, zt, rg);
@@ -274,6 +288,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TZ * TR >= 5
             rho_t += fl[i];
             jz_t += lbm::cz(i) * fl[i];
             jr_t += lbm::cr(i) * fl[i];
+            nuf_t += nu[i] * fl[i];  // sum_i nu_i f_i, the populations' part of tau-bar
         }
         s_psi[ty + 6][tc + 6] = psi_of(rho_t);
         double hz = 0, hr = 0;
@@ -284,6 +299,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TZ * TR >= 5
         }
         store_h(tc, ty, real_t, rho_t, hz, hr);
     }
+    // the tile node's loads are consumed before the ring's are issued (all of
+    // them at once do not fit the registers of the large-lattice instance)
+    __builtin_amdgcn_sched_barrier(0);
     // ring nodes; the first slot's node, when within 2 of the tile, keeps
     // rho and j for its velocity
     double rho_q = 0, jz_q = 0, jr_q = 0;
@@ -400,36 +418,49 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TZ * TR >= 5
         o.ur = (jr + 0.5 * Fr) * irho;
         return o;
     };
-    // velocity of window node (c, y) of the velocity window into LDS: a real
-    // row computes its own; rows -2, -1 and nr, nr + 1 compute their mirror
-    // node's (whose populations the load read); rows further out are never
-    // read by a tile node
-    auto velocity_into_lds = [&](int c, int y, double rho, double jz, double jr) {
+    // where window node (c, y) of the velocity window takes its velocity: a
+    // real row its own; rows -2, -1 and nr, nr + 1 their mirror node's (whose
+    // populations the load read), u_r odd at the axis; rows further out are
+    // never read by a tile node (*use false: u = 0).  One forward_at per slot.
+    auto source_row = [&](int y, bool& use, double& sgn) {
         const int yy = r0 + y;
-        double uz = 0.0, ur = 0.0;
-        if (yy >= 0 && yy < nr) {
-            const Fwd o = forward_at(c, y, rho, jz, jr);
-            uz = o.uz;
-            ur = o.ur;
-        } else if (yy >= -2 && yy < nr + 2) {
-            const int ym = (yy < 0 ? -1 - yy : 2 * nr - 1 - yy) - r0;
-            const Fwd o = forward_at(c, ym, rho, jz, jr);
-            uz = o.uz;
-            ur = yy < 0 ? -o.ur : o.ur;
-        }
-        s_uz[y + 2][c + 2] = uz;
-        s_ur[y + 2][c + 2] = ur;
+        use = yy >= -2 && yy < nr + 2;
+        sgn = yy < 0 ? -1.0 : 1.0;
+        if (yy >= 0 && yy < nr) return y;
+        const int ym = (yy < 0 ? -1 - yy : 2 * nr - 1 - yy) - r0;
+        return use ? ym : y;
     };
     Fwd fw{};
-    if (real_t) fw = forward_at(tc, ty, rho_t, jz_t, jr_t);
-    if (kAxi) {
-        if (real_t) {
-            s_uz[ty + 2][tc + 2] = fw.uz;
-            s_ur[ty + 2][tc + 2] = fw.ur;
-        } else if (has_tile) {
-            velocity_into_lds(tc, ty, rho_t, jz_t, jr_t);
+    {
+        bool use;
+        double sgn;
+        const int ys = source_row(ty, use, sgn);
+        if (has_tile && use) {
+            const Fwd o = forward_at(tc, ys, rho_t, jz_t, jr_t);
+            if (real_t) fw = o;
+            if (kAxi) {
+                s_uz[ty + 2][tc + 2] = o.uz;
+                s_ur[ty + 2][tc + 2] = sgn * o.ur;
+            }
+        } else if (kAxi && has_tile) {
+            s_uz[ty + 2][tc + 2] = 0.0;
+            s_ur[ty + 2][tc + 2] = 0.0;
         }
-        if (ring2) velocity_into_lds(cq, yq, rho_q, jz_q, jr_q);
+    }
+    if (kAxi) {
+        if (ring2) {
+            bool use;
+            double sgn;
+            const int ys = source_row(yq, use, sgn);
+            double uz = 0.0, ur = 0.0;
+            if (use) {
+                const Fwd o = forward_at(cq, ys, rho_q, jz_q, jr_q);
+                uz = o.uz;
+                ur = sgn * o.ur;
+            }
+            s_uz[yq + 2][cq + 2] = uz;
+            s_ur[yq + 2][cq + 2] = ur;
+        }
         __syncthreads();
     }
 
@@ -501,11 +532,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TZ * TR >= 5
             drur = a3 * kI36;
         }
         __builtin_amdgcn_sched_barrier(0);
-        // the node's populations again (from L2: this workgroup loaded them
-        // in step 1), rather than held in registers across three barriers
-        double fl[lbm::kQ];
+        // nu again (from L2: step 1 gathered the same values), rather than
+        // held in registers across three barriers
+        double nu[lbm::kQ];
 #pragma unroll
-        for (int i = 0; i < lbm::kQ; ++i) fl[i] = ld(bf.f, xt, i * bf.plane);
+        for (int i = 0; i < lbm::kQ; ++i) nu[i] = gather_nu(a, bf, i, zt, rt);
+        // tau-bar of BGK: sum_i nu_i (f_i - f^eq_i) / tau^2, its population
+        // part summed in step 1 (the populations are not kept)
+        double nfeq = 0.0;
         double rhob = 0, qzb = 0, qrb = 0, taub = 0, massb = 0, hzb = 0, hrb = 0;
         const double qq = 1.5 * (qz * qz + qr * qr);
 #pragma unroll
@@ -515,7 +549,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TZ * TR >= 5
             const double cu = lbm::cz(i) * qz + lbm::cr(i) * qr;
             const double poly = 3.0 * cu + 4.5 * cu * cu - qq;
             const double feq = wi * rho * (1.0 + poly);
-            taub += v * (fl[i] - feq) * inv_tau * inv_tau;
+            nfeq += v * feq;
             const double feqb = v * inv_tau;
             rhob += feqb * wi * (1.0 + poly);
             const double dpoly = wi * rho * feqb * (3.0 + 9.0 * cu);  // d feq / d cu
@@ -525,6 +559,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(TZ * TR >= 5
             hzb += 3.0 * wi * lbm::cz(i) * v;
             hrb += 3.0 * wi * lbm::cr(i) * v;
         }
+        taub += (nuf_t - nfeq) * inv_tau * inv_tau;
         double uzb = 0, urb = 0;
         if (kAxi) {
             const double mu = rho * (tau - 0.5) / 3.0;
@@ -636,7 +671,7 @@ __global__ __launch_bounds__(NT) void adj_tile_b(const TileArgs a) {
     __shared__ double s_h[kAxi ? HH : 1][kAxi ? TZ : 1];
     __shared__ double s_ir[QH];  // 1 / r of the window rows
 
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = block_tile(blockIdx.x, gridDim.x, a.tiles_z);
     const int z0 = (tile % a.tiles_z) * TZ, r0 = (tile / a.tiles_z) * TR;
     const int nz = a.nz, nr = a.nr;
     const size_t n = (size_t)a.n;
@@ -872,19 +907,23 @@ __global__ void zero_kernel(double* p, long long n) {
 }
 
 
-// tile shapes: 32 x 16 nodes and 512 threads on lattices with at least 512
-// such tiles; 16 x 8 nodes with 512 threads on smaller ones, where a
-// kernel's time is one workgroup's chain of loads and the spare threads
-// share the window (at 256 x 128 the reverse step took 19.5 us with 128
-// threads, 18.8 with 256, 18.6 with 512; 16 x 4 and 8 x 8 tiles were no
-// faster with 256 threads and 25% slower with 512)
+// Tile shapes.  Lattices of at least 262 144 nodes: 16 x 16 nodes and 256
+// threads, three workgroups per CU (held to 168 VGPRs); at 2048 x 1024 the
+// (forward + backward) / forward ratio was 5.40 with it, against 5.53 for
+// 32 x 8 tiles (256 threads), 5.93 for 32 x 16 (512 threads, one
+// workgroup per CU at 148 VGPRs), 6.26 for 32 x 8 (512 threads) and 6.33
+// for 32 x 16 held to 128 VGPRs (spills).  Smaller lattices: 16 x 8 nodes
+// with 512 threads, where a kernel's time is one workgroup's chain of loads
+// and the spare threads share the window (at 256 x 128 the reverse step
+// took 19.5 us with 128 threads, 18.8 with 256, 18.6 with 512; 16 x 4 and
+// 8 x 8 tiles were no faster with 256 threads and 25% slower with 512).
 struct Shape {
     int tz, tr;
 };
 constexpr int kSmallTZ = 16, kSmallTR = 8, kSmallNT = 512;
+constexpr int kLargeTZ = 16, kLargeTR = 16, kLargeNT = 256;
 Shape shape_of(int nz, int nr) {
-    const long long big = (long long)((nz + 31) / 32) * ((nr + 15) / 16);
-    return big >= 512 ? Shape{32, 16} : Shape{kSmallTZ, kSmallTR};
+    return (long long)nz * nr >= 262144 ? Shape{kLargeTZ, kLargeTR} : Shape{kSmallTZ, kSmallTR};
 }
 long long tiles_of(int nz, int nr) {
     const Shape s = shape_of(nz, nr);
@@ -940,9 +979,9 @@ void launch_b_t(const TileArgs& a, bool axi, bool final, int tiles, hipStream_t 
 // a.lam_out; otherwise its rho-bar_B part in a.rhob_out)
 void launch_reverse_step(const TileArgs& a, bool axi, bool final, hipStream_t s) {
     const int tiles = (int)tiles_of(a.nz, a.nr);
-    if (shape_of(a.nz, a.nr).tz == 32) {
-        launch_a_t<32, 16, 512>(a, axi, tiles, s);
-        launch_b_t<32, 16, 512>(a, axi, final, tiles, s);
+    if (shape_of(a.nz, a.nr).tr == kLargeTR) {
+        launch_a_t<kLargeTZ, kLargeTR, kLargeNT>(a, axi, tiles, s);
+        launch_b_t<kLargeTZ, kLargeTR, kLargeNT>(a, axi, final, tiles, s);
     } else {
         launch_a_t<kSmallTZ, kSmallTR, kSmallNT>(a, axi, tiles, s);
         launch_b_t<kSmallTZ, kSmallTR, kSmallNT>(a, axi, final, tiles, s);

@@ -48,9 +48,9 @@ CASES = [
     (48, 24, -5.0, 0.8, 1, 0, 0.0),
     (37, 13, -4.5, 1.1, 0, 1, 1e-4),
     (5, 8, -4.5, 0.7, 1, 1, 0.0),
-    # enough 32 x 16 tiles for the large-lattice shape, ragged in z and r
-    (520, 500, -5.5, 0.9, 1, 1, 1e-5),
-    (520, 500, -5.0, 0.8, 0, 0, 0.0),
+    # large enough for the large-lattice tiles (16 x 16), ragged in z and r
+    (530, 500, -5.5, 0.9, 1, 1, 1e-5),
+    (530, 500, -5.0, 0.8, 0, 0, 0.0),
 ]
 
 
