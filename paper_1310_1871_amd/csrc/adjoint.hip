@@ -269,6 +269,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
     const bool real_t = has_tile && rt < nr;
     const bool active = real_t && z0 + tc < nz;
     double rho_t = 0, jz_t = 0, jr_t = 0, nuf_t = 0;
+    double nu[lbm::kQ];  // the tile node's nu, kept to step 4 (a reload there misses L2)
     const unsigned xt = 8u * (unsigned)(mirror_even(rt, nr) * nz + zt);
     if (has_tile) {
         double fl[lbm::kQ];
@@ -277,7 +278,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
         // a ghost row (last tile of a short lattice) gathers at the last
         // row and discards the values: no branch around the loads
         const int rg = real_t ? rt : nr - 1;
-        double nu[lbm::kQ];
 #pragma unroll
         for (int i = 0; i < lbm::kQ; ++i) {
             const double v = gather_nu(a, bf, i, zt, rg);
@@ -532,11 +532,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
             drur = a3 * kI36;
         }
         __builtin_amdgcn_sched_barrier(0);
-        // nu again (from L2: step 1 gathered the same values), rather than
-        // held in registers across three barriers
-        double nu[lbm::kQ];
-#pragma unroll
-        for (int i = 0; i < lbm::kQ; ++i) nu[i] = gather_nu(a, bf, i, zt, rt);
         // tau-bar of BGK: sum_i nu_i (f_i - f^eq_i) / tau^2, its population
         // part summed in step 1 (the populations are not kept)
         double nfeq = 0.0;
