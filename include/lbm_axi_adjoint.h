@@ -29,12 +29,12 @@ extern "C" {
 #endif
 
 /* Bytes of FP64 scratch lbm_axi_adjoint_step and lbm_axi_adjoint_run need
- * for an nz x nr grid: four node fields that pass between the two kernels of
- * a reverse step (the part of the density adjoint that goes through the psi
- * stencils, F-bar scaled by -G psi in two components, exp(-rho/rho0)) and
- * two sums per tile for dL/dG and dL/dtau (32 B per node and 32 B per tile
- * of 16 x 16 nodes, or of 16 x 8 on grids of fewer than 262 144 nodes); 0 if
- * the size is invalid.  The adjoint needs nz >= 4 and nr >= 6
+ * for an nz x nr grid: the node fields that pass from one reverse kernel to
+ * the next (the part of the density adjoint that goes through the psi
+ * stencils; two sets of F-bar scaled by -G psi in two components and of
+ * exp(-rho/rho0)) and two sums per tile for dL/dG and dL/dtau (56 B per node
+ * and 32 B per tile of 16 x 16 nodes, or of 16 x 8 on grids of fewer than
+ * 262 144 nodes); 0 if the size is invalid.  The adjoint needs nz >= 4 and nr >= 6
  * (the psi window mirrors up to six rows at the axis and the wall) and
  * nz (nr + 12) < 2^31; other sizes give 0 here and LBM_AXI_EINVAL from the
  * calls. */
@@ -55,7 +55,7 @@ int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const doubl
  * array of LBM_AXI_NOALLOC_SCRATCH_BYTES (24 MiB) that the library holds on
  * every GPU it runs on until the process ends, instead of a workspace
  * argument.  Grids whose lbm_axi_adjoint_workspace_bytes exceed it (beyond
- * about 780 000 nodes, e.g. 1024 x 768; the 256 x 128 drop needs 1.1 MB) return
+ * about 449 000 nodes, e.g. 768 x 512 fits; the 256 x 128 drop needs 1.9 MB) return
  * LBM_AXI_ENOMEM with a message.  The caller passes inputs and outputs as
  * for lbm_axi_adjoint_step.  Allocates nothing (no hipMalloc, hipFree or
  * allocating library call); the first call on a device looks the array's

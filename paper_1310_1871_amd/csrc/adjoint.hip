@@ -73,6 +73,12 @@ struct TileArgs {
     double* pr;                // [n] P_r = -G psi F-bar_r
     double* ex;                // [n] E = exp(-rho / rho0)
     double* rhob_out;          // [n] B: rho-bar_B of lam^t
+    // the small-lattice kernel A: P and E of the previous reverse step (that
+    // of lam^{t+1}), from which it forms rho-bar_B of lam^{t+1} itself; NULL:
+    // lam_p is all of lam^{t+1}
+    const double* pz_in;
+    const double* pr_in;
+    const double* ex_in;
     double* part;              // [tiles][2] dL/dG, dL/dtau of each tile
     int accumulate;            // 1: add to part (the running sums of a run), 0: overwrite
 };
@@ -194,6 +200,14 @@ __device__ __forceinline__ int push_target(int i, int z, int r, int nz, int nr, 
     return tr * nz + tz;
 }
 
+// the same target as an offset (dc, dr) from the source node (z, r)
+__device__ __forceinline__ void push_offset(int i, int r, int nr, int wall, int& dc, int& dr) {
+    const int ty = r + lbm::cr(i);
+    const bool below = ty < 0, above = ty >= nr;
+    dc = (above && wall == 0) ? 0 : lbm::cz(i);
+    dr = below ? -r : (above ? (wall == 0 ? 0 : nr - 1 - r) : lbm::cr(i));
+}
+
 // the buffers kernel A reads and writes
 struct Bufs {
     Rsrc f, lam, rhob, out, pz, pr, ex;
@@ -226,14 +240,159 @@ __device__ __forceinline__ double gather_nu(const TileArgs& a, const Bufs& b, in
 // a power of two is a full IEEE division sequence)
 constexpr double kI36 = 1.0 / 36.0, kI12 = 1.0 / 12.0, kI18 = 1.0 / 18.0;
 
+// x y rounded on its own, never contracted into an addition that uses it
+__device__ __forceinline__ double mul_rounded(double x, double y) {
+#pragma clang fp contract(off)
+    return x * y;
+}
+
+// ---- psi-bar through the psi stencils of other nodes --------------------
+//
+// On a region of RZ x RH nodes whose first node is (z0, r0) (z0 may be
+// negative, z being periodic; r0 may be negative, rows off the lattice hold
+// nothing), from P = -G psi F-bar on the region and a ring around it:
+// psi-bar_B, the sum of the transposed SC neighbour sum, the transposed
+// d_rr = d_r of d_r psi with the direct d_r psi of F^sym_r, and the
+// transposed d_zr (1D d_z of the 1D d_r psi), folded from the ghost rows
+// onto the rows they mirror.  Kernel B evaluates it on its tile; kernel A
+// of the small-lattice path on its tile and a 3-node ring, for the next
+// step's gathers.  Both use these functions, so their values agree bit for
+// bit.
+template <int RZ, int RH>
+struct PsiBar {
+    static constexpr int QW = RZ + 8, QH = RH + 16;  // P: columns [-4, RZ + 4), rows [-8, RH + 8)
+    static constexpr int GW = RZ + 4, GH = RH + 12;  // adjoint of d_r psi: columns [-2, RZ + 2), rows [-6, RH + 6)
+    static constexpr int HH = RH + 12;               // adjoint of the 1D d_r psi: the region's columns, rows [-6, RH + 6)
+    double pz[QH][QW], pr[QH][QW];
+    double qr[QH][QW];  // d_rr-bar = P_r / (18 r), 0 off the lattice
+    double g[GH][GW];
+    double h[HH][RZ];
+};
+
+// step 1 (every thread): P on the window into LDS.  A thread issues all its
+// loads before it uses any (rows off the lattice read past the buffer's
+// end, which gives 0, and are zeroed again).
+template <int RZ, int RH, int NT, bool kAxi>
+__device__ __forceinline__ void psibar_load(PsiBar<RZ, RH>& sb, const double* pz, const double* pr, size_t nb, int z0,
+                                            int r0, int nz, int nr, int t) {
+    using S = PsiBar<RZ, RH>;
+    const Rsrc rpz = rsrc_of(pz, nb), rpr = rsrc_of(pr, nb);
+    constexpr int KQ = (S::QH * S::QW + NT - 1) / NT;
+    double vz[KQ], vr[KQ];
+#pragma unroll
+    for (int j = 0; j < KQ; ++j) {
+        const int k = t + j * NT, y = k / S::QW - 8, c = k % S::QW - 4;
+        const unsigned x = 8u * (unsigned)((r0 + y) * nz + wrap_col(z0 + c, nz));
+        vz[j] = ld(rpz, x, 0u);
+        vr[j] = ld(rpr, x, 0u);
+    }
+#pragma unroll
+    for (int j = 0; j < KQ; ++j) {
+        const int k = t + j * NT, y = k / S::QW - 8, c = k % S::QW - 4;
+        if (k < S::QH * S::QW) {
+            const bool re = r0 + y >= 0 && r0 + y < nr;
+            const double p = re ? vr[j] : 0.0;
+            sb.pz[y + 8][c + 4] = re ? vz[j] : 0.0;
+            sb.pr[y + 8][c + 4] = p;
+            if (kAxi) sb.qr[y + 8][c + 4] = p * kI18 * (1.0 / (r0 + y + 0.5));
+        }
+    }
+}
+
+// step 2 (every thread, after a barrier; axisymmetric terms only): the
+// adjoint of d_r psi on the extended rows -2 .. nr + 1 that d_rr reads (the
+// transposed isotropic stencil of d_rr-bar, plus the direct use of d_r psi
+// on a real row, d_r-bar = -P_r / (18 r^2)), and the adjoint of the 1D d_r
+// psi on real rows (the transposed z difference of d_zr-bar = P_z / (18 r))
+template <int RZ, int RH, int NT>
+__device__ __forceinline__ void psibar_stencils(PsiBar<RZ, RH>& sb, int r0, int nr, int t) {
+    using S = PsiBar<RZ, RH>;
+    for (int k = t; k < S::GH * S::GW; k += NT) {
+        const int y = k / S::GW - 6, c = k % S::GW - 2, yy = r0 + y;
+        double v = 0.0;
+        if (yy >= -2 && yy < nr + 2) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 1; i < lbm::kQ; ++i) {
+                const int cr = lbm::cr(i), cz = lbm::cz(i);
+                if (cr == 0) continue;
+                s += 8.0 * cr * sb.qr[y - cr + 8][c - cz + 4];
+                s -= cr * sb.qr[y - 2 * cr + 8][c - 2 * cz + 4];
+            }
+            v = s * kI36;
+            if (yy >= 0 && yy < nr) v += -sb.qr[y + 8][c + 4] * (1.0 / (yy + 0.5));
+        }
+        sb.g[y + 6][c + 2] = v;
+    }
+    for (int k = t; k < S::HH * RZ; k += NT) {
+        const int y = k / RZ - 6, c = k % RZ, yy = r0 + y;
+        double v = 0.0;
+        if (yy >= 0 && yy < nr) {
+            auto b = [&](int cc) { return sb.pz[y + 8][cc + 4]; };
+            // forward: out(z) = (-in(z+2) + 8 in(z+1) - 8 in(z-1) + in(z-2)) / 12
+            v = (-b(c - 2) + 8.0 * b(c - 1) - 8.0 * b(c + 1) + b(c + 2)) * (kI12 * kI18) * (1.0 / (yy + 0.5));
+        }
+        sb.h[y + 6][c] = v;
+    }
+}
+
+// step 3 (after a barrier): psi-bar_B at region node (c, y), a real row
+template <int RZ, int RH, bool kAxi>
+__device__ __forceinline__ double psibar_at(const PsiBar<RZ, RH>& sb, int c, int y, int r0, int nr) {
+    auto real = [&](int yy) { return r0 + yy >= 0 && r0 + yy < nr; };
+    // psi-bar of extended row e at this column (before folding)
+    auto ext = [&](int e) {
+        const int y = e - r0;
+        double s = 0.0;
+        if (kAxi) {
+            // d_r psi = isotropic d_r of the extended psi; only the rows
+            // -2 .. nr + 1 carry an adjoint
+#pragma unroll
+            for (int i = 1; i < lbm::kQ; ++i) {
+                const int cr = lbm::cr(i), cz = lbm::cz(i);
+                if (cr == 0) continue;
+                const int y1 = y - cr, y2 = y - 2 * cr;
+                if (r0 + y1 >= -2 && r0 + y1 < nr + 2) s += (8.0 * cr / 36.0) * sb.g[y1 + 6][c - cz + 2];
+                if (r0 + y2 >= -2 && r0 + y2 < nr + 2) s -= (cr / 36.0) * sb.g[y2 + 6][c - 2 * cz + 2];
+            }
+            // 1D d_r psi on real rows: (-p(y+2) + 8 p(y+1) - 8 p(y-1) + p(y-2)) / 12
+            const int ys[4] = {y - 2, y - 1, y + 1, y + 2};
+            const double cf[4] = {-1.0, 8.0, -8.0, 1.0};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (real(ys[k])) s += (cf[k] / 12.0) * sb.h[ys[k] + 6][c];
+        }
+        // Shan–Chen force: F^SC(x) = -G psi(x) sum_i W_i psi(x + c_i) c_i
+#pragma unroll
+        for (int i = 1; i < lbm::kQ; ++i) {
+            const int ysrc = y - lbm::cr(i), cs = c - lbm::cz(i);
+            if (real(ysrc))
+                s += lbm::weight(i) * (lbm::cz(i) * sb.pz[ysrc + 8][cs + 4] + lbm::cr(i) * sb.pr[ysrc + 8][cs + 4]);
+        }
+        return s;
+    };
+    const int r = r0 + y;
+    double psib = ext(r);
+    if (r <= 3) psib += ext(-1 - r);            // axis images (rows -4 .. -1)
+    if (r >= nr - 4) psib += ext(2 * nr - 1 - r);  // wall images (rows nr .. nr + 3)
+    return psib;
+}
+
 // Kernel A.  kAxi: the axisymmetric terms (source, F^{sym}, velocity
 // stencils) on; off, the plain 2D Shan–Chen step.
+// kFused (small lattices): rho-bar_B of lam^{t+1} is not read but formed
+// here, from the previous reverse step's P and E, on the tile and a 3-node
+// ring (the gathers' targets), so that a run needs no kernel B between its
+// steps; the gathered nu then completes in a step 3b, after the velocities.
 // The 256-thread instance is held to three waves per SIMD (168 VGPRs), so
 // that three workgroups share a CU and their loads overlap each other's
 // arithmetic.
-template <int TZ, int TR, bool kAxi, int NT>
+template <int TZ, int TR, bool kAxi, int NT, bool kFused>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 3 : 1))) void adj_tile_a(const TileArgs a) {
     using T = Tile<TZ, TR, NT>;
+    // kFused: the region of tile and 3-node ring
+    constexpr int RZ = kFused ? TZ + 6 : 1, RH = kFused ? TR + 6 : 1;
+    static_assert(!kFused || RZ * RH <= NT, "one region node per thread");
     __shared__ double s_psi[T::PH][T::PW];
     __shared__ double s_dr[T::DH][T::DW];
     __shared__ double s_d1[T::EH][T::EW];
@@ -244,6 +403,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
     __shared__ double s_hz[T::UH][T::UW];
     __shared__ double s_hr[T::UH][T::UW];
     __shared__ double s_red[2][NT / 64];
+    __shared__ PsiBar<RZ, RH> sb;  // kFused: psi-bar_B of lam^{t+1} on the region
+    __shared__ double s_rb[RH][RZ];  // kFused: rho-bar_B of lam^{t+1} on the region
 
     const int tile = block_tile(blockIdx.x, gridDim.x, a.tiles_z);
     const int z0 = (tile % a.tiles_z) * TZ, r0 = (tile / a.tiles_z) * TR;
@@ -253,6 +414,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
     const double G = a.G, tau = a.tau, rho0 = a.rho0;
     const double mu_f = (tau - 0.5) / 3.0, inv_rho0 = 1.0 / rho0;
     const Bufs bf = bufs_of(a);
+    const bool has_p = kFused && a.pz_in != nullptr;
 
     // ---- 1. loads: psi on the window; nu, and the velocity-stencil
     // adjoints, within 2 of the tile
@@ -270,6 +432,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
     const bool active = real_t && z0 + tc < nz;
     double rho_t = 0, jz_t = 0, jr_t = 0, nuf_t = 0;
     double nu[lbm::kQ];  // the tile node's nu, kept to step 4 (a reload there misses L2)
+    double fk[lbm::kQ];  // kFused: the tile node's populations, kept to step 3b
     const unsigned xt = 8u * (unsigned)(mirror_even(rt, nr) * nz + zt);
     if (has_tile) {
         double fl[lbm::kQ];
@@ -288,16 +451,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
             rho_t += fl[i];
             jz_t += lbm::cz(i) * fl[i];
             jr_t += lbm::cr(i) * fl[i];
-            nuf_t += nu[i] * fl[i];  // sum_i nu_i f_i, the populations' part of tau-bar
+            if (!kFused) nuf_t += nu[i] * fl[i];  // sum_i nu_i f_i, the populations' part of tau-bar
+            if (kFused) fk[i] = fl[i];
         }
         s_psi[ty + 6][tc + 6] = psi_of(rho_t);
-        double hz = 0, hr = 0;
+        if (!kFused) {
+            double hz = 0, hr = 0;
 #pragma unroll
-        for (int i = 0; i < lbm::kQ; ++i) {
-            hz += 3.0 * lbm::weight(i) * lbm::cz(i) * nu[i];
-            hr += 3.0 * lbm::weight(i) * lbm::cr(i) * nu[i];
+            for (int i = 0; i < lbm::kQ; ++i) {
+                hz += 3.0 * lbm::weight(i) * lbm::cz(i) * nu[i];
+                hr += 3.0 * lbm::weight(i) * lbm::cr(i) * nu[i];
+            }
+            store_h(tc, ty, real_t, rho_t, hz, hr);
         }
-        store_h(tc, ty, real_t, rho_t, hz, hr);
     }
     // the tile node's loads are consumed before the ring's are issued (all of
     // them at once do not fit the registers of the large-lattice instance)
@@ -305,6 +471,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
     // ring nodes; the first slot's node, when within 2 of the tile, keeps
     // rho and j for its velocity
     double rho_q = 0, jz_q = 0, jr_q = 0;
+    double vq[lbm::kQ - 1];  // kFused: the gathered lam_p of that node, kept to step 3b
     int cq = 0, yq = 0;
     const bool ring2 = t < T::R2N;
 #pragma unroll
@@ -342,13 +509,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
 #pragma unroll
                     for (int i = 1; i < lbm::kQ; ++i) {
                         const double v = gather_nu(a, bf, i, z, yg);
+                        if (kFused) vq[i - 1] = v;
                         hz += 3.0 * lbm::weight(i) * lbm::cz(i) * v;
                         hr += 3.0 * lbm::weight(i) * lbm::cr(i) * v;
                     }
-                    store_h(c, y, real, rho, hz, hr);
+                    if (!kFused) store_h(c, y, real, rho, hz, hr);
                 }
             }
         }
+    }
+    // kFused: P of lam^{t+1} on the region's window, and E at the thread's
+    // region node
+    double e_q = 0.0;
+    if (kFused && has_p) {
+        psibar_load<RZ, RH, NT, kAxi>(sb, a.pz_in, a.pr_in, n * sizeof(double), z0 - 3, r0 - 3, nz, nr, t);
+        const int c = t % RZ - 3, y = t / RZ - 3;
+        e_q = ld(rsrc_of(a.ex_in, n * sizeof(double)), 8u * (unsigned)((r0 + y) * nz + wrap_col(z0 + c, nz)), 0u);
     }
     __syncthreads();
 
@@ -371,6 +547,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
             const int y = k / T::EW - 2, c = k % T::EW - 4;
             s_d1[y + 2][c + 4] = (-P(c, y + 2) + 8.0 * P(c, y + 1) - 8.0 * P(c, y - 1) + P(c, y - 2)) * kI12;
         }
+        if (kFused && has_p) psibar_stencils<RZ, RH, NT>(sb, r0 - 3, nr, t);
         __syncthreads();
     }
 
@@ -447,21 +624,68 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
             s_ur[ty + 2][tc + 2] = 0.0;
         }
     }
-    if (kAxi) {
-        if (ring2) {
-            bool use;
-            double sgn;
-            const int ys = source_row(yq, use, sgn);
-            double uz = 0.0, ur = 0.0;
-            if (use) {
-                const Fwd o = forward_at(cq, ys, rho_q, jz_q, jr_q);
-                uz = o.uz;
-                ur = sgn * o.ur;
-            }
-            s_uz[yq + 2][cq + 2] = uz;
-            s_ur[yq + 2][cq + 2] = ur;
+    if (kAxi && ring2) {
+        bool use;
+        double sgn;
+        const int ys = source_row(yq, use, sgn);
+        double uz = 0.0, ur = 0.0;
+        if (use) {
+            const Fwd o = forward_at(cq, ys, rho_q, jz_q, jr_q);
+            uz = o.uz;
+            ur = sgn * o.ur;
         }
-        __syncthreads();
+        s_uz[yq + 2][cq + 2] = uz;
+        s_ur[yq + 2][cq + 2] = ur;
+    }
+    // kFused: rho-bar_B of lam^{t+1} at the thread's region node (0 on rows
+    // off the lattice, which no gather reads)
+    if (kFused && t < RZ * RH) {
+        const int c = t % RZ - 3, y = t / RZ - 3, yy = r0 + y;
+        double rb = 0.0;
+        if (has_p && yy >= 0 && yy < nr) rb = mul_rounded(psibar_at<RZ, RH, kAxi>(sb, c + 3, y + 3, r0 - 3, nr), e_q);
+        s_rb[y + 3][c + 3] = rb;
+    }
+    if (kAxi || kFused) __syncthreads();
+
+    // ---- 3b (kFused). nu = lam_p + rho-bar_B at the gathers' targets, then
+    // the velocity-stencil adjoints and the populations' part of tau-bar, in
+    // the order of step 1 of the unfused kernel
+    if (kFused) {
+        if (has_tile) {
+            if (real_t) {
+#pragma unroll
+                for (int i = 0; i < lbm::kQ; ++i) {
+                    int dc, dr;
+                    push_offset(i, rt, nr, a.wall, dc, dr);
+                    nu[i] = nu[i] + s_rb[ty + dr + 3][tc + dc + 3];
+                }
+            }
+            double hz = 0, hr = 0;
+#pragma unroll
+            for (int i = 0; i < lbm::kQ; ++i) {
+                nuf_t += nu[i] * fk[i];
+                hz += 3.0 * lbm::weight(i) * lbm::cz(i) * nu[i];
+                hr += 3.0 * lbm::weight(i) * lbm::cr(i) * nu[i];
+            }
+            store_h(tc, ty, real_t, rho_t, hz, hr);
+        }
+        if (kAxi && ring2) {
+            const int yy = r0 + yq;
+            const bool real = yy >= 0 && yy < nr;
+            double hz = 0, hr = 0;
+            if (real) {
+#pragma unroll
+                for (int i = 1; i < lbm::kQ; ++i) {
+                    int dc, dr;
+                    push_offset(i, yy, nr, a.wall, dc, dr);
+                    const double v = vq[i - 1] + s_rb[yq + dr + 3][cq + dc + 3];
+                    hz += 3.0 * lbm::weight(i) * lbm::cz(i) * v;
+                    hr += 3.0 * lbm::weight(i) * lbm::cr(i) * v;
+                }
+            }
+            store_h(cq, yq, real, rho_q, hz, hr);
+        }
+        if (kAxi) __syncthreads();
     }
 
     // ---- 4. the tile node: collision, equilibrium and source reversed,
@@ -645,135 +869,26 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 
     }
 }
 
-// x y rounded on its own, never contracted into an addition that uses it
-__device__ __forceinline__ double mul_rounded(double x, double y) {
-#pragma clang fp contract(off)
-    return x * y;
-}
-
 // Kernel B: psi-bar from the psi stencils of the other nodes, through P.
 // kFinal: add rho-bar_B to lam_out in every direction (lam_out then holds
 // lam^t); otherwise write rho-bar_B.
 template <int TZ, int TR, bool kAxi, bool kFinal, int NT>
 __global__ __launch_bounds__(NT) void adj_tile_b(const TileArgs a) {
-    constexpr int QW = TZ + 8, QH = TR + 16;  // P: columns [-4, TZ + 4), rows [-8, TR + 8)
-    constexpr int GW = TZ + 4, GH = TR + 12;  // adjoint of d_r psi: columns [-2, TZ + 2), rows [-6, TR + 6)
-    constexpr int HH = TR + 12;               // adjoint of the 1D d_r psi: the tile's columns, rows [-6, TR + 6)
-    __shared__ double s_pz[QH][QW], s_pr[QH][QW];
-    // d_rr-bar = P_r / (18 r) on the same window (0 off the lattice)
-    __shared__ double s_qr[kAxi ? QH : 1][kAxi ? QW : 1];
-    __shared__ double s_g[kAxi ? GH : 1][kAxi ? GW : 1];
-    __shared__ double s_h[kAxi ? HH : 1][kAxi ? TZ : 1];
-    __shared__ double s_ir[QH];  // 1 / r of the window rows
-
+    __shared__ PsiBar<TZ, TR> sb;
     const int tile = block_tile(blockIdx.x, gridDim.x, a.tiles_z);
     const int z0 = (tile % a.tiles_z) * TZ, r0 = (tile / a.tiles_z) * TR;
     const int nz = a.nz, nr = a.nr;
-    const size_t n = (size_t)a.n;
     const int t = threadIdx.x, tc = t % TZ, ty = t / TZ;
-    auto real = [&](int y) { return r0 + y >= 0 && r0 + y < nr; };
-
-    // P on the window: every load issued before the first is used (rows
-    // outside the lattice read past the buffer's end, which gives 0, and are
-    // zeroed again below)
     const size_t nb = (size_t)a.n * sizeof(double);
-    const Rsrc rpz = rsrc_of(a.pz, nb), rpr = rsrc_of(a.pr, nb);
-    constexpr int KQ = (QH * QW + NT - 1) / NT;
-    double vz[KQ], vr[KQ];
-#pragma unroll
-    for (int j = 0; j < KQ; ++j) {
-        const int k = t + j * NT, y = k / QW - 8, c = k % QW - 4;
-        const unsigned x = 8u * (unsigned)((r0 + y) * nz + wrap_col(z0 + c, nz));
-        vz[j] = ld(rpz, x, 0u);
-        vr[j] = ld(rpr, x, 0u);
-    }
-    if (t < QH) s_ir[t] = 1.0 / (r0 + t - 8 + 0.5);
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < KQ; ++j) {
-        const int k = t + j * NT, y = k / QW - 8, c = k % QW - 4;
-        if (k < QH * QW) {
-            const double pr = real(y) ? vr[j] : 0.0;
-            s_pz[y + 8][c + 4] = real(y) ? vz[j] : 0.0;
-            s_pr[y + 8][c + 4] = pr;
-            if (kAxi) s_qr[y + 8][c + 4] = pr * kI18 * s_ir[y + 8];
-        }
-    }
+    psibar_load<TZ, TR, NT, kAxi>(sb, a.pz, a.pr, nb, z0, r0, nz, nr, t);
     __syncthreads();
     if (kAxi) {
-        // adjoint of d_r psi on the extended rows -2 .. nr + 1 that d_rr
-        // reads: the transposed isotropic stencil of d_rr-bar = P_r / (18 r),
-        // plus the direct use of d_r psi on a real row, d_r-bar =
-        // -P_r / (18 r^2)
-        auto drrb = [&](int y, int c) { return s_qr[y + 8][c + 4]; };
-        for (int k = t; k < GH * GW; k += NT) {
-            const int y = k / GW - 6, c = k % GW - 2, yy = r0 + y;
-            double v = 0.0;
-            if (yy >= -2 && yy < nr + 2) {
-                double s = 0.0;
-#pragma unroll
-                for (int i = 1; i < lbm::kQ; ++i) {
-                    const int cr = lbm::cr(i), cz = lbm::cz(i);
-                    if (cr == 0) continue;
-                    s += 8.0 * cr * drrb(y - cr, c - cz);
-                    s -= cr * drrb(y - 2 * cr, c - 2 * cz);
-                }
-                v = s * kI36;
-                if (real(y)) v += -s_qr[y + 8][c + 4] * s_ir[y + 8];
-            }
-            s_g[y + 6][c + 2] = v;
-        }
-        // adjoint of the 1D d_r psi on real rows: the transposed z
-        // difference of d_zr-bar = P_z / (18 r)
-        for (int k = t; k < HH * TZ; k += NT) {
-            const int y = k / TZ - 6, c = k % TZ;
-            double v = 0.0;
-            if (real(y)) {
-                auto b = [&](int cc) { return s_pz[y + 8][cc + 4]; };
-                // forward: out(z) = (-in(z+2) + 8 in(z+1) - 8 in(z-1) + in(z-2)) / 12,
-                // here on d_zr-bar = P_z / (18 r)
-                v = (-b(c - 2) + 8.0 * b(c - 1) - 8.0 * b(c + 1) + b(c + 2)) * (kI12 * kI18) * s_ir[y + 8];
-            }
-            s_h[y + 6][c] = v;
-        }
+        psibar_stencils<TZ, TR, NT>(sb, r0, nr, t);
         __syncthreads();
     }
     const int r = r0 + ty;
     if (t >= TZ * TR || r >= nr || z0 + tc >= nz) return;
-    // psi-bar of extended row e at this column (before folding)
-    auto ext = [&](int e) {
-        const int y = e - r0;
-        double s = 0.0;
-        if (kAxi) {
-            // d_r psi = isotropic d_r of the extended psi; only the rows
-            // -2 .. nr + 1 carry an adjoint
-#pragma unroll
-            for (int i = 1; i < lbm::kQ; ++i) {
-                const int cr = lbm::cr(i), cz = lbm::cz(i);
-                if (cr == 0) continue;
-                const int y1 = y - cr, y2 = y - 2 * cr;
-                if (r0 + y1 >= -2 && r0 + y1 < nr + 2) s += (8.0 * cr / 36.0) * s_g[y1 + 6][tc - cz + 2];
-                if (r0 + y2 >= -2 && r0 + y2 < nr + 2) s -= (cr / 36.0) * s_g[y2 + 6][tc - 2 * cz + 2];
-            }
-            // 1D d_r psi on real rows: (-p(y+2) + 8 p(y+1) - 8 p(y-1) + p(y-2)) / 12
-            const int ys[4] = {y - 2, y - 1, y + 1, y + 2};
-            const double cf[4] = {-1.0, 8.0, -8.0, 1.0};
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (real(ys[k])) s += (cf[k] / 12.0) * s_h[ys[k] + 6][tc];
-        }
-        // Shan–Chen force: F^SC(x) = -G psi(x) sum_i W_i psi(x + c_i) c_i
-#pragma unroll
-        for (int i = 1; i < lbm::kQ; ++i) {
-            const int ysrc = y - lbm::cr(i), c = tc - lbm::cz(i);
-            if (real(ysrc))
-                s += lbm::weight(i) * (lbm::cz(i) * s_pz[ysrc + 8][c + 4] + lbm::cr(i) * s_pr[ysrc + 8][c + 4]);
-        }
-        return s;
-    };
-    double psib = ext(r);
-    if (r <= 3) psib += ext(-1 - r);            // axis images (rows -4 .. -1)
-    if (r >= nr - 4) psib += ext(2 * nr - 1 - r);  // wall images (rows nr .. nr + 3)
+    const double psib = psibar_at<TZ, TR, kAxi>(sb, tc, ty, r0, nr);
     const unsigned x = 8u * (unsigned)(r * nz + z0 + tc);
     // a rounded product, never fused into the additions below: a run adds
     // the stored rho-bar_B in the next step's gathers, and its lam must equal
@@ -925,16 +1040,28 @@ long long tiles_of(int nz, int nr) {
     return (long long)((nz + s.tz - 1) / s.tz) * ((nr + s.tr - 1) / s.tr);
 }
 
-// workspace (doubles): rho-bar_B [n], P_z [n], P_r [n], E [n], the tiles'
-// partial sums of one step [tiles][2], the running sums of a run [tiles][2]
+// workspace (doubles): rho-bar_B [n]; two sets of P_z, P_r, E [n] each
+// (the fused kernel A reads the previous step's set while it writes its
+// own); the tiles' partial sums of one step [tiles][2]; the running sums of
+// a run [tiles][2]
+constexpr size_t kWsFields = 7;
 struct Layout {
-    double *rhob, *pz, *pr, *ex, *part, *run;
+    double *rhob, *pz[2], *pr[2], *ex[2], *part, *run;
 };
 Layout layout_of(void* ws, int nz, int nr) {
     const size_t n = (size_t)nz * nr;
     const size_t nt = (size_t)tiles_of(nz, nr);
     double* b = static_cast<double*>(ws);
-    return Layout{b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, b + 4 * n + 2 * nt};
+    Layout w;
+    w.rhob = b;
+    for (int k = 0; k < 2; ++k) {
+        w.pz[k] = b + (1 + 3 * k) * n;
+        w.pr[k] = b + (2 + 3 * k) * n;
+        w.ex[k] = b + (3 + 3 * k) * n;
+    }
+    w.part = b + kWsFields * n;
+    w.run = w.part + 2 * nt;
+    return w;
 }
 
 TileArgs tile_args(const lbm_axi_params* p, const Layout& w) {
@@ -948,18 +1075,21 @@ TileArgs tile_args(const lbm_axi_params* p, const Layout& w) {
     a.gz = p->gz;
     a.wall = p->wall;
     a.tiles_z = (p->nz + shape_of(p->nz, p->nr).tz - 1) / shape_of(p->nz, p->nr).tz;
-    a.pz = w.pz;
-    a.pr = w.pr;
-    a.ex = w.ex;
+    a.pz = w.pz[0];
+    a.pr = w.pr[0];
+    a.ex = w.ex[0];
     return a;
 }
 
-template <int TZ, int TR, int NT>
+// the small-lattice path fuses kernel B into the next step's kernel A
+bool fused_path(int nz, int nr) { return shape_of(nz, nr).tr != kLargeTR; }
+
+template <int TZ, int TR, int NT, bool kFused>
 void launch_a_t(const TileArgs& a, bool axi, int tiles, hipStream_t s) {
     if (axi)
-        hipLaunchKernelGGL((adj_tile_a<TZ, TR, true, NT>), dim3(tiles), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((adj_tile_a<TZ, TR, true, NT, kFused>), dim3(tiles), dim3(NT), 0, s, a);
     else
-        hipLaunchKernelGGL((adj_tile_a<TZ, TR, false, NT>), dim3(tiles), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((adj_tile_a<TZ, TR, false, NT, kFused>), dim3(tiles), dim3(NT), 0, s, a);
 }
 template <int TZ, int TR, int NT>
 void launch_b_t(const TileArgs& a, bool axi, bool final, int tiles, hipStream_t s) {
@@ -969,18 +1099,21 @@ void launch_b_t(const TileArgs& a, bool axi, bool final, int tiles, hipStream_t 
     if (!axi && final) hipLaunchKernelGGL((adj_tile_b<TZ, TR, false, true, NT>), g, b, 0, s, a);
     if (!axi && !final) hipLaunchKernelGGL((adj_tile_b<TZ, TR, false, false, NT>), g, b, 0, s, a);
 }
-
-// one reverse step: kernel A, then kernel B (final: lam^t complete in
-// a.lam_out; otherwise its rho-bar_B part in a.rhob_out)
-void launch_reverse_step(const TileArgs& a, bool axi, bool final, hipStream_t s) {
+void launch_a(const TileArgs& a, bool axi, hipStream_t s) {
     const int tiles = (int)tiles_of(a.nz, a.nr);
-    if (shape_of(a.nz, a.nr).tr == kLargeTR) {
-        launch_a_t<kLargeTZ, kLargeTR, kLargeNT>(a, axi, tiles, s);
-        launch_b_t<kLargeTZ, kLargeTR, kLargeNT>(a, axi, final, tiles, s);
-    } else {
-        launch_a_t<kSmallTZ, kSmallTR, kSmallNT>(a, axi, tiles, s);
+    if (fused_path(a.nz, a.nr))
+        launch_a_t<kSmallTZ, kSmallTR, kSmallNT, true>(a, axi, tiles, s);
+    else
+        launch_a_t<kLargeTZ, kLargeTR, kLargeNT, false>(a, axi, tiles, s);
+}
+// final: lam^t complete in a.lam_out; otherwise its rho-bar_B part in
+// a.rhob_out
+void launch_b(const TileArgs& a, bool axi, bool final, hipStream_t s) {
+    const int tiles = (int)tiles_of(a.nz, a.nr);
+    if (fused_path(a.nz, a.nr))
         launch_b_t<kSmallTZ, kSmallTR, kSmallNT>(a, axi, final, tiles, s);
-    }
+    else
+        launch_b_t<kLargeTZ, kLargeTR, kLargeNT>(a, axi, final, tiles, s);
 }
 
 int check_adjoint(const lbm_axi_params* p, size_t ws_bytes) {
@@ -1006,7 +1139,10 @@ int reverse_step(const lbm_axi_params* p, const double* d_f, const double* d_lam
     a.lam_out = d_lam;
     a.part = w.part;
     a.accumulate = 0;
-    launch_reverse_step(a, p->axisym != 0, true, s);
+    // kernel A (which, fused, finds no previous step's P: pz_in NULL), then
+    // kernel B completing lam^t in place
+    launch_a(a, p->axisym != 0, s);
+    launch_b(a, p->axisym != 0, true, s);
     if (d_grad_acc)
         hipLaunchKernelGGL(rev_reduce, dim3(1), dim3(256), 0, s, w.part, (int)tiles_of(p->nz, p->nr), d_grad_acc);
     const hipError_t e = hipGetLastError();
@@ -1062,7 +1198,7 @@ int lbm_axi_adjoint_step_noalloc(const lbm_axi_params* p, const double* d_f, con
 size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr) {
     if (nz < 4 || nr < 6 || (long long)nz * (nr + 12) > INT_MAX) return 0;
     const size_t n = (size_t)nz * nr;
-    return (4 * n + 4 * (size_t)tiles_of(nz, nr)) * sizeof(double);
+    return (kWsFields * n + 4 * (size_t)tiles_of(nz, nr)) * sizeof(double);
 }
 
 int lbm_axi_adjoint_step(const lbm_axi_params* p, const double* d_f, const double* d_lam_next, double* d_lam,
@@ -1087,16 +1223,34 @@ int lbm_axi_adjoint_run(const lbm_axi_params* p, const double* d_states, int32_t
     hipLaunchKernelGGL(zero_kernel, dim3(nblk(2 * (long long)tiles)), dim3(256), 0, s, w.run, 2 * (long long)tiles);
     double* cur = d_lam;  // lam^{t0+j+1} before step j: all of it (j = k - 1), or its lam_p part
     double* nxt = d_tmp;
+    const bool fused = fused_path(p->nz, p->nr), axi = p->axisym != 0;
     for (int32_t j = k - 1; j >= 0; --j) {
         TileArgs a = tile_args(p, w);
         a.f = d_states + (size_t)j * n9;
         a.lam_p = cur;
-        a.rhob_in = j == k - 1 ? nullptr : w.rhob;
         a.lam_out = nxt;
         a.rhob_out = w.rhob;
         a.part = w.run;
         a.accumulate = 1;
-        launch_reverse_step(a, p->axisym != 0, j == 0, s);
+        if (fused) {
+            // step j writes P and E to set j % 2 and forms the rest of
+            // lam^{j+1} from set (j + 1) % 2; a kernel B only completes lam
+            // after the last step
+            const int mine = j & 1, prev = 1 - mine;
+            a.pz = w.pz[mine];
+            a.pr = w.pr[mine];
+            a.ex = w.ex[mine];
+            a.rhob_in = nullptr;
+            a.pz_in = j == k - 1 ? nullptr : w.pz[prev];
+            a.pr_in = j == k - 1 ? nullptr : w.pr[prev];
+            a.ex_in = j == k - 1 ? nullptr : w.ex[prev];
+            launch_a(a, axi, s);
+            if (j == 0) launch_b(a, axi, true, s);
+        } else {
+            a.rhob_in = j == k - 1 ? nullptr : w.rhob;
+            launch_a(a, axi, s);
+            launch_b(a, axi, j == 0, s);
+        }
         double* t = cur;
         cur = nxt;
         nxt = t;

@@ -71,8 +71,8 @@ def _both(nz, nr, seed):
 
 
 def test_noalloc_adjoint_step_matches_workspace_step_twice():
-    _both(1024, 512, 31)  # first call on this GPU: looks the scratch up (16 x 16 tiles)
-    _both(64, 32, 32)     # a smaller grid in the same scratch (16 x 8 tiles)
+    _both(768, 512, 31)   # first call on this GPU: looks the scratch up (16 x 16 tiles)
+    _both(64, 32, 32)     # a smaller grid in the same scratch (16 x 8 tiles, the fused path)
 
 
 def test_noalloc_rejects_grids_beyond_the_scratch():
