@@ -33,8 +33,8 @@ extern "C" {
  * the next (the part of the density adjoint that goes through the psi
  * stencils; two sets of F-bar scaled by -G psi in two components and of
  * exp(-rho/rho0)) and two sums per tile for dL/dG and dL/dtau (56 B per node
- * and 32 B per tile of 16 x 16 nodes, or of 16 x 8 on grids of fewer than
- * 262 144 nodes); 0 if the size is invalid.  The adjoint needs nz >= 4 and nr >= 6
+ * and 32 B per tile of 16 x 16 nodes, or of 16 x 8 on grids with fewer than
+ * 192 of the larger tiles); 0 if the size is invalid.  The adjoint needs nz >= 4 and nr >= 6
  * (the psi window mirrors up to six rows at the axis and the wall) and
  * nz (nr + 12) < 2^31; other sizes give 0 here and LBM_AXI_EINVAL from the
  * calls. */

@@ -1017,23 +1017,29 @@ __global__ void zero_kernel(double* p, long long n) {
 }
 
 
-// Tile shapes.  Lattices of at least 262 144 nodes: 16 x 16 nodes and 256
-// threads, three workgroups per CU (held to 168 VGPRs); at 2048 x 1024 the
-// (forward + backward) / forward ratio was 5.40 with it, against 5.53 for
-// 32 x 8 tiles (256 threads), 5.93 for 32 x 16 (512 threads, one
+// Tile shapes.  Lattices with at least 192 tiles of 16 x 16 nodes (three
+// for every four CUs): 16 x 16 nodes and 256 threads, three workgroups per
+// CU (held to 168 VGPRs), kernels A and B per step.  At 2048 x 1024 the
+// (forward + backward) / forward ratio was 5.40 with this shape, against
+// 5.53 for 32 x 8 tiles (256 threads), 5.93 for 32 x 16 (512 threads, one
 // workgroup per CU at 148 VGPRs), 6.26 for 32 x 8 (512 threads) and 6.33
-// for 32 x 16 held to 128 VGPRs (spills).  Smaller lattices: 16 x 8 nodes
-// with 512 threads, where a kernel's time is one workgroup's chain of loads
-// and the spare threads share the window (at 256 x 128 the reverse step
-// took 19.5 us with 128 threads, 18.8 with 256, 18.6 with 512; 16 x 4 and
-// 8 x 8 tiles were no faster with 256 threads and 25% slower with 512).
+// for 32 x 16 held to 128 VGPRs (spills); at 512 x 256, 384 x 192 and
+// 362 x 181 it was 4.62, 4.39 and 4.35, against 6.82, 5.49 and 5.51 on the
+// small-lattice path.  Smaller lattices (the 256 x 128 adjoint workload has
+// 128 such tiles): 16 x 8 nodes with 512 threads, where a kernel's time is
+// one workgroup's chain of loads and the spare threads share the window,
+// and kernel B fused into the next step's kernel A (before the fusion, the
+// reverse step took 19.5 us with 128 threads, 18.8 with 256, 18.6 with
+// 512; 16 x 4 and 8 x 8 tiles were no faster with 256 threads and 25%
+// slower with 512).
 struct Shape {
     int tz, tr;
 };
 constexpr int kSmallTZ = 16, kSmallTR = 8, kSmallNT = 512;
 constexpr int kLargeTZ = 16, kLargeTR = 16, kLargeNT = 256;
 Shape shape_of(int nz, int nr) {
-    return (long long)nz * nr >= 262144 ? Shape{kLargeTZ, kLargeTR} : Shape{kSmallTZ, kSmallTR};
+    const long long large = (long long)((nz + kLargeTZ - 1) / kLargeTZ) * ((nr + kLargeTR - 1) / kLargeTR);
+    return large >= 192 ? Shape{kLargeTZ, kLargeTR} : Shape{kSmallTZ, kSmallTR};
 }
 long long tiles_of(int nz, int nr) {
     const Shape s = shape_of(nz, nr);

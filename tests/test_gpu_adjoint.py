@@ -295,14 +295,17 @@ def test_shape_loss_gradient_full_adjoint_workload():
     assert np.all(np.abs(g_gpu - fd) <= 1e-6 * np.abs(fd) + 1e-8 * np.abs(fd).max()), (g_gpu, fd)
 
 
-def test_record_and_adjoint_run_match_single_steps():
+@pytest.mark.parametrize("nz,nr,k", [(48, 24, 7), (272, 192, 4)])
+def test_record_and_adjoint_run_match_single_steps(nz, nr, k):
     """lbm_axi_record writes the same states as stepping one by one, and
     lbm_axi_adjoint_run over k recorded states equals k single adjoint
     steps: lam bit for bit (same kernels), the G and tau derivatives to
-    rounding (the run reduces its block sums once, not every step)."""
+    rounding (the run reduces its block sums once, not every step).  48 x 24
+    takes the small-lattice path (the psi-stencil kernel fused into the next
+    step), 272 x 192 the large-lattice one (two kernels per step)."""
     L, A = _libs()
-    nz, nr, G, tau, k = 48, 24, -5.5, 0.9, 7
-    _say("record / adjoint_run vs single steps")
+    G, tau = -5.5, 0.9
+    _say(f"record / adjoint_run vs single steps {nz}x{nr} k={k}")
     f, rng = _state(3, nz, nr, G)
     params = L.make_params(nz, nr, G=G, tau=tau)
     rho = torch.from_numpy(f.sum(0)).cuda()
