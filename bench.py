@@ -185,25 +185,28 @@ def _omp_threads():
 
 def _oracle_rate(p, f, budget_s):
     """MLUPS of the oracle as it stands on whole steps of (p, f), over about
-    budget_s seconds (at least one step after a start-up step)."""
+    budget_s seconds: chunks of whole steps (each about a tenth of the
+    budget) until the budget is spent, after one start-up step."""
     import oracle as O
     f = O.run(p, f, 1)  # start-up (thread pool, first touch) outside the sample
     t0 = time.perf_counter()
-    f = O.run(p, f, 2)
-    t1 = (time.perf_counter() - t0) / 2
-    steps = max(1, int(budget_s / max(t1, 1e-4)))
-    t0 = time.perf_counter()
-    O.run(p, f, steps)
-    el = time.perf_counter() - t0
+    f = O.run(p, f, 1)
+    chunk = max(1, int(0.1 * budget_s / max(time.perf_counter() - t0, 1e-4)))
+    steps, el = 0, 0.0
+    while el < budget_s:
+        t0 = time.perf_counter()
+        f = O.run(p, f, chunk)
+        el += time.perf_counter() - t0
+        steps += chunk
     return p.nz * p.nr * steps / el / 1e6, steps, el
 
 
 def cpu_baseline(rho, budget_s=12.0):
     """The oracle as it stands, timed on the host: the 4096 x 512 thread
-    workload (the benchmarked one) on every host thread and on one, and the
-    64 x 32 static drop and the 256 x 128 oscillating drop on every thread,
-    each over a bounded sample of whole steps (about budget_s seconds of
-    CPU work each, 2000-step runs where they fit)."""
+    workload (the benchmarked one) on every host thread (about budget_s
+    seconds of whole steps) and on one (about budget_s / 2), and the 64 x 32
+    static drop and the 256 x 128 oscillating drop on every thread (2000
+    steps each, about a second)."""
     import numpy as np
     import oracle as O
     from lbm_inputs import oscillating_drop, static_drop
