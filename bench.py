@@ -37,6 +37,9 @@ BYTES_PER_LU = {"f64": 9 * 2 * 8, "f32": 9 * 2 * 4}  # read + write every popula
 KERNEL_SOURCES = ("paper_1310_1871_amd/csrc/step_kernel.hpp", "paper_1310_1871_amd/csrc/lattice.hpp",
                   "paper_1310_1871_amd/csrc/lbm_axi.hip", "paper_1310_1871_amd/csrc/common.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_axi_step_4096x512.md")
+# --kernel: the step kernels of lbm_axi_set_kernel
+KERNELS = {"tile": "KERNEL_TILE", "strip": "KERNEL_STRIP", "tile-alternate": "KERNEL_TILE_ALTERNATE",
+           "tile-columns": "KERNEL_TILE_COLUMNS"}
 
 
 def kernel_source_hash():
@@ -71,7 +74,7 @@ def time_gpu(precision, rho, rho_ref, steps, warmup, kernel="tile", strip_rows=4
     from paper_1310_1871_amd import lbm_axi as L
     p = L.make_params(NZ, NR, G=G, tau=TAU, wall=L.WALL_FREESLIP, axisym=1, precision=precision, rho_ref=rho_ref)
     sim = L.AxiLBM(p, torch.from_numpy(rho).cuda())
-    sim.set_kernel(L.KERNEL_STRIP if kernel == "strip" else L.KERNEL_TILE, strip_rows)
+    sim.set_kernel(getattr(L, KERNELS[kernel]), strip_rows)
     sim.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -249,7 +252,7 @@ def main():
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain copy kernel of known size (for counter calibration)")
-    ap.add_argument("--kernel", choices=("tile", "strip"), default="tile",
+    ap.add_argument("--kernel", choices=tuple(KERNELS), default="tile",
                     help="step kernel of the FP64 and FP32 legs (lbm_axi_set_kernel); tile is the library default")
     ap.add_argument("--strip-rows", type=int, default=43, help="chunk height of the strip kernel")
     args = ap.parse_args()

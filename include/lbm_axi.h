@@ -233,15 +233,23 @@ int lbm_axi_record(lbm_axi_t h, int64_t n, void* d_states);
 
 /* Step kernel selection (the arithmetic is the same; the organisation of
  * the work differs).  LBM_AXI_KERNEL_TILE: one workgroup per tile of nodes,
- * every tile recomputing a 6-node halo.  LBM_AXI_KERNEL_STRIP: each
- * workgroup walks a band of 64 columns up a chunk of chunk_rows rows,
- * keeping the halo rows it has computed (needs nz >= 70; the Guo and
- * wall-derivative options only, no open rows).  create selects the tile
- * kernel, the faster of the two on MI355X (4096 x 512 FP64: 77 us per step
- * against 93 us for the strip with chunks of 43 rows); set_open goes back to
- * the tile kernel.  Returns LBM_AXI_EUNSUP when the strip does not apply. */
+ * every tile recomputing a 6-node halo, each XCD walking a run of whole tile
+ * rows.  LBM_AXI_KERNEL_STRIP: each workgroup walks a band of 64 columns up
+ * a chunk of chunk_rows rows, keeping the halo rows it has computed (needs
+ * nz >= 70; the Guo and wall-derivative options only, no open rows).
+ * LBM_AXI_KERNEL_TILE_ALTERNATE: the tile kernel walking its runs from the
+ * end on every other step (each step starts on the tiles the previous one
+ * ended on).  LBM_AXI_KERNEL_TILE_COLUMNS: the tile kernel with each XCD
+ * walking its rows of tiles column by column (where the runs are whole
+ * rows).  The tile orders give the same populations bit for bit; chunk_rows
+ * is read by the strip only.  create selects the tile kernel, the fastest on
+ * MI355X (4096 x 512 FP64: 77 us per step, against 78 us alternating, 80 us
+ * by columns and 93 us for the strip with chunks of 43 rows); set_open goes
+ * back to it.  Returns LBM_AXI_EUNSUP when the strip does not apply. */
 #define LBM_AXI_KERNEL_TILE 0
 #define LBM_AXI_KERNEL_STRIP 1
+#define LBM_AXI_KERNEL_TILE_ALTERNATE 2
+#define LBM_AXI_KERNEL_TILE_COLUMNS 3
 int lbm_axi_set_kernel(lbm_axi_t h, int32_t kind, int32_t chunk_rows);
 
 /* Rebind the stream later calls are issued on. */

@@ -238,6 +238,7 @@ struct lbm_axi_ctx {
     lbm_axi_params p;
     int strip_rows = 0;  // chunk height of the row-marching step kernel, 0: tile kernel
     int alternate = 0;   // tile kernel: walk the tiles in reverse order on every other step
+    int colmajor = 0;    // tile kernel: each XCD walks its rows of tiles column by column
     // two steps (from buffer 0 and from buffer 1) captured as a graph, replayed
     // by lbm_axi_step on small lattices; dropped when the launch arguments change
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -276,6 +277,7 @@ lbm::StepArgs make_args(lbm_axi_ctx* h) {
     a.rho_bc_out = h->rho_out;
     a.u_in = reinterpret_cast<const double*>(h->ws + h->L.off_open);
     if (h->in_row >= 0 || h->out_row >= 0) a.opts |= 8;
+    a.colmajor = h->colmajor;
     a.h_in = reinterpret_cast<const double*>(h->ws + h->L.off_h);
     return a;
 }
@@ -659,13 +661,15 @@ int lbm_axi_record(lbm_axi_t h, int64_t n, void* d_states) {
 
 int lbm_axi_set_kernel(lbm_axi_t h, int32_t kind, int32_t chunk_rows) {
     if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
-    if (kind == LBM_AXI_KERNEL_TILE || kind == 2) {
+    if (kind == LBM_AXI_KERNEL_TILE || kind == LBM_AXI_KERNEL_TILE_ALTERNATE || kind == LBM_AXI_KERNEL_TILE_COLUMNS) {
         h->strip_rows = 0;
-        h->alternate = kind == 2;
+        h->alternate = kind == LBM_AXI_KERNEL_TILE_ALTERNATE;
+        h->colmajor = kind == LBM_AXI_KERNEL_TILE_COLUMNS;
         drop_graphs(h);
         return LBM_AXI_OK;
     }
-    if (kind != LBM_AXI_KERNEL_STRIP) return fail(LBM_AXI_EINVAL, "kind must be LBM_AXI_KERNEL_TILE or _STRIP");
+    if (kind != LBM_AXI_KERNEL_STRIP)
+        return fail(LBM_AXI_EINVAL, "kind must be LBM_AXI_KERNEL_TILE, _STRIP, _TILE_ALTERNATE or _TILE_COLUMNS");
     if (chunk_rows < 1) return fail(LBM_AXI_EINVAL, "chunk_rows must be >= 1 (got %d)", chunk_rows);
     if (h->p.nz < lbm::kStripW + 6)
         return fail(LBM_AXI_EUNSUP, "the row-marching kernel needs nz >= %d (got %d)", lbm::kStripW + 6, h->p.nz);

@@ -44,6 +44,7 @@ struct StepArgs {
     int tiles_z;       // tiles along z (tile id = tr * tiles_z + tz: z fastest)
     int big_nz;        // 1 if nz >= TZ + 6: periodic wrap needs one add/sub
     int reverse;       // 1: each XCD walks its run of tiles from the end
+    int colmajor;      // 1: each XCD walks its run of whole tile rows column by column
     int wall;          // 0 no-slip, 1 free-slip
     int axisym;        // 1 axisymmetric terms on
     int opts;          // option bits: 1 Guo forcing, 2 no derivative terms across the wall,
@@ -100,6 +101,17 @@ __device__ __forceinline__ int xcd_remap_rev(int b, int nb) {
     const int x = b & 7, k = b >> 3;
     const int len = q + (x < rem ? 1 : 0);
     return x * q + (x < rem ? x : rem) + (len - 1 - k);
+}
+
+// the same runs, walked column by column (all the run's tile rows of one
+// column, then the next column) when every run is a whole number of tile
+// rows; otherwise as xcd_remap
+__device__ __forceinline__ int xcd_remap_col(int b, int nb, int tiles_z) {
+    const int q = nb >> 3, rem = nb & 7;
+    if (rem != 0 || q % tiles_z != 0) return xcd_remap(b, nb);
+    const int x = b & 7, k = b >> 3;
+    const int rows = q / tiles_z;
+    return x * q + (k % rows) * tiles_z + k / rows;
 }
 
 __device__ __forceinline__ int wrap_z(int z, int nz, bool big) {
@@ -682,7 +694,9 @@ __device__ __forceinline__ int slab_tile(int b, int nb, int tiles_z) {
 template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt = 0, bool kSlab = false, int kStoreAux = 0>
 __global__ __launch_bounds__(NT) void axi_tile_kernel(const StepArgs a) {
     const int tile = kSlab ? slab_tile(blockIdx.x, gridDim.x, a.tiles_z)
-                           : (a.reverse ? xcd_remap_rev(blockIdx.x, gridDim.x) : xcd_remap(blockIdx.x, gridDim.x));
+                           : (a.colmajor ? xcd_remap_col(blockIdx.x, gridDim.x, a.tiles_z)
+                                         : (a.reverse ? xcd_remap_rev(blockIdx.x, gridDim.x)
+                                                      : xcd_remap(blockIdx.x, gridDim.x)));
     tile_body<P, TZ, TR, NT, kMoments, kOpt, kStoreAux>(a, tile, blockIdx.x);
 }
 

@@ -37,6 +37,8 @@ NINTERFACE = 7
 MAX_DROPS = 64
 KERNEL_TILE = 0
 KERNEL_STRIP = 1
+KERNEL_TILE_ALTERNATE = 2
+KERNEL_TILE_COLUMNS = 3
 
 
 class Params(ctypes.Structure):
@@ -290,8 +292,9 @@ class AxiLBM:
         return out
 
     def set_kernel(self, kind, chunk_rows=48):
-        """Step kernel: KERNEL_TILE or KERNEL_STRIP with chunks of
-        chunk_rows rows (include/lbm_axi.h, lbm_axi_set_kernel)."""
+        """Step kernel: KERNEL_TILE, KERNEL_STRIP with chunks of chunk_rows
+        rows, KERNEL_TILE_ALTERNATE or KERNEL_TILE_COLUMNS
+        (include/lbm_axi.h, lbm_axi_set_kernel)."""
         check(lib.lbm_axi_set_kernel(self._h, int(kind), int(chunk_rows)))
 
     def set_coupling(self, G, tau):

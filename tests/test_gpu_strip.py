@@ -1,5 +1,6 @@
 """GPU parity of the row-marching step kernel (lbm_axi_set_kernel with
-LBM_AXI_KERNEL_STRIP) against the CPU oracle, and against the tile kernel.
+LBM_AXI_KERNEL_STRIP) against the CPU oracle, and against the tile kernel;
+the tile kernel's other tile orders against its default order.
 
 The strip computes the same step as the tile kernel (Sec. II: Eqs. scforce,
 scAxisExtra, uhydro, ueq, condition_h, H_terms, lbm2d_mod_new and the
@@ -129,3 +130,23 @@ def test_strip_selection_rules():
     with pytest.raises(L.LbmAxiError):
         sim.set_kernel(L.KERNEL_STRIP, 0)
     sim.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("nz,nr", [(1024, 256), (4096, 512)])
+def test_tile_orders_give_the_same_populations(precision, nz, nr):
+    """LBM_AXI_KERNEL_TILE_ALTERNATE and LBM_AXI_KERNEL_TILE_COLUMNS only
+    change the order in which the tiles run: 21 steps (both buffer parities,
+    graph replay included) give the default order's populations bit for bit.
+    Both lattices have whole tile rows per XCD, so the column order applies."""
+    L = _lib()
+    rg, rl = coexistence_densities(-5.5)
+    rho = thread_density(nz, nr, nr / 8.0, rl, rg, 2.0, 0.1, 1)
+    kw = dict(G=-5.5, tau=0.8, wall=1, precision=precision, rho_ref=rg if precision else 0.0)
+    _say(f"tile orders {nz}x{nr} precision={precision}")
+    _, f0 = _gpu(nz, nr, rho, 21, L.KERNEL_TILE, **kw)
+    for kind in (L.KERNEL_TILE_ALTERNATE, L.KERNEL_TILE_COLUMNS):
+        _, fk = _gpu(nz, nr, rho, 21, kind, **kw)
+        d = np.abs(f0 - fk).max()
+        _say(f"  kind {kind}: max |f - f_default| = {d:.3e}")
+        assert d == 0.0
