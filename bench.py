@@ -39,7 +39,7 @@ KERNEL_SOURCES = ("paper_1310_1871_amd/csrc/step_kernel.hpp", "paper_1310_1871_a
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_axi_step_4096x512.md")
 # --kernel: the step kernels of lbm_axi_set_kernel
 KERNELS = {"tile": "KERNEL_TILE", "strip": "KERNEL_STRIP", "tile-alternate": "KERNEL_TILE_ALTERNATE",
-           "tile-columns": "KERNEL_TILE_COLUMNS"}
+           "tile-columns": "KERNEL_TILE_COLUMNS", "tile-pairs": "KERNEL_TILE_PAIRS"}
 
 
 def kernel_source_hash():

@@ -241,15 +241,21 @@ int lbm_axi_record(lbm_axi_t h, int64_t n, void* d_states);
  * end on every other step (each step starts on the tiles the previous one
  * ended on).  LBM_AXI_KERNEL_TILE_COLUMNS: the tile kernel with each XCD
  * walking its rows of tiles column by column (where the runs are whole
- * rows).  The tile orders give the same populations bit for bit; chunk_rows
- * is read by the strip only.  create selects the tile kernel, the fastest on
- * MI355X (4096 x 512 FP64: 77 us per step, against 78 us alternating, 80 us
- * by columns and 93 us for the strip with chunks of 43 rows); set_open goes
- * back to it.  Returns LBM_AXI_EUNSUP when the strip does not apply. */
+ * rows).  LBM_AXI_KERNEL_TILE_PAIRS: the tile kernel with each thread
+ * holding two z-adjacent nodes, moved in one 16-byte access per plane (8
+ * bytes in FP32) where nz is even and z periodic; it applies to lattices of
+ * at least 1024 tiles of 64 x 16 (smaller ones run the tile kernel).  The
+ * tile variants give the same populations bit for bit; chunk_rows is read by
+ * the strip only.  create selects the tile kernel, the fastest on MI355X
+ * (4096 x 512 FP64: 76 us per step, against 78 us alternating, 80 us by
+ * columns, 80 us with node pairs and 93 us for the strip with chunks of 43
+ * rows); set_open leaves the strip for it.  Returns LBM_AXI_EUNSUP when the
+ * strip does not apply. */
 #define LBM_AXI_KERNEL_TILE 0
 #define LBM_AXI_KERNEL_STRIP 1
 #define LBM_AXI_KERNEL_TILE_ALTERNATE 2
 #define LBM_AXI_KERNEL_TILE_COLUMNS 3
+#define LBM_AXI_KERNEL_TILE_PAIRS 4
 int lbm_axi_set_kernel(lbm_axi_t h, int32_t kind, int32_t chunk_rows);
 
 /* Rebind the stream later calls are issued on. */

@@ -239,6 +239,7 @@ struct lbm_axi_ctx {
     int strip_rows = 0;  // chunk height of the row-marching step kernel, 0: tile kernel
     int alternate = 0;   // tile kernel: walk the tiles in reverse order on every other step
     int colmajor = 0;    // tile kernel: each XCD walks its rows of tiles column by column
+    int pairs = 0;       // tile kernel: z-adjacent node pairs per thread (large tiles, steps only)
     // two steps (from buffer 0 and from buffer 1) captured as a graph, replayed
     // by lbm_axi_step on small lattices; dropped when the launch arguments change
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -299,6 +300,17 @@ void launch_shape(lbm_axi_ctx* h, const lbm::StepArgs& a) {
             else
                 hipLaunchKernelGGL((lbm::axi_strip_kernel<lbm::PrecF32S, kOpt, 16>), sgrid, dim3(lbm::kStripNT), 0,
                                    h->stream, a, sa);
+            return;
+        }
+    }
+    if constexpr (!kMoments) {
+        if (h->L.cfg == 0 && h->pairs) {
+            if (f64)
+                hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF64, 64, 16, kNT64, false, kOpt, false, 0, true>),
+                                   grid, dim3(kNT64), 0, h->stream, a);
+            else
+                hipLaunchKernelGGL((lbm::axi_tile_kernel<lbm::PrecF32S, 64, 16, kNT32, false, kOpt, true, 16, true>),
+                                   grid, dim3(kNT32), 0, h->stream, a);
             return;
         }
     }
@@ -661,15 +673,18 @@ int lbm_axi_record(lbm_axi_t h, int64_t n, void* d_states) {
 
 int lbm_axi_set_kernel(lbm_axi_t h, int32_t kind, int32_t chunk_rows) {
     if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
-    if (kind == LBM_AXI_KERNEL_TILE || kind == LBM_AXI_KERNEL_TILE_ALTERNATE || kind == LBM_AXI_KERNEL_TILE_COLUMNS) {
+    if (kind == LBM_AXI_KERNEL_TILE || kind == LBM_AXI_KERNEL_TILE_ALTERNATE || kind == LBM_AXI_KERNEL_TILE_COLUMNS ||
+        kind == LBM_AXI_KERNEL_TILE_PAIRS) {
         h->strip_rows = 0;
         h->alternate = kind == LBM_AXI_KERNEL_TILE_ALTERNATE;
         h->colmajor = kind == LBM_AXI_KERNEL_TILE_COLUMNS;
+        h->pairs = kind == LBM_AXI_KERNEL_TILE_PAIRS;
         drop_graphs(h);
         return LBM_AXI_OK;
     }
     if (kind != LBM_AXI_KERNEL_STRIP)
-        return fail(LBM_AXI_EINVAL, "kind must be LBM_AXI_KERNEL_TILE, _STRIP, _TILE_ALTERNATE or _TILE_COLUMNS");
+        return fail(LBM_AXI_EINVAL,
+                    "kind must be LBM_AXI_KERNEL_TILE, _STRIP, _TILE_ALTERNATE, _TILE_COLUMNS or _TILE_PAIRS");
     if (chunk_rows < 1) return fail(LBM_AXI_EINVAL, "chunk_rows must be >= 1 (got %d)", chunk_rows);
     if (h->p.nz < lbm::kStripW + 6)
         return fail(LBM_AXI_EUNSUP, "the row-marching kernel needs nz >= %d (got %d)", lbm::kStripW + 6, h->p.nz);

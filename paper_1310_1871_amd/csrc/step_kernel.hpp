@@ -133,16 +133,27 @@ __device__ __forceinline__ int mirror_row(int y, int nr) {
     return y >= nr ? nr - 1 : y;
 }
 
+// position of window column x (>= 0) in an LDS row of W (even) entries: x
+// itself, or (kSplit) the even columns first and the odd ones after them.
+// With the split rows, lanes that hold z-adjacent node pairs (pair p at
+// columns 2p, 2p + 1) read consecutive entries for any stencil offset, as
+// lanes holding one node each do with plain rows.
+template <bool kSplit>
+__device__ __forceinline__ int lds_col(int x, int W) {
+    return kSplit ? (x & 1) * (W >> 1) + (x >> 1) : x;
+}
+
 // isotropic first derivative (Sec. II.D): (1/36) sum_i (8 phi(x+c_i) -
 // phi(x+2 c_i)) c_i,axis, on an LDS window of row pitch W
-template <bool kAlongR, class C>
+template <bool kAlongR, bool kSplit = false, class C>
 __device__ __forceinline__ C d_iso(const C* __restrict__ E, int y, int x, int W) {
     C s = C(0);
 #pragma unroll
     for (int i = 1; i < kQ; ++i) {
         const int c = kAlongR ? cr(i) : cz(i);
         if (c == 0) continue;
-        const C t = C(8) * E[(y + cr(i)) * W + x + cz(i)] - E[(y + 2 * cr(i)) * W + x + 2 * cz(i)];
+        const C t = C(8) * E[(y + cr(i)) * W + lds_col<kSplit>(x + cz(i), W)] -
+                    E[(y + 2 * cr(i)) * W + lds_col<kSplit>(x + 2 * cz(i), W)];
         s += c > 0 ? t : -t;
     }
     return s * C(1.0 / 36.0);
@@ -174,6 +185,56 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, kAux);
 }
 
+// Two adjacent values in one access (16 bytes in FP64, 8 in FP32); the
+// offset must be a multiple of the access size.  A 16-byte store takes its
+// whole offset in the vector operand and 0 as the scalar one: a vector
+// instruction that overwrites the data registers of a wider-than-8-byte
+// buffer store right after it has corrupted the stored value on gfx950 also
+// with a scalar-register offset, a form the compiler inserts no wait state
+// for; with the constant offset it does.
+typedef double pair_f64 __attribute__((ext_vector_type(2)));
+typedef float pair_f32 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void buf_load2(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double& x,
+                                          double& y) {
+    const pair_f64 v = __builtin_bit_cast(pair_f64, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    x = v.x;
+    y = v.y;
+}
+__device__ __forceinline__ void buf_load2(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float& x,
+                                          float& y) {
+    const pair_f32 v = __builtin_bit_cast(pair_f32, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    x = v.x;
+    y = v.y;
+}
+template <int kAux = 0>
+__device__ __forceinline__ void buf_store2(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double x,
+                                           double y) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0u, 0u, 0));
+    const pair_f64 v = {x, y};
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, v), r, voff + soff, 0u, kAux);
+}
+template <int kAux = 0>
+__device__ __forceinline__ void buf_store2(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float x, float y) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
+    const pair_f32 v = {x, y};
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, kAux);
+}
+
+// the value a lane one below (wave_shr:1) or one above (wave_shl:1) holds in
+// the wave (DPP row/wave control codes of GFX9); the ends of the wave read 0
+constexpr int kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138;
+template <int kCtrl>
+__device__ __forceinline__ double lane_from(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, kCtrl, 0xf, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), kCtrl, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <int kCtrl>
+__device__ __forceinline__ float lane_from(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kCtrl, 0xf, 0xf, false));
+}
+
 // One TZ x TR tile of one lattice: the whole step (or the moments) for the
 // tile's nodes.  `tile` = tr * tiles_z + tz; `slot` indexes the per-block
 // partial sums of the moments mode.  kOpt: the option bits, known at compile
@@ -194,16 +255,21 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
 // with h_i(y) = W_i (mass(y) + 3 c_i . H(y)) from StepArgs::h_in (written by
 // a moments pass with h_out); across the axis y is the mirror node with H_r
 // reversed, across the outer wall the mirror node.  kStoreAux: cache-policy
-// bits of the population stores (see buf_store).
-template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt = 0, int kStoreAux = 0>
+// bits of the population stores (see buf_store).  kPair: a thread holds
+// z-adjacent node pairs and, where nz and the plane pitch are even, z is
+// periodic and the buffers aligned, moves each pair in one 16-byte (FP32: 8)
+// access per plane, on LDS rows split into even and odd columns; the step is
+// the same to the bit.  It is not the default: on 4096 x 512 it was slower
+// (80.4 against 76.0 us per step in FP64): 13% more vector instructions, 20% more LDS
+// instructions and 2.5x the LDS bank conflicts outweighed the 24% fewer
+// memory instructions.
+template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt = 0, int kStoreAux = 0, bool kPair = false>
 __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, const int slot) {
     using S = typename P::S;
     using C = typename P::C;
     constexpr int PZ = TZ + 12, PR = TR + 12;  // psi window (halo 6)
     constexpr int DZ = TZ + 8, DR = TR + 8;    // d_r psi window (halo 4)
     constexpr int UZ = TZ + 4, UR = TR + 4;    // velocity window (halo 2)
-    static_assert(NT % TZ == 0, "tile width must divide the workgroup");
-    constexpr int RSTEP = NT / TZ;
     constexpr int NPT = TZ * TR / NT;          // tile nodes per thread
     static_assert(NPT * NT == TZ * TR, "tile must be a multiple of the workgroup");
 
@@ -283,7 +349,24 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     constexpr int NSIDE = 12 * TR;  // 6 columns left and 6 right
     constexpr int NRING = NBAND + NSIDE;
     constexpr int NIT = (NRING + NT - 1) / NT;
-    const int lz = t % TZ, lrb = t / TZ;
+    // a thread's tile nodes: one per row slot, or (kPair) z-adjacent pairs
+    // (2p, 2p + 1) of a row, so that a pair moves in one access of both
+    // values
+    static_assert(!kPair || NPT % 2 == 0, "node pairs need an even count of nodes per thread");
+    constexpr int ZL = kPair ? TZ / 2 : TZ;  // threads per tile row
+    static_assert(NT % ZL == 0, "tile row must divide the workgroup");
+    constexpr int RS = NT / ZL;  // rows between a thread's row slots
+    const int lzb = kPair ? 2 * (t % ZL) : t % ZL, lrb = t / ZL;
+    auto node_lz = [&](int k) { return kPair ? lzb + (k & 1) : lzb; };
+    auto node_lr = [&](int k) { return kPair ? lrb + (k >> 1) * RS : lrb + k * RS; };
+    // pair accesses need both nodes adjacent and the pair aligned to its
+    // size in every plane: an even nz and pitch, aligned buffers and
+    // periodic z (the mirror at z walls reverses a pair); (workgroup-uniform)
+    const bool pio = kPair && ((nz & 1) | (a.plane & 1)) == 0 && !zwalls &&
+                     ((reinterpret_cast<uintptr_t>(a.fin) | reinterpret_cast<uintptr_t>(a.fout)) &
+                      (2 * sizeof(S) - 1)) == 0;
+    // LDS windows: rows split into even and odd columns with node pairs
+    auto lc = [](int x, int W) { return lds_col<kPair>(x, W); };
     C f[NPT][kQ];
     {
         C v[NIT][kQ];
@@ -311,21 +394,33 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
 #pragma unroll
             for (int i = 0; i < kQ; ++i) v[it][i] = live ? C(buf_load(fin, node * (unsigned)sizeof(S), i * plane_bytes, S())) : C(0);
         }
+        if (pio) {
 #pragma unroll
-        for (int k = 0; k < NPT; ++k) {
-            const int lr = lrb + k * RSTEP;
-            const int gz = col_of(z0 + lz);
-            const int gr = mirror_row(r0 + lr, nr);
-            const unsigned node = (unsigned)(gr * nz + gz);
+            for (int k = 0; k < NPT; k += 2) {
+                const unsigned node = (unsigned)(mirror_row(r0 + node_lr(k), nr) * nz + col_of(z0 + lzb));
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) f[k][i] = C(buf_load(fin, node * (unsigned)sizeof(S), i * plane_bytes, S()));
+                for (int i = 0; i < kQ; ++i) {
+                    S x, y;
+                    buf_load2(fin, node * (unsigned)sizeof(S), i * plane_bytes, x, y);
+                    f[k][i] = C(x);
+                    f[k + 1][i] = C(y);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const unsigned node = (unsigned)(mirror_row(r0 + node_lr(k), nr) * nz + col_of(z0 + node_lz(k)));
+#pragma unroll
+                for (int i = 0; i < kQ; ++i)
+                    f[k][i] = C(buf_load(fin, node * (unsigned)sizeof(S), i * plane_bytes, S()));
+            }
         }
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             if (hrz[it] < 0) continue;
             const int hr = hrz[it] >> 16, hz = hrz[it] & 0xffff;
             const C rho = rho_of(v[it]);
-            s_psi[hr * PZ + hz] = psi_of(rho);
+            s_psi[hr * PZ + lc(hz, PZ)] = psi_of(rho);
             const int uy = hr - 4, ux = hz - 4, gr = r0 - 6 + hr;
             if (uy >= 0 && uy < UR && ux >= 0 && ux < UZ && gr >= 0 && gr < nr) {
                 const int o = ring_index(uy, ux);
@@ -336,16 +431,19 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         }
     }
 #pragma unroll
-    for (int k = 0; k < NPT; ++k) s_psi[(lrb + k * RSTEP + 6) * PZ + lz + 6] = psi_of(rho_of(f[k]));
+    for (int k = 0; k < NPT; ++k) s_psi[(node_lr(k) + 6) * PZ + lc(node_lz(k) + 6, PZ)] = psi_of(rho_of(f[k]));
     __syncthreads();
 
     // ---- 2. isotropic d_r psi on the 4-node halo, and the 1D d_r psi that
     // the mixed derivative d_zr differences along z ----------------------
+    // (idx runs over LDS positions: with split rows, position q holds
+    // column 2q, or 2 (q - DZ/2) + 1 in the row's second half)
     for (int idx = t; idx < DR * DZ; idx += NT) {
-        const int y = idx / DZ, x = idx - y * DZ;
-        s_dr[idx] = d_iso<true>(s_psi, y + 2, x + 2, PZ);
+        const int y = idx / DZ, q = idx - y * DZ;
+        const int x = kPair ? (q < DZ / 2 ? 2 * q : 2 * (q - DZ / 2) + 1) : q;
+        s_dr[idx] = d_iso<true, kPair>(s_psi, y + 2, x + 2, PZ);
         if (y >= 2 && y < DR - 2) {
-            const int c = x + 2;  // psi-window column; rows y .. y + 4
+            const int c = lc(x + 2, PZ);  // psi-window column; rows y .. y + 4
             s_d1[idx] = (-s_psi[(y + 4) * PZ + c] + C(8) * s_psi[(y + 3) * PZ + c] - C(8) * s_psi[(y + 1) * PZ + c] +
                          s_psi[y * PZ + c]) *
                         C(1.0 / 12.0);
@@ -365,20 +463,22 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         C sz = C(0), sr = C(0);
 #pragma unroll
         for (int i = 1; i < kQ; ++i) {
-            const C ps = s_psi[(py + cr(i)) * PZ + px + cz(i)] * C(weight(i));
+            const C ps = s_psi[(py + cr(i)) * PZ + lc(px + cz(i), PZ)] * C(weight(i));
             if (cz(i) != 0) sz += cz(i) > 0 ? ps : -ps;
             if (cr(i) != 0) sr += cr(i) > 0 ? ps : -ps;
         }
-        const C psi = s_psi[py * PZ + px];
+        const C psi = s_psi[py * PZ + lc(px, PZ)];
         Fz = -G * psi * sz;
         Fr = -G * psi * sr;
         // F^{gamma,sym} reads psi up to 4 rows away
         if (a.axisym && !no_fsym(z0 - 2 + ux, r0 - 2 + uy)) {
-            const C dr1 = s_dr[dy * DZ + dx];
-            const C drr = d_iso<true>(s_dr, dy, dx, DZ);
+            const C dr1 = s_dr[dy * DZ + lc(dx, DZ)];
+            const C drr = d_iso<true, kPair>(s_dr, dy, dx, DZ);
             // mixed derivative: 1D fourth-order d_z of the 1D fourth-order d_r
-            const C* d1 = s_d1 + dy * DZ + dx - 2;
-            const C dzr = (-d1[4] + C(8) * d1[3] - C(8) * d1[1] + d1[0]) * C(1.0 / 12.0);
+            const C* d1 = s_d1 + dy * DZ;
+            const C dzr = (-d1[lc(dx + 2, DZ)] + C(8) * d1[lc(dx + 1, DZ)] - C(8) * d1[lc(dx - 1, DZ)] +
+                           d1[lc(dx - 2, DZ)]) *
+                          C(1.0 / 12.0);
             const C inv_r = dev_rcp(rr);
             const C pre = -g18 * psi;
             Fz += pre * dzr * inv_r;
@@ -391,7 +491,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     // 3a. tile nodes of real rows, from the populations in registers
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        const int lr = lrb + k * RSTEP;
+        const int lr = node_lr(k), lz = node_lz(k);
         const int gr = r0 + lr;
         Fz_t[k] = C(0);
         Fr_t[k] = C(0);
@@ -402,8 +502,8 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             Fz_t[k] = Fz;
             Fr_t[k] = Fr;
             const C inv_rho = dev_rcp(rho);
-            s_uz[(lr + 2) * UZ + lz + 2] = (jz_of(f[k]) + C(0.5) * Fz) * inv_rho;
-            s_ur[(lr + 2) * UZ + lz + 2] = (jr_of(f[k]) + C(0.5) * Fr) * inv_rho;
+            s_uz[(lr + 2) * UZ + lc(lz + 2, UZ)] = (jz_of(f[k]) + C(0.5) * Fz) * inv_rho;
+            s_ur[(lr + 2) * UZ + lc(lz + 2, UZ)] = (jr_of(f[k]) + C(0.5) * Fr) * inv_rho;
         }
     }
     // 3b. velocity-ring nodes of real rows, from rho and j in LDS
@@ -426,8 +526,8 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         C Fz, Fr;
         force_at(uy, ux, rho, C(y) + C(0.5), Fz, Fr);
         const C inv_rho = dev_rcp(rho);
-        s_uz[uy * UZ + ux] = (s_mom[1][idx] + C(0.5) * Fz) * inv_rho;
-        s_ur[uy * UZ + ux] = (s_mom[2][idx] + C(0.5) * Fr) * inv_rho;
+        s_uz[uy * UZ + lc(ux, UZ)] = (s_mom[1][idx] + C(0.5) * Fz) * inv_rho;
+        s_ur[uy * UZ + lc(ux, UZ)] = (s_mom[2][idx] + C(0.5) * Fr) * inv_rho;
     }
     __syncthreads();
     // 3c. rows outside the lattice (only in tiles at the axis or the wall):
@@ -436,6 +536,8 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     const int axis_rows = r0 < 2 ? 2 - r0 : 0;  // velocity-window rows below the axis
     const int wall_lo = nr - (r0 - 2);           // first velocity-window row beyond the wall
     if (axis_rows > 0 || wall_lo < UR) {         // uniform over the workgroup
+        // (a copy within one LDS column position: the same column in
+        // either row layout)
         for (int idx = t; idx < UR * UZ; idx += NT) {
             const int uy = idx / UZ, ux = idx - uy * UZ;
             const bool axis_side = uy < axis_rows;
@@ -463,9 +565,39 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     const C inv_tau = C(1) / tau;
     const C mu_fac = (tau - C(0.5)) * C(1.0 / 3.0);  // mu = rho c_s^2 (tau - 1/2)
     double part[4] = {0.0, 0.0, 0.0, 0.0};
+    // push of an interior pair (nodes 2p, 2p + 1 of a tile row at byte
+    // offset a_off) in aligned pairs: the pushes along r land on the pair's
+    // own columns; along +z the target pair (2p, 2p + 1) takes the second
+    // node of pair p - 1 (one lane below) and this pair's first node, along
+    // -z this pair's second node and the first node of pair p + 1 (one lane
+    // above).  The ends of a tile row store their odd value alone.
+    auto push_pair = [&](unsigned a_off, const C* fa, const C* fb) {
+        const __amdgpu_buffer_rsrc_t fo = pop_rsrc(a.fout, a.state_bytes);
+        const int p = t % ZL;
+        const bool first = p == 0, last = p == ZL - 1;
+        constexpr unsigned sz = (unsigned)sizeof(S);
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const unsigned soff = (unsigned)i * plane_bytes + (unsigned)(cr(i) * nz * (int)sizeof(S));
+            const S va = S(fa[i]), vb = S(fb[i]);
+            if (cz(i) == 0) {
+                buf_store2<kStoreAux>(fo, a_off, soff, va, vb);
+            } else if (cz(i) > 0) {
+                const S prev_b = lane_from<kDppWaveShr1>(vb);
+                if (!first) buf_store2<kStoreAux>(fo, a_off, soff, prev_b, va);
+                else buf_store<kStoreAux>(fo, a_off + sz, soff, va);
+                if (last) buf_store<kStoreAux>(fo, a_off + 2 * sz, soff, vb);
+            } else {
+                const S next_a = lane_from<kDppWaveShl1>(va);
+                if (!last) buf_store2<kStoreAux>(fo, a_off, soff, vb, next_a);
+                else buf_store<kStoreAux>(fo, a_off, soff, vb);
+                if (first) buf_store<kStoreAux>(fo, a_off - sz, soff, va);
+            }
+        }
+    };
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        const int lr = lrb + k * RSTEP;
+        const int lr = node_lr(k), lz = node_lz(k);
         const int gz = z0 + lz, gr = r0 + lr;
         const bool valid = gz < nz && gr < nr;
         if (!valid) continue;
@@ -476,16 +608,16 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         const C rho = P::kShift ? sig + rho_ref : sig;
         const C jz = (f[k][1] - f[k][3]) + (f[k][5] - f[k][6]) + (f[k][8] - f[k][7]);
         const C jr = (f[k][2] - f[k][4]) + (f[k][5] - f[k][8]) + (f[k][6] - f[k][7]);
-        const C uz = s_uz[uy * UZ + ux], ur = s_ur[uy * UZ + ux];
+        const C uz = s_uz[uy * UZ + lc(ux, UZ)], ur = s_ur[uy * UZ + lc(ux, UZ)];
         const C rr = C(gr) + C(0.5);
 
         // H and the mass source of the node (Eqs. H_terms, condition_h)
         auto source_terms = [&](C& hz, C& hr, C& mass) {
             // the velocity derivatives read rows up to 2 away
             const bool zd = no_du(gz, gr);
-            const C druz = zd ? C(0) : d_iso<true>(s_uz, uy, ux, UZ);
-            const C dzur = zd ? C(0) : d_iso<false>(s_ur, uy, ux, UZ);
-            const C drur = zd ? C(0) : d_iso<true>(s_ur, uy, ux, UZ);
+            const C druz = zd ? C(0) : d_iso<true, kPair>(s_uz, uy, ux, UZ);
+            const C dzur = zd ? C(0) : d_iso<false, kPair>(s_ur, uy, ux, UZ);
+            const C drur = zd ? C(0) : d_iso<true, kPair>(s_ur, uy, ux, UZ);
             const C inv_r = dev_rcp(rr);
             const C mu = rho * mu_fac;
             hz = (mu * (druz + dzur) - rho * ur * uz) * inv_r;
@@ -546,8 +678,8 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
                     br = C(a.u_in[nz + gz]);
                 } else {
                     brho = C(a.rho_bc_out);
-                    bz = s_uz[(uy - 1) * UZ + ux];
-                    br = s_ur[(uy - 1) * UZ + ux];
+                    bz = s_uz[(uy - 1) * UZ + lc(ux, UZ)];
+                    br = s_ur[(uy - 1) * UZ + lc(ux, UZ)];
                 }
             }
             const C bqq = C(1.5) * (bz * bz + br * br);
@@ -619,13 +751,19 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             // displacement folded into the scalar offset.
             if (plain) {
                 const unsigned node_off = (unsigned)(gr * nz + gz) * (unsigned)sizeof(S);
+                if (kPair && pio) {
+                    // a pair is pushed once its second node is done (both lie
+                    // in one row and are valid: nz is even)
+                    if (k & 1) push_pair(node_off - (unsigned)sizeof(S), f[k - 1], f[k]);
+                } else {
 #pragma unroll
-                for (int i = 0; i < kQ; ++i) {
-                    // i * plane + displacement is the (non-negative) offset of the
-                    // target in plane i; unsigned wrap-around adds the signed
-                    // displacement exactly
-                    const unsigned disp = (unsigned)((cr(i) * nz + cz(i)) * (int)sizeof(S));
-                    buf_store<kStoreAux>(fout, node_off, (unsigned)i * plane_bytes + disp, S(f[k][i]));
+                    for (int i = 0; i < kQ; ++i) {
+                        // i * plane + displacement is the (non-negative) offset of the
+                        // target in plane i; unsigned wrap-around adds the signed
+                        // displacement exactly
+                        const unsigned disp = (unsigned)((cr(i) * nz + cz(i)) * (int)sizeof(S));
+                        buf_store<kStoreAux>(fout, node_off, (unsigned)i * plane_bytes + disp, S(f[k][i]));
+                    }
                 }
             } else {
 #pragma unroll
@@ -690,14 +828,16 @@ __device__ __forceinline__ int slab_tile(int b, int nb, int tiles_z) {
     return tr * tiles_z + (b & 7) * sw + (k - tr * sw);
 }
 
-// kSlab: slab order (slab_tile) instead of runs of tile rows (xcd_remap)
-template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt = 0, bool kSlab = false, int kStoreAux = 0>
+// kSlab: slab order (slab_tile) instead of runs of tile rows (xcd_remap);
+// kPair: each thread holds z-adjacent node pairs (see tile_body)
+template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt = 0, bool kSlab = false, int kStoreAux = 0,
+          bool kPair = false>
 __global__ __launch_bounds__(NT) void axi_tile_kernel(const StepArgs a) {
     const int tile = kSlab ? slab_tile(blockIdx.x, gridDim.x, a.tiles_z)
                            : (a.colmajor ? xcd_remap_col(blockIdx.x, gridDim.x, a.tiles_z)
                                          : (a.reverse ? xcd_remap_rev(blockIdx.x, gridDim.x)
                                                       : xcd_remap(blockIdx.x, gridDim.x)));
-    tile_body<P, TZ, TR, NT, kMoments, kOpt, kStoreAux>(a, tile, blockIdx.x);
+    tile_body<P, TZ, TR, NT, kMoments, kOpt, kStoreAux, kPair>(a, tile, blockIdx.x);
 }
 
 }  // namespace lbm

@@ -39,6 +39,7 @@ KERNEL_TILE = 0
 KERNEL_STRIP = 1
 KERNEL_TILE_ALTERNATE = 2
 KERNEL_TILE_COLUMNS = 3
+KERNEL_TILE_PAIRS = 4
 
 
 class Params(ctypes.Structure):
@@ -293,8 +294,8 @@ class AxiLBM:
 
     def set_kernel(self, kind, chunk_rows=48):
         """Step kernel: KERNEL_TILE, KERNEL_STRIP with chunks of chunk_rows
-        rows, KERNEL_TILE_ALTERNATE or KERNEL_TILE_COLUMNS
-        (include/lbm_axi.h, lbm_axi_set_kernel)."""
+        rows, KERNEL_TILE_ALTERNATE, KERNEL_TILE_COLUMNS or
+        KERNEL_TILE_PAIRS (include/lbm_axi.h, lbm_axi_set_kernel)."""
         check(lib.lbm_axi_set_kernel(self._h, int(kind), int(chunk_rows)))
 
     def set_coupling(self, G, tau):

@@ -136,16 +136,18 @@ def test_strip_selection_rules():
 @pytest.mark.parametrize("nz,nr", [(1024, 256), (4096, 512)])
 def test_tile_orders_give_the_same_populations(precision, nz, nr):
     """LBM_AXI_KERNEL_TILE_ALTERNATE and LBM_AXI_KERNEL_TILE_COLUMNS only
-    change the order in which the tiles run: 21 steps (both buffer parities,
-    graph replay included) give the default order's populations bit for bit.
-    Both lattices have whole tile rows per XCD, so the column order applies."""
+    change the order in which the tiles run, LBM_AXI_KERNEL_TILE_PAIRS the
+    nodes a thread holds and the width of its accesses: 21 steps (both buffer
+    parities, graph replay included) give the default kernel's populations
+    bit for bit.  Both lattices have whole tile rows per XCD, so the column
+    order applies; node pairs apply to the larger one (64 x 16 tiles)."""
     L = _lib()
     rg, rl = coexistence_densities(-5.5)
     rho = thread_density(nz, nr, nr / 8.0, rl, rg, 2.0, 0.1, 1)
     kw = dict(G=-5.5, tau=0.8, wall=1, precision=precision, rho_ref=rg if precision else 0.0)
     _say(f"tile orders {nz}x{nr} precision={precision}")
     _, f0 = _gpu(nz, nr, rho, 21, L.KERNEL_TILE, **kw)
-    for kind in (L.KERNEL_TILE_ALTERNATE, L.KERNEL_TILE_COLUMNS):
+    for kind in (L.KERNEL_TILE_ALTERNATE, L.KERNEL_TILE_COLUMNS, L.KERNEL_TILE_PAIRS):
         _, fk = _gpu(nz, nr, rho, 21, kind, **kw)
         d = np.abs(f0 - fk).max()
         _say(f"  kind {kind}: max |f - f_default| = {d:.3e}")
