@@ -34,9 +34,16 @@ __global__ __launch_bounds__(NT) void axi_batch_kernel(const BatchInstance* __re
         const int inst = __builtin_amdgcn_readfirstlane(w.x);
         const int tile = __builtin_amdgcn_readfirstlane(w.y);
         const StepArgs a = insts[inst].args[parity];
+        // the thread index passes through an empty asm on every item, so
+        // the values the tile body derives from it (window coordinates, LDS
+        // addresses) are formed per item instead of being hoisted out of the
+        // loop and held in registers across it (FP32 64 x 16 / 512 threads:
+        // 124 -> 76 VGPRs, 2 -> 3 workgroups per CU)
+        int t = threadIdx.x;
+        asm volatile("" : "+v"(t));
         // FP32 stores device scope, as on a single large lattice (41.4 ->
         // 42.1 GLUPS on a 256-instance ensemble)
-        tile_body<P, TZ, TR, NT, false, kOpt, sizeof(typename P::S) == 4 ? 16 : 0>(a, tile, 0);
+        tile_body<P, TZ, TR, NT, false, kOpt, sizeof(typename P::S) == 4 ? 16 : 0>(a, tile, 0, t);
         __syncthreads();  // the next item reuses the LDS windows
     }
 }

@@ -264,7 +264,7 @@ __device__ __forceinline__ float lane_from(float v) {
 // instructions and 2.5x the LDS bank conflicts outweighed the 24% fewer
 // memory instructions.
 template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt = 0, int kStoreAux = 0, bool kPair = false>
-__device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, const int slot) {
+__device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, const int slot, const int t) {
     using S = typename P::S;
     using C = typename P::C;
     constexpr int PZ = TZ + 12, PR = TR + 12;  // psi window (halo 6)
@@ -288,7 +288,6 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     const unsigned plane_bytes = (unsigned)a.plane * (unsigned)sizeof(S);
     const int nz = a.nz, nr = a.nr;
     const bool big = a.big_nz != 0;
-    const int t = threadIdx.x;
     const int tri = tile / a.tiles_z;
     const int z0 = (tile - tri * a.tiles_z) * TZ, r0 = tri * TR;
     const int opts = kOpt < 0 ? a.opts : kOpt;
@@ -765,6 +764,20 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
                         buf_store<kStoreAux>(fout, node_off, (unsigned)i * plane_bytes + disp, S(f[k][i]));
                     }
                 }
+            } else if (!zwalls && gr > 0 && gr < nr - 1) {
+                // a row between the axis and the wall in a tile at an end of
+                // z (or on a lattice narrower than a tile): the same push, the
+                // targets across a periodic end moved by one period
+                const unsigned node_off = (unsigned)(gr * nz + gz) * (unsigned)sizeof(S);
+                const unsigned period = (unsigned)nz * (unsigned)sizeof(S);
+                const unsigned off_m = gz == 0 ? node_off + period : node_off;       // c_z = -1
+                const unsigned off_p = gz == nz - 1 ? node_off - period : node_off;  // c_z = +1 (gr >= 1)
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) {
+                    const unsigned disp = (unsigned)((cr(i) * nz + cz(i)) * (int)sizeof(S));
+                    buf_store<kStoreAux>(fout, cz(i) < 0 ? off_m : (cz(i) > 0 ? off_p : node_off),
+                                         (unsigned)i * plane_bytes + disp, S(f[k][i]));
+                }
             } else {
 #pragma unroll
                 for (int i = 0; i < kQ; ++i) {
@@ -837,7 +850,7 @@ __global__ __launch_bounds__(NT) void axi_tile_kernel(const StepArgs a) {
                            : (a.colmajor ? xcd_remap_col(blockIdx.x, gridDim.x, a.tiles_z)
                                          : (a.reverse ? xcd_remap_rev(blockIdx.x, gridDim.x)
                                                       : xcd_remap(blockIdx.x, gridDim.x)));
-    tile_body<P, TZ, TR, NT, kMoments, kOpt, kStoreAux, kPair>(a, tile, blockIdx.x);
+    tile_body<P, TZ, TR, NT, kMoments, kOpt, kStoreAux, kPair>(a, tile, blockIdx.x, threadIdx.x);
 }
 
 }  // namespace lbm
