@@ -259,10 +259,10 @@ __device__ __forceinline__ float lane_from(float v) {
 // z-adjacent node pairs and, where nz and the plane pitch are even, z is
 // periodic and the buffers aligned, moves each pair in one 16-byte (FP32: 8)
 // access per plane, on LDS rows split into even and odd columns; the step is
-// the same to the bit.  It is not the default: on 4096 x 512 it was slower
-// (80.4 against 76.0 us per step in FP64): 13% more vector instructions, 20% more LDS
-// instructions and 2.5x the LDS bank conflicts outweighed the 24% fewer
-// memory instructions.
+// the same to the bit.  It is not the default: on 4096 x 512 it is slower
+// (78.8 against 75.3 us per step in FP64): 13% more vector and 24% more LDS
+// instructions and 2.5x the LDS bank conflicts outweigh 24% fewer memory
+// reads.
 template <class P, int TZ, int TR, int NT, bool kMoments, int kOpt = 0, int kStoreAux = 0, bool kPair = false>
 __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, const int slot, const int t) {
     using S = typename P::S;
