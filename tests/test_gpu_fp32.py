@@ -137,7 +137,12 @@ def test_fp32_drop_frequency_vs_oracle():
     (rho_ref = rho_g) vs the FP64 oracle's: relative difference <= 0.5 %.
     The GPU FP64 trace is also fitted and must reproduce the oracle's
     frequency to 1e-6.  Both are compared with Miller and Scriven's
-    frequency (Sec. IV.B) at the fitted R_D: +2.1 % (bound 3 %)."""
+    frequency (Sec. IV.B) at the fitted R_D: +2.1 % (bound 3 %).  The paper
+    fixes no damping; the fitted decay rate b (4.7e-4 per step) is set
+    beside Lamb's (l - 1)(2 l + 1) nu / R_D^2 for a free drop (3.1e-4): 1.5
+    times it, the excess that the gas, the interface boundary layers (a
+    tenth of Lamb's rate by Miller and Scriven's correction) and the
+    diffuse interface of a few nodes add; bound 1-2."""
     case = oscillating_drop()
     steps, every = 20000, 10
     mid = 0.5 * (case.rho_l + case.rho_g)
@@ -175,11 +180,14 @@ def test_fp32_drop_frequency_vs_oracle():
         w0 = np.sqrt(24 * gam / (R0 ** 3 * (2 * rout + 3 * rin)))
         al = 25 * nu * rin * rout / (np.sqrt(2) * R0 * (2 * rout + 3 * rin) * (np.sqrt(nu) * (rin + rout)))
         ms = w0 - 0.5 * al * np.sqrt(w0) + 0.25 * al * al
-        _say(f"  {name}: R_D {R0:.3f}  omega {w:.6e}  Miller-Scriven {ms:.6e}  rel err {w / ms - 1:+.4f}")
+        lamb = 5.0 * nu / R0 ** 2  # (l - 1)(2 l + 1) nu / R^2, l = 2
+        _say(f"  {name}: R_D {R0:.3f}  omega {w:.6e}  Miller-Scriven {ms:.6e}  rel err {w / ms - 1:+.4f}  "
+             f"decay {popt[2]:.3e}  Lamb {lamb:.3e}  ratio {popt[2] / lamb:.3f}")
         # the paper reports about 1 % at G = -6, tau = 1 on 320 x 128 (the
         # oracle pin reproduces that); this drop (G = -5.5, tau = 0.8,
         # R = 40) is 2.1 % fast
         assert abs(w / ms - 1.0) < 0.03
+        assert 1.0 < popt[2] / lamb < 2.0
 
 
 def _flat_surface_tension(G, tau):
