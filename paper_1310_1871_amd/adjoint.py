@@ -129,6 +129,25 @@ def adjoint_run(params, states, k, lam, tmp, grad_acc, ws):
                                     ws.numel() * ws.element_size(), _s()))
 
 
+# The backward pass recomputes each checkpoint segment on a second stream
+# while the previous segment is reversed, on lattices of at most this many
+# nodes: there neither the forward steps nor the reverse steps fill the GPU
+# (256 x 128: (forward + backward) / forward 3.57 -> 2.81, 384 x 192 4.40 ->
+# 3.80, 512 x 256 4.65 -> 4.07); on 1024 x 512 and 2048 x 1024 it changed
+# nothing beyond the run-to-run spread.  Set to 0 to keep one stream.
+OVERLAP_MAX_NODES = 1 << 18
+_side_streams = {}
+
+
+def _side_stream(dev):
+    """One recompute stream per device (default priority), made once."""
+    idx = torch.device(dev).index
+    idx = torch.cuda.current_device() if idx is None else idx
+    if idx not in _side_streams:
+        _side_streams[idx] = torch.cuda.Stream(device=idx)
+    return _side_streams[idx]
+
+
 class ShapeLoss(torch.autograd.Function):
     """loss = sum_t sum_m (r(theta_m, t) - target[t, m])^2 of a run started
     from f^eq(rho0, 0); differentiable in rho0, G and tau.
@@ -176,19 +195,44 @@ class ShapeLoss(torch.autograd.Function):
         grad_acc = torch.zeros(2, dtype=torch.float64, device=dev)
         lam_a = torch.zeros((9, nr, nz), dtype=torch.float64, device=dev)
         lam_b = torch.zeros_like(lam_a)
-        seg_states = torch.empty((checkpoint, 9, nr, nz), dtype=torch.float64, device=dev)
         scaled_rbar = rbar * gout.to(torch.float64)
         # lam currently holds dL/df^T (T = steps)
         if steps % every == 0:
             probe.add_vjp(scaled_rbar[steps // every - 1], lam_a)
-        sim = None
-        for s in reversed(range(len(ckpts))):
+        # The states of segment s - 1 are recomputed (on a second stream on
+        # small lattices, see OVERLAP_MAX_NODES) while the reverse sweep of
+        # segment s runs on this one: two state buffers, ordered by events.
+        # The reverse sweep, and so every accumulation, keeps its order on
+        # this stream, so the gradients do not depend on the overlap.
+        main = torch.cuda.current_stream(dev)
+        side = _side_stream(dev) if nz * nr <= OVERLAP_MAX_NODES else main
+        side.wait_stream(main)
+        bufs = [torch.empty((checkpoint, 9, nr, nz), dtype=torch.float64, device=dev) for _ in range(2)]
+        swept = [None, None]  # event after the last reverse sweep that read each buffer
+        recorded = {}
+        with torch.cuda.stream(side):
+            sim = L.AxiLBM(params, rho0.detach())
+
+        def recompute(s):
+            # the states f^t, t0 <= t < t0 + checkpoint, in one call
+            b = s % 2
+            with torch.cuda.stream(side):
+                if swept[b] is not None:
+                    side.wait_event(swept[b])
+                sim.set_state(ckpts[s].reshape(-1).view(torch.uint8))
+                sim.record(checkpoint, bufs[b])
+                recorded[s] = torch.cuda.Event()
+                recorded[s].record(side)
+
+        nseg = len(ckpts)
+        if nseg:
+            recompute(nseg - 1)
+        for s in reversed(range(nseg)):
+            if s > 0:
+                recompute(s - 1)
+            main.wait_event(recorded.pop(s))
+            seg_states = bufs[s % 2]
             t0 = s * checkpoint
-            # recompute the states f^t, t0 <= t < t0 + checkpoint, in one call
-            if sim is None:
-                sim = L.AxiLBM(params, rho0.detach())
-            sim.set_state(ckpts[s].reshape(-1).view(torch.uint8))
-            sim.record(checkpoint, seg_states)
             # reverse sweep in runs between sample steps; after lam^t is
             # formed at a sample step t > 0, its misfit VJP is added
             hi = checkpoint
@@ -200,8 +244,14 @@ class ShapeLoss(torch.autograd.Function):
             adjoint_run(params, seg_states[0], hi, lam_a, lam_b, grad_acc, ws)
             if t0 > 0 and t0 % every == 0:
                 probe.add_vjp(scaled_rbar[t0 // every - 1], lam_a)
-        if sim is not None:
-            sim.close()
+            swept[s % 2] = torch.cuda.Event()
+            swept[s % 2].record(main)
+        # the side stream's work is complete once main has waited for the
+        # last recompute; the buffers and the handle were used on both
+        main.wait_stream(side)
+        for b in bufs:
+            b.record_stream(side)
+        sim.close()
         rho_bar = torch.empty((nr, nz), dtype=torch.float64, device=dev)
         _check(_lib.lbm_axi_init_vjp(_p(lam_a), None, None, nz, nr, _p(rho_bar), _s()))
         g = grad_acc.to(torch.float64)

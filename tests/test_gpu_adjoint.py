@@ -339,7 +339,9 @@ def test_record_and_adjoint_run_match_single_steps(nz, nr, k):
 
 def test_checkpointing_is_exact():
     """Recomputing segments from checkpoints reproduces the gradient of the
-    no-recomputation run bit for bit (the step kernel is deterministic)."""
+    no-recomputation run bit for bit (the step kernel is deterministic), and
+    so does the backward pass with the recomputation on the reverse sweep's
+    own stream instead of a second one (OVERLAP_MAX_NODES = 0)."""
     L, A = _libs()
     nz, nr, R, G, tau, rg, rl, ls, a_t, a_0 = _c4_small()
     steps, every = 200, 50
@@ -348,9 +350,17 @@ def test_checkpointing_is_exact():
     rho0 = torch.from_numpy(drop_density(nz, nr, nz / 2.0, R, rl, rg, 2.0, a_0)).cuda()
     tgt = A.radius_history(torch.from_numpy(drop_density(nz, nr, nz / 2.0, R, rl, rg, 2.0, a_t)).cuda(), G, tau,
                            probe, steps, every)
+    assert nz * nr <= A.OVERLAP_MAX_NODES
     grads = []
-    for ck in (50, 200):
-        r0 = rho0.clone().requires_grad_(True)
-        A.shape_loss(r0, G, tau, probe, tgt, steps, every, ck).backward()
-        grads.append(r0.grad.clone())
+    for ck, overlap in ((50, True), (200, True), (50, False)):
+        keep = A.OVERLAP_MAX_NODES
+        A.OVERLAP_MAX_NODES = keep if overlap else 0
+        try:
+            r0 = rho0.clone().requires_grad_(True)
+            G_ = torch.tensor(G, dtype=torch.float64, device="cuda", requires_grad=True)
+            A.shape_loss(r0, G_, tau, probe, tgt, steps, every, ck).backward()
+        finally:
+            A.OVERLAP_MAX_NODES = keep
+        grads.append(torch.cat([r0.grad.reshape(-1), G_.grad.reshape(-1)]))
     assert torch.equal(grads[0], grads[1])
+    assert torch.equal(grads[0], grads[2])
