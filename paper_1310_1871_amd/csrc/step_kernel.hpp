@@ -454,9 +454,9 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     const C G = C(a.G);
     const C g18 = G * C(1.0 / 18.0);  // (G/2) c_s^4
     const C gz_acc = C(a.gz);
-    // force at velocity-window coordinates (uy, ux) of a real row with
-    // radius rr
-    auto force_at = [&](int uy, int ux, C rho, C rr, C& Fz, C& Fr) {
+    // force at velocity-window coordinates (uy, ux) of a real row whose
+    // radius r + 1/2 has the reciprocal inv_r
+    auto force_at = [&](int uy, int ux, C rho, C inv_r, C& Fz, C& Fr) {
         const int py = uy + 4, px = ux + 4;  // psi window
         const int dy = uy + 2, dx = ux + 2;  // d_r psi window
         C sz = C(0), sr = C(0);
@@ -478,7 +478,6 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             const C dzr = (-d1[lc(dx + 2, DZ)] + C(8) * d1[lc(dx + 1, DZ)] - C(8) * d1[lc(dx - 1, DZ)] +
                            d1[lc(dx - 2, DZ)]) *
                           C(1.0 / 12.0);
-            const C inv_r = dev_rcp(rr);
             const C pre = -g18 * psi;
             Fz += pre * dzr * inv_r;
             Fr += pre * (drr * inv_r - dr1 * inv_r * inv_r);
@@ -487,6 +486,8 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
     };
 
     C Fz_t[NPT], Fr_t[NPT];
+    // 1 / (r + 1/2) and 1 / rho of the tile nodes, kept for the collision
+    C inv_r_t[NPT], inv_rho_t[NPT];
     // 3a. tile nodes of real rows, from the populations in registers
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
@@ -494,13 +495,17 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         const int gr = r0 + lr;
         Fz_t[k] = C(0);
         Fr_t[k] = C(0);
+        inv_r_t[k] = C(0);
+        inv_rho_t[k] = C(0);
         if (gr < nr) {
             const C rho = rho_of(f[k]);
+            inv_r_t[k] = dev_rcp(C(gr) + C(0.5));
             C Fz, Fr;
-            force_at(lr + 2, lz + 2, rho, C(gr) + C(0.5), Fz, Fr);
+            force_at(lr + 2, lz + 2, rho, inv_r_t[k], Fz, Fr);
             Fz_t[k] = Fz;
             Fr_t[k] = Fr;
             const C inv_rho = dev_rcp(rho);
+            inv_rho_t[k] = inv_rho;
             s_uz[(lr + 2) * UZ + lc(lz + 2, UZ)] = (jz_of(f[k]) + C(0.5) * Fz) * inv_rho;
             s_ur[(lr + 2) * UZ + lc(lz + 2, UZ)] = (jr_of(f[k]) + C(0.5) * Fr) * inv_rho;
         }
@@ -523,7 +528,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         if (y < 0 || y >= nr) continue;
         const C rho = s_mom[0][idx];
         C Fz, Fr;
-        force_at(uy, ux, rho, C(y) + C(0.5), Fz, Fr);
+        force_at(uy, ux, rho, dev_rcp(C(y) + C(0.5)), Fz, Fr);
         const C inv_rho = dev_rcp(rho);
         s_uz[uy * UZ + lc(ux, UZ)] = (s_mom[1][idx] + C(0.5) * Fz) * inv_rho;
         s_ur[uy * UZ + lc(ux, UZ)] = (s_mom[2][idx] + C(0.5) * Fr) * inv_rho;
@@ -617,7 +622,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             const C druz = zd ? C(0) : d_iso<true, kPair>(s_uz, uy, ux, UZ);
             const C dzur = zd ? C(0) : d_iso<false, kPair>(s_ur, uy, ux, UZ);
             const C drur = zd ? C(0) : d_iso<true, kPair>(s_ur, uy, ux, UZ);
-            const C inv_r = dev_rcp(rr);
+            const C inv_r = inv_r_t[k];
             const C mu = rho * mu_fac;
             hz = (mu * (druz + dzur) - rho * ur * uz) * inv_r;
             hr = (C(2) * mu * (drur - ur * inv_r) - rho * ur * ur) * inv_r;
@@ -659,7 +664,7 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             const C Fz = Fz_t[k], Fr = Fr_t[k];
             C hz = C(0), hr = C(0), mass = C(0);
             if (a.axisym) source_terms(hz, hr, mass);
-            const C inv_rho = dev_rcp(rho);
+            const C inv_rho = inv_rho_t[k];  // rho is summed as in 3a
             // equilibrium velocity: shifted by tau F (Eq. ueq), or the
             // hydrodynamic velocity with Guo forcing
             const C qz = guo ? uz : (jz + tau * Fz) * inv_rho;
