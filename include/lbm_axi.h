@@ -248,7 +248,7 @@ int lbm_axi_record(lbm_axi_t h, int64_t n, void* d_states);
  * tile variants give the same populations bit for bit; chunk_rows is read by
  * the strip only.  create selects the tile kernel, the fastest on MI355X
  * (4096 x 512 FP64: 75 us per step, against 77 us alternating, 78 us by
- * columns, 79 us with node pairs and 93 us for the strip with chunks of 43
+ * columns, 80 us with node pairs and 93 us for the strip with chunks of 43
  * rows); set_open leaves the strip for it.  Returns LBM_AXI_EUNSUP when the
  * strip does not apply. */
 #define LBM_AXI_KERNEL_TILE 0
