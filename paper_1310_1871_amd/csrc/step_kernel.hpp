@@ -429,8 +429,17 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             }
         }
     }
+    // the tile nodes' sums of the stored values (rho - rho_ref when shifted)
+    // and j, formed once here and in 3a and read again by the collision
+    C sig_t[NPT], jz_t[NPT], jr_t[NPT];
 #pragma unroll
-    for (int k = 0; k < NPT; ++k) s_psi[(node_lr(k) + 6) * PZ + lc(node_lz(k) + 6, PZ)] = psi_of(rho_of(f[k]));
+    for (int k = 0; k < NPT; ++k) {
+        C sg = C(0);
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) sg += f[k][i];
+        sig_t[k] = sg;
+        s_psi[(node_lr(k) + 6) * PZ + lc(node_lz(k) + 6, PZ)] = psi_of(P::kShift ? sg + rho_ref : sg);
+    }
     __syncthreads();
 
     // ---- 2. isotropic d_r psi on the 4-node halo, and the 1D d_r psi that
@@ -497,8 +506,10 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         Fr_t[k] = C(0);
         inv_r_t[k] = C(0);
         inv_rho_t[k] = C(0);
+        jz_t[k] = C(0);
+        jr_t[k] = C(0);
         if (gr < nr) {
-            const C rho = rho_of(f[k]);
+            const C rho = P::kShift ? sig_t[k] + rho_ref : sig_t[k];
             inv_r_t[k] = dev_rcp(C(gr) + C(0.5));
             C Fz, Fr;
             force_at(lr + 2, lz + 2, rho, inv_r_t[k], Fz, Fr);
@@ -506,8 +517,10 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
             Fr_t[k] = Fr;
             const C inv_rho = dev_rcp(rho);
             inv_rho_t[k] = inv_rho;
-            s_uz[(lr + 2) * UZ + lc(lz + 2, UZ)] = (jz_of(f[k]) + C(0.5) * Fz) * inv_rho;
-            s_ur[(lr + 2) * UZ + lc(lz + 2, UZ)] = (jr_of(f[k]) + C(0.5) * Fr) * inv_rho;
+            jz_t[k] = jz_of(f[k]);
+            jr_t[k] = jr_of(f[k]);
+            s_uz[(lr + 2) * UZ + lc(lz + 2, UZ)] = (jz_t[k] + C(0.5) * Fz) * inv_rho;
+            s_ur[(lr + 2) * UZ + lc(lz + 2, UZ)] = (jr_t[k] + C(0.5) * Fr) * inv_rho;
         }
     }
     // 3b. velocity-ring nodes of real rows, from rho and j in LDS
@@ -606,12 +619,9 @@ __device__ __forceinline__ void tile_body(const StepArgs& a, const int tile, con
         const bool valid = gz < nz && gr < nr;
         if (!valid) continue;
         const int uy = lr + 2, ux = lz + 2;
-        C sig = C(0);  // sum of the stored values: rho - rho_ref when shifted
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) sig += f[k][i];
+        const C sig = sig_t[k];  // sum of the stored values: rho - rho_ref when shifted
         const C rho = P::kShift ? sig + rho_ref : sig;
-        const C jz = (f[k][1] - f[k][3]) + (f[k][5] - f[k][6]) + (f[k][8] - f[k][7]);
-        const C jr = (f[k][2] - f[k][4]) + (f[k][5] - f[k][8]) + (f[k][6] - f[k][7]);
+        const C jz = jz_t[k], jr = jr_t[k];
         const C uz = s_uz[uy * UZ + lc(ux, UZ)], ur = s_ur[uy * UZ + lc(ux, UZ)];
         const C rr = C(gr) + C(0.5);
 
