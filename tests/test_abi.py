@@ -157,3 +157,30 @@ def test_adjoint_size_limits():
     dummy = ctypes.c_void_p(16)  # never dereferenced: validation fails first
     rc = A._lib.lbm_axi_adjoint_step(ctypes.byref(p), dummy, dummy, ctypes.c_void_p(32), None, dummy, 1 << 20, None)
     assert rc == L.EINVAL
+
+
+# The largest lattices accepted with nz = 16383 (= 129 x 127, ragged for
+# the tiles): one population buffer, 9 planes of nz nr values each padded
+# by 8 KiB, must stay below 4 GiB, the reach of the kernels' 32-bit buffer
+# offsets.  9 (16383 x 3641 x 8 + 8192) = 4 294 909 944 bytes; one more row
+# is 4 296 089 520.  FP32 storage holds twice the rows.
+LARGEST_NZ = 16383
+LARGEST_NR = {0: 3641, 1: 7282}
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_largest_accepted_lattice(precision):
+    """check_params (no device) accepts the largest lattice of 16383
+    columns and rejects one more row with a message; the workspace holds
+    two buffers of at least 9 padded planes each."""
+    from paper_1310_1871_amd import lbm_axi as L
+    nr = LARGEST_NR[precision]
+    size = 8 if precision == 0 else 4
+    assert 9 * (LARGEST_NZ * nr * size + 8192) < 2 ** 32 <= 9 * (LARGEST_NZ * (nr + 1) * size + 8192)
+    ok = L.make_params(LARGEST_NZ, nr, precision=precision, rho_ref=0.5 * precision)
+    assert L.lib.lbm_axi_check_params(ctypes.byref(ok)) == L.OK
+    assert L.workspace_bytes(ok) >= 2 * 9 * (LARGEST_NZ * nr * size + 8192)
+    big = L.make_params(LARGEST_NZ, nr + 1, precision=precision, rho_ref=0.5 * precision)
+    assert L.lib.lbm_axi_check_params(ctypes.byref(big)) == L.EINVAL
+    assert "4 GiB" in L.last_error()
+    assert L.workspace_bytes(big) == 0

@@ -144,6 +144,62 @@ def test_full_size_thread_fields():
     _compare(4096, 512, rho, 3, G=G, tau=0.8, wall=1)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_largest_lattice_repeats_one_period(precision):
+    """The largest lattice the library accepts with nz = 16383: each
+    population buffer just below 4 GiB (3641 rows in FP64, 7282 in FP32),
+    the end of the kernels' 32-bit buffer offsets, and ragged for the tiles
+    (the last tile column 63 wide, the last tile row 9 or 2 rows).  Its
+    state repeats with period 127 in z (129 periods).  z is periodic, so the
+    step commutes with the shift by one period: after 12 steps every
+    population of the large lattice equals the one of a 127-column lattice
+    run alone (small tiles), which in FP64 matches the oracle.  The two tile
+    shapes order a few operations differently, so "equals" is up to the
+    storage type's rounding (measured 5.6e-16 in FP64, 3.6e-7 in FP32);
+    a wrapped offset or a misplaced plane anywhere in the 4 GiB gives
+    differences of the populations' own size.  The 3D mass of the large
+    lattice is 129 times the small one's: to summation order in FP64, and
+    in FP32 to roundings of random sign in 1.2e8 nodes (measured 2.7e-11,
+    bound 1e-9)."""
+    L = _lib()
+    nz, period = 16383, 127
+    nr = 3641 if precision == 0 else 7282
+    steps, G, tau, wall = 12, -5.0, 0.9, precision
+    rref = 0.0 if precision == 0 else 0.5
+    _say(f"largest lattice case precision={precision} nz={nz} nr={nr} period={period} steps={steps}")
+    rho, uz, ur = random_state_fields(16383 + precision, period, nr, rho_lo=0.3, rho_hi=2.0, u_amp=0.01)
+
+    def run(n, reps):
+        p = L.make_params(n, nr, G=G, tau=tau, wall=wall, precision=precision, rho_ref=rref)
+        dev = [torch.from_numpy(a).cuda().repeat(1, reps) for a in (rho, uz, ur)]
+        sim = L.AxiLBM(p, *dev)
+        sim.step(steps)
+        return sim
+
+    small = run(period, 1)
+    dt = torch.float64 if precision == 0 else torch.float32
+    fs = small.get_state().view(dt).reshape(9, nr, 1, period)
+    mass_small = small.reduce()[0]
+    big = run(nz, nz // period)
+    fb = big.get_state().view(dt).reshape(9, nr, nz // period, period)
+    mass_big = big.reduce()[0]
+    torch.cuda.synchronize()
+    err = max((fb[i] - fs[i]).abs().max().item() for i in range(9))
+    _say(f"  max |f_large - f_period| = {err:.3e}; 3D mass {mass_big!r} against 129 x {mass_small!r}")
+    del fb
+    big.close()
+    assert err <= (1e-12 if precision == 0 else 1e-5)
+    assert abs(mass_big - (nz // period) * mass_small) <= (1e-12 if precision == 0 else 1e-9) * abs(mass_big)
+    if precision == 0:
+        rg, uzg, urg = (t.cpu().numpy() for t in small.moments())
+        p = O.make_params(period, nr, G=G, tau=tau, wall=wall)
+        ro, uzo, uro = O.moments(p, O.run(p, O.equilibrium(p, rho, uz, ur), steps))
+        e = max(np.abs(rg - ro).max(), np.abs(uzg - uzo).max(), np.abs(urg - uro).max())
+        _say(f"  period lattice against the oracle: {e:.3e}")
+        assert e <= TOL
+    small.close()
+
+
 @pytest.mark.parametrize("wall", [0, 1])
 def test_large_tile_shape_ragged(wall):
     """A lattice large enough for the large 64 x 16 tiles (2145 of them) but
