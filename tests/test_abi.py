@@ -144,6 +144,18 @@ def test_batch_rejects_midlink_source():
     assert "MIDLINK" in L.last_error()
 
 
+def test_empty_batch_is_rejected():
+    """A batch needs at least one instance: a count of 0 (or a NULL list)
+    gives no workspace size and an error message."""
+    from paper_1310_1871_amd import batch as B
+    from paper_1310_1871_amd import lbm_axi as L
+    ps = (L.Params * 1)(L.make_params(64, 32))
+    assert B._lib.lbm_axi_batch_workspace_bytes(ps, 0) == 0
+    assert "at least one instance" in L.last_error()
+    assert B._lib.lbm_axi_batch_workspace_bytes(None, 1) == 0
+    assert B._lib.lbm_axi_batch_workspace_bytes(ps, 1) > 0
+
+
 def test_adjoint_size_limits():
     """The adjoint takes nz >= 4 and nr >= 6 (its psi window mirrors up to
     six rows at the axis and the wall); smaller grids get no workspace size,

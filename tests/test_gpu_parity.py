@@ -454,3 +454,61 @@ def test_graph_replay_matches_direct_launches():
         assert torch.equal(fa, fb) and ra == rb
     a.close()
     b.close()
+
+
+def test_zero_counts_change_nothing_and_negative_counts_fail():
+    """Empty work: lbm_axi_step(0), lbm_axi_batch_step(0) and
+    lbm_axi_adjoint_run with k = 0 return OK and leave every state (and the
+    adjoint's lam and gradient sums) bit for bit as it was; the steps after
+    them match a lattice that never made the empty call.  A negative count,
+    and a record of 0 states, fail with LBM_AXI_EINVAL."""
+    import ctypes
+    from paper_1310_1871_amd import adjoint as A
+    from paper_1310_1871_amd import batch as B
+    L = _lib()
+    nz, nr = 100, 37
+    rho, uz, ur = random_state_fields(10037, nz, nr, rho_lo=0.5, rho_hi=1.5, u_amp=0.01)
+    _say("zero-count case single lattice 100x37")
+    p = L.make_params(nz, nr, G=-4.0, tau=0.9, wall=1)
+    fields = [torch.from_numpy(a).cuda() for a in (rho, uz, ur)]
+    a = L.AxiLBM(p, *fields)
+    b = L.AxiLBM(L.make_params(nz, nr, G=-4.0, tau=0.9, wall=1), *fields)
+    a.step(3)
+    b.step(3)
+    before = a.populations()
+    assert L.lib.lbm_axi_step(a._h, 0) == L.OK
+    assert torch.equal(a.populations(), before)
+    assert L.lib.lbm_axi_step(a._h, -1) == L.EINVAL and ">= 0" in L.last_error()
+    rec = torch.empty(a.state_bytes(), dtype=torch.uint8, device="cuda")
+    assert L.lib.lbm_axi_record(a._h, 0, ctypes.c_void_p(rec.data_ptr())) == L.EINVAL
+    a.step(5)
+    b.step(5)
+    assert torch.equal(a.populations(), b.populations())
+    f_state = a.get_state().view(torch.float64).reshape(9, nr, nz).clone()
+    a.close()
+    b.close()
+
+    _say("zero-count case batch of two")
+    ps = [L.make_params(64, 32, G=-5.0, tau=0.9), L.make_params(nz, nr, G=-4.0, tau=0.9, wall=1)]
+    rg, rl = coexistence_densities(-5.0)
+    rhos = [torch.from_numpy(drop_density(64, 32, 32.0, 10.0, rl, rg, 2.0, {2: 1.0})).cuda(), fields[0]]
+    bat = B.AxiBatch(ps, rhos)
+    bat.step(2)
+    bat.synchronize()
+    keep = [bat.populations(k) for k in range(2)]
+    assert B._lib.lbm_axi_batch_step(bat._h, 0) == L.OK
+    assert B._lib.lbm_axi_batch_step(bat._h, -2) == L.EINVAL
+    bat.synchronize()
+    assert all(torch.equal(bat.populations(k), keep[k]) for k in range(2))
+    bat.close()
+
+    _say("zero-count case adjoint run")
+    dev = torch.device("cuda")
+    ws = torch.empty(A._lib.lbm_axi_adjoint_workspace_bytes(nz, nr) // 8, dtype=torch.float64, device=dev)
+    lam = torch.from_numpy(np.random.Generator(np.random.PCG64(5)).standard_normal((9, nr, nz))).to(dev)
+    lam0 = lam.clone()
+    acc = torch.tensor([0.25, -0.5], dtype=torch.float64, device=dev)
+    A.adjoint_run(p, f_state, 0, lam, torch.empty_like(lam), acc, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(lam, lam0)
+    assert acc.tolist() == [0.25, -0.5]
