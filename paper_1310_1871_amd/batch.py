@@ -4,6 +4,7 @@ Argument marshalling only: the ensemble runs in the HIP library (one
 persistent launch per step, replayed from a captured HIP graph on a
 non-default stream).  Device memory comes from torch.
 """
+import contextlib
 import ctypes
 
 import torch
@@ -41,7 +42,11 @@ class AxiBatch:
 
     ``params``: list of lbm_axi Params (same precision); ``rho0``: list of
     float64 device tensors [nr, nz].  The batch issues its work on ``stream``
-    (default: a new non-default torch stream, so steps are graph-replayed)."""
+    (default: a new non-default torch stream, so steps are graph-replayed).
+    Calls that read or write caller tensors are ordered on both sides: the
+    batch's stream first waits for the caller's current stream (which may
+    still use that memory), and the caller's stream then waits for the
+    batch's work on it."""
 
     def __init__(self, params, rho0, device="cuda", stream=None):
         n = len(params)
@@ -59,12 +64,27 @@ class AxiBatch:
             if tuple(r.shape) != (p.nr, p.nz):
                 raise ValueError("rho0 shape does not match its parameters")
         ptrs = (_vp * n)(*[r.data_ptr() for r in self._rho0])
-        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         h = _vp()
-        L.check(_lib.lbm_axi_batch_create(arr, n, ptrs, _vp(self.workspace.data_ptr()), nbytes,
-                                          _vp(self.stream.cuda_stream), ctypes.byref(h)))
+        with self._handoff():
+            # the allocator reuses the workspace only after the batch's
+            # stream has finished with it
+            self.workspace.record_stream(self.stream)
+            L.check(_lib.lbm_axi_batch_create(arr, n, ptrs, _vp(self.workspace.data_ptr()), nbytes,
+                                              _vp(self.stream.cuda_stream), ctypes.byref(h)))
         self._h = h
         self.n = n
+
+    @contextlib.contextmanager
+    def _handoff(self):
+        """Stream order around a call that reads or writes caller tensors
+        (see the class docstring)."""
+        cur = torch.cuda.current_stream(self.device)
+        other = self.stream != cur
+        if other:
+            self.stream.wait_stream(cur)
+        yield
+        if other:
+            cur.wait_stream(self.stream)
 
     def nodes(self):
         return int(_lib.lbm_axi_batch_nodes(self._h))
@@ -96,13 +116,12 @@ class AxiBatch:
 
     def moments(self, k):
         p = self.params[k]
-        with torch.cuda.stream(self.stream):
-            rho = torch.empty((p.nr, p.nz), dtype=torch.float64, device=self.device)
-            uz = torch.empty_like(rho)
-            ur = torch.empty_like(rho)
-        L.check(_lib.lbm_axi_batch_moments(self._h, int(k), _vp(rho.data_ptr()), _vp(uz.data_ptr()),
-                                           _vp(ur.data_ptr())))
-        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        rho = torch.empty((p.nr, p.nz), dtype=torch.float64, device=self.device)
+        uz = torch.empty_like(rho)
+        ur = torch.empty_like(rho)
+        with self._handoff():
+            L.check(_lib.lbm_axi_batch_moments(self._h, int(k), _vp(rho.data_ptr()), _vp(uz.data_ptr()),
+                                               _vp(ur.data_ptr())))
         return rho, uz, ur
 
     def populations(self, k):
@@ -110,10 +129,9 @@ class AxiBatch:
         the library (lbm_axi_batch_populations: the shift is added back in
         FP32 storage)."""
         p = self.params[k]
-        with torch.cuda.stream(self.stream):
-            out = torch.empty((9, p.nr, p.nz), dtype=torch.float64, device=self.device)
-        L.check(_lib.lbm_axi_batch_populations(self._h, int(k), _vp(out.data_ptr())))
-        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        out = torch.empty((9, p.nr, p.nz), dtype=torch.float64, device=self.device)
+        with self._handoff():
+            L.check(_lib.lbm_axi_batch_populations(self._h, int(k), _vp(out.data_ptr())))
         return out
 
     def synchronize(self):

@@ -5,6 +5,7 @@ every step of the method runs in the HIP library.  Importing this module on
 a machine where the built library is missing raises ImportError; there is no
 CPU fallback.
 """
+import contextlib
 import ctypes
 import os
 import warnings
@@ -145,6 +146,12 @@ class AxiLBM:
 
     ``rho0``, ``uz0``, ``ur0`` are float64 tensors [nr, nz] (velocities may be
     None) on the device; the populations start at f^eq(rho0, u0).
+
+    The library works on ``stream`` if one is given, else on the caller's
+    current stream at each call.  With a stream of its own, every call that
+    reads or writes caller tensors is ordered on both sides: the handle's
+    stream first waits for the caller's (which may still use that memory),
+    and the caller's stream then waits for the handle's work on it.
     """
 
     def __init__(self, params, rho0, uz0=None, ur0=None, device="cuda", stream=None):
@@ -160,10 +167,32 @@ class AxiLBM:
         uz0 = self._field(uz0) if uz0 is not None else None
         ur0 = self._field(ur0) if ur0 is not None else None
         h = ctypes.c_void_p()
-        check(lib.lbm_axi_create(ctypes.byref(params), _ptr(rho0), _ptr(uz0), _ptr(ur0),
-                                 _ptr(self.workspace), nbytes, _stream_handle(stream), ctypes.byref(h)))
+        with self._handoff(sync=False):
+            if self._own_stream():
+                # the allocator reuses the workspace only after the
+                # handle's stream has finished with it
+                self.workspace.record_stream(self.stream)
+            check(lib.lbm_axi_create(ctypes.byref(params), _ptr(rho0), _ptr(uz0), _ptr(ur0),
+                                     _ptr(self.workspace), nbytes, _stream_handle(stream), ctypes.byref(h)))
         self._h = h
         self._keep = (rho0, uz0, ur0)  # inputs stay alive until the init kernel has run
+
+    def _own_stream(self):
+        return self.stream is not None and self.stream != torch.cuda.current_stream(self.device)
+
+    @contextlib.contextmanager
+    def _handoff(self, sync=True):
+        """Stream order around a call that reads or writes caller tensors
+        (see the class docstring); also points the handle at its stream."""
+        cur = torch.cuda.current_stream(self.device)
+        other = self._own_stream()
+        if other:
+            self.stream.wait_stream(cur)
+        if sync:
+            self._sync_stream()
+        yield
+        if other:
+            cur.wait_stream(self.stream)
 
     def _field(self, a):
         t = torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
@@ -188,12 +217,12 @@ class AxiLBM:
 
     def moments(self):
         """(rho, u_z, u_r) float64 tensors [nr, nz] of the current state."""
-        self._sync_stream()
         shape = (self.nr, self.nz)
         rho = torch.empty(shape, dtype=torch.float64, device=self.device)
         uz = torch.empty_like(rho)
         ur = torch.empty_like(rho)
-        check(lib.lbm_axi_moments(self._h, _ptr(rho), _ptr(uz), _ptr(ur)))
+        with self._handoff():
+            check(lib.lbm_axi_moments(self._h, _ptr(rho), _ptr(uz), _ptr(ur)))
         return rho, uz, ur
 
     def reduce(self):
@@ -213,11 +242,11 @@ class AxiLBM:
         dict with A, neck, r_max, rho_axis_min, rho_in, rho_out, dp; the
         radius profile R(z) goes into ``radius_out`` (float64 device tensor
         [nz]) if given.  Synchronises the stream."""
-        self._sync_stream()
         z_col = self.nz // 2 if z_col is None else int(z_col)
         out = (ctypes.c_double * NINTERFACE)()
-        check(lib.lbm_axi_interface(self._h, float(rho_mid), z_col, _ptr(radius_out) if radius_out is not None else None,
-                                    out))
+        with self._handoff():
+            check(lib.lbm_axi_interface(self._h, float(rho_mid), z_col,
+                                        _ptr(radius_out) if radius_out is not None else None, out))
         keys = ("A", "neck", "r_max", "rho_axis_min", "rho_in", "rho_out", "dp")
         return {k: float(v) for k, v in zip(keys, out)}
 
@@ -232,8 +261,9 @@ class AxiLBM:
             self._open_keep = (uz, ur)  # alive until the stream has copied them
         else:
             uz = ur = None
-        check(lib.lbm_axi_set_open(self._h, int(in_row), float(rho_in), _ptr(uz), _ptr(ur), int(out_row),
-                                   float(rho_out)))
+        with self._handoff():
+            check(lib.lbm_axi_set_open(self._h, int(in_row), float(rho_in), _ptr(uz), _ptr(ur), int(out_row),
+                                       float(rho_out)))
 
     def _column(self, a):
         t = torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
@@ -260,19 +290,19 @@ class AxiLBM:
         """Copy of the populations (the library's storage type, [9][nr][nz]);
         into ``out`` (a contiguous device tensor of state_bytes bytes) if
         given."""
-        self._sync_stream()
         if out is None:
             out = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
         elif out.numel() * out.element_size() != self.state_bytes() or not out.is_contiguous():
             raise ValueError("state buffer of the wrong size or not contiguous")
-        check(lib.lbm_axi_get_state(self._h, _ptr(out)))
+        with self._handoff():
+            check(lib.lbm_axi_get_state(self._h, _ptr(out)))
         return out
 
     def set_state(self, src):
         if src.numel() * src.element_size() != self.state_bytes() or not src.is_contiguous():
             raise ValueError("state buffer of the wrong size or not contiguous")
-        self._sync_stream()
-        check(lib.lbm_axi_set_state(self._h, _ptr(src)))
+        with self._handoff():
+            check(lib.lbm_axi_set_state(self._h, _ptr(src)))
 
     def record(self, n, out):
         """Write the states f^t .. f^{t+n-1} into ``out`` (a contiguous
@@ -280,16 +310,16 @@ class AxiLBM:
         f^{t+n-1}."""
         if n < 1 or out.numel() * out.element_size() != n * self.state_bytes() or not out.is_contiguous():
             raise ValueError("record buffer of the wrong size or not contiguous")
-        self._sync_stream()
-        check(lib.lbm_axi_record(self._h, int(n), _ptr(out)))
+        with self._handoff():
+            check(lib.lbm_axi_record(self._h, int(n), _ptr(out)))
 
     def populations(self):
         """Current populations f_i as a float64 tensor [9, nr, nz], decoded
         by the library (lbm_axi_populations: the shift is added back in FP32
         storage)."""
-        self._sync_stream()
         out = torch.empty((9, self.nr, self.nz), dtype=torch.float64, device=self.device)
-        check(lib.lbm_axi_populations(self._h, _ptr(out)))
+        with self._handoff():
+            check(lib.lbm_axi_populations(self._h, _ptr(out)))
         return out
 
     def set_kernel(self, kind, chunk_rows=48):

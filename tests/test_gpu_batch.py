@@ -149,6 +149,31 @@ def test_graph_replay_equals_direct_launches():
     d.close()
 
 
+def test_outputs_are_ordered_on_the_callers_stream():
+    """moments and populations of a batch on its own stream, reduced on the
+    caller's stream as soon as they return and freed at once (the allocator
+    hands their memory to the next call), with steps in between: equal to
+    the same batch run on the caller's stream, bit for bit."""
+    L, B = _libs()
+    params, rhos, _ = _small_ensemble(L.FP64)
+    g = B.AxiBatch(params, rhos)
+    d = B.AxiBatch(params, rhos, stream=torch.cuda.current_stream())
+    _say("batch outputs on the caller's stream")
+    got, want = [], []
+    for rep in range(5):
+        g.step(3)
+        d.step(3)
+        for b, acc in ((g, got), (d, want)):
+            for k in range(len(params)):
+                rho, uz, ur = b.moments(k)
+                acc.append(torch.stack([rho.sum(), uz.abs().sum(), ur.abs().sum()]))
+                del rho, uz, ur
+                acc.append(b.populations(k).sum(dim=(1, 2)))
+    assert torch.equal(torch.cat(got).cpu(), torch.cat(want).cpu())
+    g.close()
+    d.close()
+
+
 def test_schedules_agree_and_autotune_restores_state():
     L, B = _libs()
     params, rhos, _ = _small_ensemble(L.FP32_SHIFTED)

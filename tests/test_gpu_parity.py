@@ -512,3 +512,45 @@ def test_zero_counts_change_nothing_and_negative_counts_fail():
     torch.cuda.synchronize()
     assert torch.equal(lam, lam0)
     assert acc.tolist() == [0.25, -0.5]
+
+
+def test_own_stream_handle_orders_caller_tensors():
+    """A handle with a stream of its own, used with no explicit
+    synchronisation: the initial density is computed on the caller's stream
+    just before create, the state is replaced from a tensor the caller has
+    just written, and moments, populations and get_state are reduced on the
+    caller's stream as soon as they return, then freed, in a loop (so the
+    allocator hands their memory to the next call at once).  Every value
+    equals that of a handle on the caller's stream, bit for bit; the
+    binding orders the two streams around each call that touches caller
+    memory."""
+    L = _lib()
+    nz, nr = 128, 64
+    rho_np, uz_np, ur_np = random_state_fields(12864, nz, nr, rho_lo=0.5, rho_hi=1.5, u_amp=0.01)
+    _say("own-stream handle case 128x64")
+    side = torch.cuda.Stream()
+    base = torch.from_numpy(rho_np).cuda()
+    ref = L.AxiLBM(L.make_params(nz, nr, G=-4.0, tau=0.9), base)
+    a = L.AxiLBM(L.make_params(nz, nr, G=-4.0, tau=0.9), base * 1.0, stream=side)
+    sums_ref, sums = [], []
+    for it in range(6):
+        ref.step(7)
+        a.step(7)
+        for sim, acc in ((ref, sums_ref), (a, sums)):
+            rho, uz, ur = sim.moments()
+            acc.append(torch.stack([rho.sum(), uz.abs().sum(), ur.abs().sum()]))
+            del rho, uz, ur
+            acc.append(sim.populations().sum(dim=(1, 2)))
+            acc.append(sim.get_state().view(torch.float64).reshape(9, nr, nz)[:, ::7, ::5].sum(dim=(1, 2)))
+        if it == 3:
+            # both lattices continue from one state written on the caller's stream
+            st = ref.get_state().view(torch.float64).reshape(9, nr, nz) * 1.0
+            ref.set_state(st.reshape(-1).view(torch.uint8))
+            a.set_state((st * 1.0).reshape(-1).view(torch.uint8))
+            del st
+    got = torch.cat(sums).cpu()
+    want = torch.cat(sums_ref).cpu()
+    _say(f"  max |difference| over {got.numel()} sums: {(got - want).abs().max().item():.3e}")
+    assert torch.equal(got, want)
+    a.close()
+    ref.close()
