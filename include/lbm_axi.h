@@ -131,7 +131,11 @@ int lbm_axi_create(const lbm_axi_params* p, const double* d_rho0, const double* 
 /* Advance n >= 0 full time steps (Sec. II, Eq. lbm2d_mod_new with the
  * Shan–Chen force of Eq. scforce, the axisymmetric extra force of
  * Eq. scAxisExtra, the source terms of Eqs. condition_h/H_terms and the
- * boundary rules of Sec. II.E).  Asynchronous. */
+ * boundary rules of Sec. II.E).  Asynchronous.  On a stream the caller is
+ * capturing into a graph, the step kernels go into that graph (the library
+ * does not replay graphs of its own then) and n must be even
+ * (LBM_AXI_EINVAL otherwise): the handle keeps which of its two buffers
+ * holds the state on the host, and a replay runs the captured launches. */
 int lbm_axi_step(lbm_axi_t h, int64_t n);
 
 /* Density rho = sum f_i (Eq. hydro_var) and hydrodynamic velocity

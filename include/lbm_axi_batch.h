@@ -44,7 +44,10 @@ int lbm_axi_batch_create(const lbm_axi_params* ps, int32_t n_inst, const double*
                          void* d_workspace, size_t ws_bytes, void* hip_stream, lbm_axi_batch_t* out);
 
 /* Advance every instance by n steps with the persistent kernel (graph
- * replay on a non-null stream, direct launches on the null stream). */
+ * replay on a non-null stream, direct launches on the null stream).  On a
+ * stream the caller is capturing into a graph, the launches go into that
+ * graph and n must be even (LBM_AXI_EINVAL otherwise), as for
+ * lbm_axi_step. */
 int lbm_axi_batch_step(lbm_axi_batch_t b, int64_t n);
 
 /* The same n steps with one ordinary launch per instance per step (the

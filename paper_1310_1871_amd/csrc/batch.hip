@@ -300,7 +300,15 @@ int lbm_axi_batch_create(const lbm_axi_params* ps, int32_t n_inst, const double*
 int lbm_axi_batch_step(lbm_axi_batch_t b, int64_t n) {
     if (!b) return fail(LBM_AXI_EINVAL, "batch is NULL");
     if (n < 0) return fail(LBM_AXI_EINVAL, "n must be >= 0");
-    const bool graphs = b->stream != nullptr;
+    // a stream the caller is capturing into a graph of its own gets the
+    // launches themselves; the buffer parity is host state, so a capture
+    // that is to be replayed must hold an even number of steps
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (b->stream != nullptr) HIP_TRY(hipStreamIsCapturing(b->stream, &cs), "stream capture status");
+    const bool captured = cs != hipStreamCaptureStatusNone;
+    if (captured && (n & 1))
+        return fail(LBM_AXI_EINVAL, "n must be even while the stream is being captured (got %lld)", (long long)n);
+    const bool graphs = b->stream != nullptr && !captured;
     int64_t done = 0;
     if (graphs && n >= 2) {
         int rc = ensure_graph(b, b->parity);

@@ -460,10 +460,18 @@ int ensure_graph(lbm_axi_ctx* h, int from) {
 int lbm_axi_step(lbm_axi_t h, int64_t n) {
     if (!h) return fail(LBM_AXI_EINVAL, "handle is NULL");
     if (n < 0) return fail(LBM_AXI_EINVAL, "n must be >= 0");
+    // a stream the caller is capturing into a graph of its own gets the
+    // launches themselves; the buffer parity is host state, so a capture
+    // that is to be replayed must hold an even number of steps
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (h->stream != nullptr) HIP_TRY(hipStreamIsCapturing(h->stream, &cs), "stream capture status");
+    const bool captured = cs != hipStreamCaptureStatusNone;
+    if (captured && (n & 1))
+        return fail(LBM_AXI_EINVAL, "n must be even while the stream is being captured (got %lld)", (long long)n);
     int64_t done = 0;
     // pairs of steps as graph replays: small lattices, a capturable stream
-    // (not the null stream)
-    if (n >= 4 && h->stream != nullptr && (long long)h->p.nz * h->p.nr <= kGraphMaxNodes) {
+    // (not the null stream) that nobody captures
+    if (n >= 4 && h->stream != nullptr && !captured && (long long)h->p.nz * h->p.nr <= kGraphMaxNodes) {
         const int rc = ensure_graph(h, h->cur);
         if (rc != LBM_AXI_OK) return rc;
         for (; done + 2 <= n; done += 2) HIP_TRY(hipGraphLaunch(h->graph[h->cur], h->stream), "graph launch");

@@ -174,6 +174,37 @@ def test_outputs_are_ordered_on_the_callers_stream():
     d.close()
 
 
+def test_batch_step_captured_into_a_caller_graph():
+    """lbm_axi_batch_step on the batch's stream while the caller captures
+    it (torch.cuda.graph on that stream): the persistent launches go into
+    the caller's graph, an odd step count is refused there, and each of
+    several replays, with eager work between them, equals eager steps of a
+    second batch bit for bit."""
+    L, B = _libs()
+    params, rhos, _ = _small_ensemble(L.FP64)
+    s = torch.cuda.Stream()
+    cap = B.AxiBatch(params, rhos, stream=s)
+    ref = B.AxiBatch(params, rhos)
+    cap.step(2)  # the batch's own graphs exist before the capture
+    ref.step(2)
+    torch.cuda.synchronize()
+    _say("caller graph capture of lbm_axi_batch_step")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        with pytest.raises(L.LbmAxiError) as e:
+            cap.step(5)
+        cap.step(4)
+    assert e.value.code == L.EINVAL
+    for rep in range(3):
+        g.replay()
+        ref.step(4)
+        _ = torch.ones(1000, device="cuda").sum().item()  # eager work between the replays
+        for k in range(len(params)):
+            assert torch.equal(cap.populations(k), ref.populations(k)), (rep, k)
+    cap.close()
+    ref.close()
+
+
 def test_schedules_agree_and_autotune_restores_state():
     L, B = _libs()
     params, rhos, _ = _small_ensemble(L.FP32_SHIFTED)

@@ -554,3 +554,36 @@ def test_own_stream_handle_orders_caller_tensors():
     assert torch.equal(got, want)
     a.close()
     ref.close()
+
+
+def test_step_captured_into_a_caller_graph():
+    """lbm_axi_step on a stream the caller captures (torch.cuda.graph):
+    the step kernels go into the caller's graph instead of a graph of the
+    library's own, an odd step count is refused there (the buffer parity
+    is host state), and each of several replays, with eager work and a
+    synchronisation between them, equals eager steps of a second lattice
+    bit for bit.  The capture itself runs nothing."""
+    L = _lib()
+    rg, rl = coexistence_densities(-5.5)
+    rho = drop_density(128, 64, 64.0, 20.0, rl, rg, 2.0, {2: 3.0})
+    _say("caller graph capture of lbm_axi_step 128x64")
+    a = L.AxiLBM(L.make_params(128, 64, G=-5.5, tau=0.9), torch.from_numpy(rho).cuda())
+    b = L.AxiLBM(L.make_params(128, 64, G=-5.5, tau=0.9), torch.from_numpy(rho).cuda())
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        with pytest.raises(L.LbmAxiError) as e:
+            a.step(3)
+        a.step(6)
+    assert e.value.code == L.EINVAL and "even" in str(e.value)
+    torch.cuda.synchronize()
+    assert torch.equal(a.populations(), b.populations())
+    for rep in range(4):
+        g.replay()
+        b.step(6)
+        ra, rb = a.reduce(), b.reduce()  # eager work between the replays (synchronises)
+        fa, fb = a.populations(), b.populations()
+        _say(f"  replay {rep}: max |df| = {(fa - fb).abs().max().item():.3e}")
+        assert torch.equal(fa, fb) and ra == rb, rep
+    a.close()
+    b.close()
