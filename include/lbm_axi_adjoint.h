@@ -99,7 +99,11 @@ int lbm_axi_density(const double* d_f, int32_t nz, int32_t nr, double* d_rho, vo
  * arrays: ray-major CSR (h_row_ptr[n_rays+1], h_col, h_val) and node-major
  * CSR (h_node_ptr[n_nodes+1], h_nodes, h_node_row, h_node_val).  Call once
  * with the array pointers NULL to get *h_nnz and *h_n_nodes, then with
- * arrays of capacity cap >= nnz (LBM_AXI_ENOMEM otherwise). */
+ * arrays of capacity cap >= nnz (LBM_AXI_ENOMEM otherwise).  LBM_AXI_EINVAL
+ * (message in lbm_axi_last_error) for ds <= 0, s_max < 0, non-finite zc,
+ * ds, s_max or angle, |zc| + s_max > 1e9, more than 2^24 samples per ray,
+ * or nz nr or nnz beyond 32-bit indices; LBM_AXI_ENOMEM when the host
+ * allocation fails. */
 int lbm_axi_ray_weights(int32_t nz, int32_t nr, double zc, const double* h_thetas, int32_t n_rays, double ds,
                         double s_max, int32_t cap, int32_t* h_row_ptr, int32_t* h_col, double* h_val,
                         int32_t* h_node_ptr, int32_t* h_nodes, int32_t* h_node_row, double* h_node_val,

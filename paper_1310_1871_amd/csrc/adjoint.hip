@@ -43,6 +43,7 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "../../include/lbm_axi.h"
@@ -1317,69 +1318,88 @@ int lbm_axi_ray_weights(int32_t nz, int32_t nr, double zc, const double* h_theta
                         double s_max, int32_t cap, int32_t* h_row_ptr, int32_t* h_col, double* h_val,
                         int32_t* h_node_ptr, int32_t* h_nodes, int32_t* h_node_row, double* h_node_val,
                         int32_t* h_nnz, int32_t* h_n_nodes) {
-    if (nz < 1 || nr < 1 || n_rays < 0 || !(ds > 0.0) || !h_nnz || !h_n_nodes || (n_rays > 0 && !h_thetas))
-        return LBM_AXI_EINVAL;
-    // per ray: node -> weight of the bilinear interpolants of the samples
-    // s_k = (k + 1/2) ds along the ray from (zc, 0) at angle theta; rows
-    // below row 0 mirror onto the real rows, rows above the last clamp to
-    // it, z is periodic
-    std::vector<std::map<int32_t, double>> rows((size_t)n_rays);
-    const int nk = (int)std::floor(s_max / ds);
-    for (int m = 0; m < n_rays; ++m) {
-        const double ct = std::cos(h_thetas[m]), st = std::sin(h_thetas[m]);
-        for (int k = 0; k < nk; ++k) {
-            const double sk = (k + 0.5) * ds;
-            const double zz = zc + sk * ct, y = sk * st - 0.5;
-            const int j0 = (int)std::floor(y), k0 = (int)std::floor(zz);
-            const double ty = y - j0, tz = zz - k0;
-            for (int dj = 0; dj < 2; ++dj) {
-                const double wy = dj ? ty : 1.0 - ty;
-                int jj = j0 + dj;
-                if (jj < 0) jj = -1 - jj;
-                if (jj > nr - 1) jj = nr - 1;
-                for (int dk = 0; dk < 2; ++dk) {
-                    const double wz = dk ? tz : 1.0 - tz;
-                    const double wgt = ds * wy * wz;
-                    if (wgt == 0.0) continue;
-                    int kk = (k0 + dk) % nz;
-                    if (kk < 0) kk += nz;
-                    rows[m][jj * nz + kk] += wgt;
+    using lbm_host::fail;
+    if (nz < 1 || nr < 1 || n_rays < 0 || !h_nnz || !h_n_nodes || (n_rays > 0 && !h_thetas))
+        return fail(LBM_AXI_EINVAL, "ray weights: need nz, nr >= 1, n_rays >= 0 and non-NULL outputs");
+    if ((long long)nz * nr > INT_MAX) return fail(LBM_AXI_EINVAL, "ray weights: grid %d x %d too large", nz, nr);
+    // the sample coordinates are converted to int: finite, and within
+    // kMaxRayReach of the origin; at most kMaxRaySamples samples per ray
+    constexpr double kMaxRayReach = 1e9;
+    constexpr double kMaxRaySamples = 1 << 24;
+    if (!std::isfinite(ds) || !(ds > 0.0) || !std::isfinite(s_max) || !(s_max >= 0.0) || !std::isfinite(zc))
+        return fail(LBM_AXI_EINVAL, "ray weights: ds > 0, s_max >= 0 and zc must be finite");
+    if (std::fabs(zc) + s_max > kMaxRayReach)
+        return fail(LBM_AXI_EINVAL, "ray weights: |zc| + s_max beyond %g", kMaxRayReach);
+    if (std::floor(s_max / ds) > kMaxRaySamples)
+        return fail(LBM_AXI_EINVAL, "ray weights: s_max / ds gives more than %g samples per ray", kMaxRaySamples);
+    for (int m = 0; m < n_rays; ++m)
+        if (!std::isfinite(h_thetas[m])) return fail(LBM_AXI_EINVAL, "ray weights: theta %d is not finite", m);
+    try {
+        // per ray: node -> weight of the bilinear interpolants of the samples
+        // s_k = (k + 1/2) ds along the ray from (zc, 0) at angle theta; rows
+        // below row 0 mirror onto the real rows, rows above the last clamp to
+        // it, z is periodic
+        std::vector<std::map<int32_t, double>> rows((size_t)n_rays);
+        const int nk = (int)std::floor(s_max / ds);
+        for (int m = 0; m < n_rays; ++m) {
+            const double ct = std::cos(h_thetas[m]), st = std::sin(h_thetas[m]);
+            for (int k = 0; k < nk; ++k) {
+                const double sk = (k + 0.5) * ds;
+                const double zz = zc + sk * ct, y = sk * st - 0.5;
+                const int j0 = (int)std::floor(y), k0 = (int)std::floor(zz);
+                const double ty = y - j0, tz = zz - k0;
+                for (int dj = 0; dj < 2; ++dj) {
+                    const double wy = dj ? ty : 1.0 - ty;
+                    int jj = j0 + dj;
+                    if (jj < 0) jj = -1 - jj;
+                    if (jj > nr - 1) jj = nr - 1;
+                    for (int dk = 0; dk < 2; ++dk) {
+                        const double wz = dk ? tz : 1.0 - tz;
+                        const double wgt = ds * wy * wz;
+                        if (wgt == 0.0) continue;
+                        int kk = (k0 + dk) % nz;
+                        if (kk < 0) kk += nz;
+                        rows[m][jj * nz + kk] += wgt;
+                    }
                 }
             }
         }
-    }
-    std::map<int32_t, std::vector<std::pair<int32_t, double>>> by_node;
-    int32_t nnz = 0;
-    for (int m = 0; m < n_rays; ++m) {
-        nnz += (int32_t)rows[m].size();
-        for (const auto& kv : rows[m]) by_node[kv.first].push_back({m, kv.second});
-    }
-    *h_nnz = nnz;
-    *h_n_nodes = (int32_t)by_node.size();
-    if (!h_row_ptr || !h_col || !h_val || !h_node_ptr || !h_nodes || !h_node_row || !h_node_val) return LBM_AXI_OK;
-    if (cap < nnz) return LBM_AXI_ENOMEM;
-    int32_t k = 0;
-    h_row_ptr[0] = 0;
-    for (int m = 0; m < n_rays; ++m) {
-        for (const auto& kv : rows[m]) {
-            h_col[k] = kv.first;
-            h_val[k] = kv.second;
-            ++k;
+        std::map<int32_t, std::vector<std::pair<int32_t, double>>> by_node;
+        long long total = 0;
+        for (int m = 0; m < n_rays; ++m) total += (long long)rows[m].size();
+        if (total > INT_MAX) return fail(LBM_AXI_EINVAL, "ray weights: %lld entries, beyond 32-bit indices", total);
+        const int32_t nnz = (int32_t)total;
+        for (int m = 0; m < n_rays; ++m)
+            for (const auto& kv : rows[m]) by_node[kv.first].push_back({m, kv.second});
+        *h_nnz = nnz;
+        *h_n_nodes = (int32_t)by_node.size();
+        if (!h_row_ptr || !h_col || !h_val || !h_node_ptr || !h_nodes || !h_node_row || !h_node_val) return LBM_AXI_OK;
+        if (cap < nnz) return fail(LBM_AXI_ENOMEM, "ray weights: capacity %d below nnz %d", cap, nnz);
+        int32_t k = 0;
+        h_row_ptr[0] = 0;
+        for (int m = 0; m < n_rays; ++m) {
+            for (const auto& kv : rows[m]) {
+                h_col[k] = kv.first;
+                h_val[k] = kv.second;
+                ++k;
+            }
+            h_row_ptr[m + 1] = k;
         }
-        h_row_ptr[m + 1] = k;
-    }
-    int32_t j = 0, q = 0;
-    h_node_ptr[0] = 0;
-    for (const auto& kv : by_node) {
-        h_nodes[q] = kv.first;
-        for (const auto& e : kv.second) {
-            h_node_row[j] = e.first;
-            h_node_val[j] = e.second;
-            ++j;
+        int32_t j = 0, q = 0;
+        h_node_ptr[0] = 0;
+        for (const auto& kv : by_node) {
+            h_nodes[q] = kv.first;
+            for (const auto& e : kv.second) {
+                h_node_row[j] = e.first;
+                h_node_val[j] = e.second;
+                ++j;
+            }
+            h_node_ptr[++q] = j;
         }
-        h_node_ptr[++q] = j;
+        return LBM_AXI_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_AXI_ENOMEM, "ray weights: host allocation failed");
     }
-    return LBM_AXI_OK;
 }
 
 }  // extern "C"

@@ -136,6 +136,34 @@ def test_ray_weights_host_builder_matches_oracle():
                                        nodes, nrow, nval, ctypes.byref(nnz), ctypes.byref(nn)) == L.ENOMEM
 
 
+def test_ray_weights_rejects_bad_geometry():
+    """The host-side ray builder refuses, with LBM_AXI_EINVAL and a message,
+    every input that would reach an undefined float-to-int conversion or a
+    runaway sample count: non-finite zc, ds, s_max or angle, ds <= 0,
+    s_max < 0, |zc| + s_max > 1e9, more than 2^24 samples per ray, a grid
+    beyond 32-bit node indices.  Valid geometry still builds."""
+    import math
+    from paper_1310_1871_amd import lbm_axi as L
+    lib = L.lib
+    i32, dbl = ctypes.c_int32, ctypes.c_double
+    nnz, nn = i32(), i32()
+
+    def call(nz=64, nr=32, zc=32.0, th=(0.3, 1.2), ds=0.5, s_max=20.0):
+        tha = (dbl * len(th))(*th)
+        return lib.lbm_axi_ray_weights(nz, nr, dbl(zc), tha, len(th), dbl(ds), dbl(s_max), 0, None, None, None,
+                                       None, None, None, None, ctypes.byref(nnz), ctypes.byref(nn))
+
+    assert call() == L.OK and nnz.value > 0
+    bad = [dict(zc=math.nan), dict(zc=math.inf), dict(ds=math.nan), dict(ds=0.0), dict(ds=-0.5),
+           dict(s_max=math.inf), dict(s_max=math.nan), dict(s_max=-1.0), dict(th=(0.3, math.nan)),
+           dict(zc=2e9), dict(s_max=1e7, ds=0.5), dict(nz=1 << 20, nr=1 << 12)]
+    for kw in bad:
+        assert call(**kw) == L.EINVAL, kw
+        assert "ray weights" in L.last_error(), kw
+    # the limits themselves are accepted
+    assert call(s_max=float(1 << 23), ds=0.5, th=(0.3,), nz=64, nr=32) == L.OK
+
+
 def test_batch_rejects_midlink_source():
     from paper_1310_1871_amd import batch as B
     from paper_1310_1871_amd import lbm_axi as L
