@@ -84,11 +84,13 @@ int lbm_axi_adjoint_run(const lbm_axi_params* p, const double* d_states, int32_t
 
 /* Adjoint of the initial equilibrium f_i = f^eq_i(rho0, u0) (appendix,
  * Eq. e_distribution): d_rho0_bar = sum_i d_lam0_i df^eq_i/drho0.
- * d_uz0 / d_ur0 may be NULL (zero initial velocity). */
+ * d_uz0 / d_ur0 may be NULL (zero initial velocity).  LBM_AXI_EINVAL for
+ * NULL d_lam0 / d_rho0_bar or nz, nr < 1. */
 int lbm_axi_init_vjp(const double* d_lam0, const double* d_uz0, const double* d_ur0, int32_t nz, int32_t nr,
                      double* d_rho0_bar, void* hip_stream);
 
-/* rho = sum_i f_i of a state (Eq. hydro_var). */
+/* rho = sum_i f_i of a state (Eq. hydro_var).  LBM_AXI_EINVAL for NULL
+ * pointers or nz, nr < 1. */
 int lbm_axi_density(const double* d_f, int32_t nz, int32_t nr, double* d_rho, void* hip_stream);
 
 /* Host-side construction of the ray-integral interface radius
@@ -110,19 +112,25 @@ int lbm_axi_ray_weights(int32_t nz, int32_t nr, double zc, const double* h_theta
                         int32_t* h_nnz, int32_t* h_n_nodes);
 
 /* d_out[m] = sum_k val_mk (rho[col_mk] - rho_g) / (rho_l - rho_g) with the
- * ray-major matrix on the device (fixed-order FP64 reduction). */
+ * ray-major matrix on the device (fixed-order FP64 reduction).
+ * LBM_AXI_EINVAL for NULL pointers, n_rows < 0, or rho_l, rho_g not finite
+ * or equal; n_rows = 0 does nothing. */
 int lbm_axi_ray_forward(const double* d_rho, int32_t n_rows, const int32_t* d_row_ptr, const int32_t* d_col,
                         const double* d_val, double rho_l, double rho_g, double* d_out, void* hip_stream);
 
 /* Adjoint of lbm_axi_ray_forward applied to rho = sum_i f_i:
  * d_lam_i(x) += sum_m d_rbar[m] w_mx / (rho_l - rho_g) for every direction
- * i, with the node-major matrix on the device. */
+ * i, with the node-major matrix on the device (built by lbm_axi_ray_weights
+ * for the same nz, nr: d_lam holds nine planes of nz nr values).
+ * LBM_AXI_EINVAL for NULL pointers, n_nodes < 0, nz, nr < 1, nz nr beyond
+ * 32-bit indices, or rho_l, rho_g not finite or equal. */
 int lbm_axi_ray_vjp(const double* d_rbar, int32_t n_nodes, const int32_t* d_node_ptr, const int32_t* d_node_row,
                     const double* d_node_val, const int32_t* d_nodes, double rho_l, double rho_g, int32_t nz,
                     int32_t nr, double* d_lam, void* hip_stream);
 
 /* *d_loss += sum_m (d_r[m] - d_target[m])^2 and, if d_rbar is not NULL,
- * d_rbar[m] = 2 (d_r[m] - d_target[m]) (FP64). */
+ * d_rbar[m] = 2 (d_r[m] - d_target[m]) (FP64).  LBM_AXI_EINVAL for NULL
+ * d_r, d_target, d_loss or m < 0. */
 int lbm_axi_misfit(const double* d_r, const double* d_target, int32_t m, double* d_loss, double* d_rbar,
                    void* hip_stream);
 

@@ -1271,7 +1271,8 @@ int lbm_axi_adjoint_run(const lbm_axi_params* p, const double* d_states, int32_t
 
 int lbm_axi_init_vjp(const double* d_lam0, const double* d_uz0, const double* d_ur0, int32_t nz, int32_t nr,
                      double* d_rho0_bar, void* hip_stream) {
-    if (!d_lam0 || !d_rho0_bar || nz < 1 || nr < 1) return LBM_AXI_EINVAL;
+    if (!d_lam0 || !d_rho0_bar) return lbm_host::fail(LBM_AXI_EINVAL, "init_vjp: NULL argument");
+    if (nz < 1 || nr < 1) return lbm_host::fail(LBM_AXI_EINVAL, "init_vjp: grid %d x %d", nz, nr);
     const long long n = (long long)nz * nr;
     hipLaunchKernelGGL(init_vjp_kernel, dim3(nblk(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), d_lam0,
                        d_uz0, d_ur0, n, d_rho0_bar);
@@ -1279,7 +1280,8 @@ int lbm_axi_init_vjp(const double* d_lam0, const double* d_uz0, const double* d_
 }
 
 int lbm_axi_density(const double* d_f, int32_t nz, int32_t nr, double* d_rho, void* hip_stream) {
-    if (!d_f || !d_rho || nz < 1 || nr < 1) return LBM_AXI_EINVAL;
+    if (!d_f || !d_rho) return lbm_host::fail(LBM_AXI_EINVAL, "density: NULL argument");
+    if (nz < 1 || nr < 1) return lbm_host::fail(LBM_AXI_EINVAL, "density: grid %d x %d", nz, nr);
     const long long n = (long long)nz * nr;
     hipLaunchKernelGGL(density_kernel, dim3(nblk(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), d_f, n, d_rho);
     return hipGetLastError() == hipSuccess ? LBM_AXI_OK : LBM_AXI_EHIP;
@@ -1287,7 +1289,11 @@ int lbm_axi_density(const double* d_f, int32_t nz, int32_t nr, double* d_rho, vo
 
 int lbm_axi_ray_forward(const double* d_rho, int32_t n_rows, const int32_t* d_row_ptr, const int32_t* d_col,
                         const double* d_val, double rho_l, double rho_g, double* d_out, void* hip_stream) {
-    if (!d_rho || !d_row_ptr || !d_col || !d_val || !d_out || n_rows < 0 || rho_l == rho_g) return LBM_AXI_EINVAL;
+    if (!d_rho || !d_row_ptr || !d_col || !d_val || !d_out)
+        return lbm_host::fail(LBM_AXI_EINVAL, "ray_forward: NULL argument");
+    if (n_rows < 0) return lbm_host::fail(LBM_AXI_EINVAL, "ray_forward: n_rows %d", n_rows);
+    if (!std::isfinite(rho_l) || !std::isfinite(rho_g) || rho_l == rho_g)
+        return lbm_host::fail(LBM_AXI_EINVAL, "ray_forward: rho_l and rho_g must be finite and differ");
     if (n_rows == 0) return LBM_AXI_OK;
     hipLaunchKernelGGL(ray_forward_kernel, dim3(n_rows), dim3(256), 0, static_cast<hipStream_t>(hip_stream), d_rho,
                        d_row_ptr, d_col, d_val, rho_l, rho_g, d_out);
@@ -1297,8 +1303,13 @@ int lbm_axi_ray_forward(const double* d_rho, int32_t n_rows, const int32_t* d_ro
 int lbm_axi_ray_vjp(const double* d_rbar, int32_t n_nodes, const int32_t* d_node_ptr, const int32_t* d_node_row,
                     const double* d_node_val, const int32_t* d_nodes, double rho_l, double rho_g, int32_t nz,
                     int32_t nr, double* d_lam, void* hip_stream) {
-    if (!d_rbar || !d_node_ptr || !d_node_row || !d_node_val || !d_nodes || !d_lam || n_nodes < 0 || rho_l == rho_g)
-        return LBM_AXI_EINVAL;
+    if (!d_rbar || !d_node_ptr || !d_node_row || !d_node_val || !d_nodes || !d_lam)
+        return lbm_host::fail(LBM_AXI_EINVAL, "ray_vjp: NULL argument");
+    // the kernel adds into the nine planes of nz nr values of d_lam
+    if (n_nodes < 0 || nz < 1 || nr < 1 || (long long)nz * nr > INT_MAX)
+        return lbm_host::fail(LBM_AXI_EINVAL, "ray_vjp: n_nodes %d, grid %d x %d", n_nodes, nz, nr);
+    if (!std::isfinite(rho_l) || !std::isfinite(rho_g) || rho_l == rho_g)
+        return lbm_host::fail(LBM_AXI_EINVAL, "ray_vjp: rho_l and rho_g must be finite and differ");
     if (n_nodes == 0) return LBM_AXI_OK;
     hipLaunchKernelGGL(ray_vjp_kernel, dim3((n_nodes + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
                        d_rbar, d_node_ptr, d_node_row, d_node_val, d_nodes, n_nodes, rho_l, rho_g,
@@ -1308,7 +1319,8 @@ int lbm_axi_ray_vjp(const double* d_rbar, int32_t n_nodes, const int32_t* d_node
 
 int lbm_axi_misfit(const double* d_r, const double* d_target, int32_t m, double* d_loss, double* d_rbar,
                    void* hip_stream) {
-    if (!d_r || !d_target || !d_loss || m < 0) return LBM_AXI_EINVAL;
+    if (!d_r || !d_target || !d_loss) return lbm_host::fail(LBM_AXI_EINVAL, "misfit: NULL argument");
+    if (m < 0) return lbm_host::fail(LBM_AXI_EINVAL, "misfit: m %d", m);
     hipLaunchKernelGGL(misfit_kernel, dim3(1), dim3(256), 0, static_cast<hipStream_t>(hip_stream), d_r, d_target, m,
                        d_loss, d_rbar);
     return hipGetLastError() == hipSuccess ? LBM_AXI_OK : LBM_AXI_EHIP;

@@ -164,6 +164,36 @@ def test_ray_weights_rejects_bad_geometry():
     assert call(s_max=float(1 << 23), ds=0.5, th=(0.3,), nz=64, nr=32) == L.OK
 
 
+def test_adjoint_helpers_reject_bad_arguments_without_device_work():
+    """The adjoint's helper calls check their arguments before any launch
+    and say why in last_error: NULL pointers, negative counts, empty grids,
+    a grid beyond 32-bit indices for the ray VJP (whose kernel adds into
+    the nine nz nr planes of lam), and equal or non-finite phase
+    densities."""
+    import math
+    from paper_1310_1871_amd import adjoint as A
+    from paper_1310_1871_amd import lbm_axi as L
+    lib = A._lib
+    p = ctypes.c_void_p(4096)  # never dereferenced: every call below fails its checks first
+    cases = [
+        (lambda: lib.lbm_axi_init_vjp(None, None, None, 8, 8, p, None), "init_vjp"),
+        (lambda: lib.lbm_axi_init_vjp(p, None, None, 0, 8, p, None), "init_vjp"),
+        (lambda: lib.lbm_axi_density(p, 8, -1, p, None), "density"),
+        (lambda: lib.lbm_axi_ray_forward(p, -1, p, p, p, 2.0, 0.1, p, None), "ray_forward"),
+        (lambda: lib.lbm_axi_ray_forward(p, 4, p, p, p, 1.0, 1.0, p, None), "ray_forward"),
+        (lambda: lib.lbm_axi_ray_forward(p, 4, p, p, p, math.nan, 0.1, p, None), "ray_forward"),
+        (lambda: lib.lbm_axi_ray_vjp(p, 4, p, p, p, p, 2.0, 0.1, 0, 8, p, None), "ray_vjp"),
+        (lambda: lib.lbm_axi_ray_vjp(p, 4, p, p, p, p, 2.0, 0.1, 1 << 20, 1 << 12, p, None), "ray_vjp"),
+        (lambda: lib.lbm_axi_ray_vjp(p, 4, p, p, p, p, 2.0, math.inf, 8, 8, p, None), "ray_vjp"),
+        (lambda: lib.lbm_axi_ray_vjp(None, 4, p, p, p, p, 2.0, 0.1, 8, 8, p, None), "ray_vjp"),
+        (lambda: lib.lbm_axi_misfit(p, p, -3, p, None, None), "misfit"),
+        (lambda: lib.lbm_axi_misfit(p, None, 3, p, None, None), "misfit"),
+    ]
+    for call, name in cases:
+        assert call() == L.EINVAL, name
+        assert name in L.last_error(), (name, L.last_error())
+
+
 def test_batch_rejects_midlink_source():
     from paper_1310_1871_amd import batch as B
     from paper_1310_1871_amd import lbm_axi as L
