@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import oracle as O
-from lbm_inputs import coexistence_densities, drop_density, ensemble, thread_density
+from lbm_inputs import coexistence_densities, drop_density, ensemble, random_state_fields, thread_density
 
 pytestmark = pytest.mark.gpu
 
@@ -129,6 +129,35 @@ def test_batch_bitwise_equals_per_instance_and_solo(precision):
         solo.close()
     ref.close()
     per.close()
+
+
+def test_instances_beyond_4gib_of_the_workspace():
+    """Three FP64 instances of 16383 x 1500 (1.77 GB per population buffer):
+    the first buffer of the third instance straddles 4 GiB from the start
+    of the batch workspace and every second buffer lies beyond it (14.8 GiB
+    in all), while each buffer stays below the 4 GiB reach of the kernels'
+    32-bit offsets.  After 6 steps every instance equals a one-instance
+    batch of it, bit for bit, so nothing on the host or in the work list
+    truncates an instance's place in the workspace."""
+    L, B = _libs()
+    nz, nr = 16383, 1500
+    params, rhos = [], []
+    for k in range(3):
+        rho, _, _ = random_state_fields(70 + k, nz, nr, rho_lo=0.4, rho_hi=1.8, u_amp=0.0)
+        params.append(L.make_params(nz, nr, G=-4.5, tau=0.9, wall=k % 2))
+        rhos.append(torch.from_numpy(rho).cuda())
+    _say("batch instances beyond 4 GiB: 3 x 16383x1500 FP64")
+    big = B.AxiBatch(params, rhos)
+    big.step(6)
+    for k in range(3):
+        solo = B.AxiBatch([params[k]], [rhos[k]])
+        solo.step(6)
+        a, c = big.populations(k), solo.populations(0)
+        _say(f"  instance {k}: max |df| = {(a - c).abs().max().item():.3e}")
+        assert torch.equal(a, c), k
+        del a, c
+        solo.close()
+    big.close()
 
 
 def test_graph_replay_equals_direct_launches():
