@@ -34,10 +34,11 @@ extern "C" {
  * stencils; two sets of F-bar scaled by -G psi in two components and of
  * exp(-rho/rho0)) and two sums per tile for dL/dG and dL/dtau (56 B per node
  * and 32 B per tile of 16 x 16 nodes, or of 16 x 8 on grids with fewer than
- * 192 of the larger tiles); 0 if the size is invalid.  The adjoint needs nz >= 4 and nr >= 6
- * (the psi window mirrors up to six rows at the axis and the wall) and
- * nz (nr + 12) < 2^31; other sizes give 0 here and LBM_AXI_EINVAL from the
- * calls. */
+ * 192 of the larger tiles); 0 if the size is invalid.  The adjoint needs
+ * nz >= 4 and nr >= 6 (the psi window mirrors up to six rows at the axis
+ * and the wall), nz (nr + 12) < 2^31, and one FP64 state, 72 nz nr bytes,
+ * below 4 GiB (its kernels address a state with 32-bit byte offsets); other
+ * sizes give 0 here and LBM_AXI_EINVAL from the calls. */
 size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr);
 
 /* One reverse step.  With f' = step(f; G, tau) (post-streaming states,

@@ -1123,11 +1123,18 @@ void launch_b(const TileArgs& a, bool axi, bool final, hipStream_t s) {
         launch_b_t<kLargeTZ, kLargeTR, kLargeNT>(a, axi, final, tiles, s);
 }
 
+// grids the reverse step handles: its psi window mirrors up to six rows at
+// the axis and the wall (nz >= 4, nr >= 6), node indices of the window are
+// 32-bit, and the kernels address a whole FP64 state (nine planes) through
+// buffer resources with 32-bit byte offsets, so one state stays below 4 GiB
+bool adjoint_grid_ok(int nz, int nr) {
+    return nz >= 4 && nr >= 6 && (long long)nz * (nr + 12) <= INT_MAX &&
+           9ull * 8ull * (unsigned long long)nz * (unsigned long long)nr < (1ull << 32);
+}
+
 int check_adjoint(const lbm_axi_params* p, size_t ws_bytes) {
     if (!p) return LBM_AXI_EINVAL;
-    if (p->nz < 4 || p->nr < 6 || !(p->tau > 0.5) || !(p->psi_rho0 > 0.0)) return LBM_AXI_EINVAL;
-    // node indices are 32-bit
-    if ((long long)p->nz * (p->nr + 12) > INT_MAX) return LBM_AXI_EINVAL;
+    if (!adjoint_grid_ok(p->nz, p->nr) || !(p->tau > 0.5) || !(p->psi_rho0 > 0.0)) return LBM_AXI_EINVAL;
     if (p->wall != 0 && p->wall != 1) return LBM_AXI_EINVAL;
     if (p->precision != LBM_AXI_FP64 || p->flags != 0) return LBM_AXI_EUNSUP;
     if (ws_bytes < lbm_axi_adjoint_workspace_bytes(p->nz, p->nr)) return LBM_AXI_ENOMEM;
@@ -1203,7 +1210,7 @@ int lbm_axi_adjoint_step_noalloc(const lbm_axi_params* p, const double* d_f, con
 }
 
 size_t lbm_axi_adjoint_workspace_bytes(int32_t nz, int32_t nr) {
-    if (nz < 4 || nr < 6 || (long long)nz * (nr + 12) > INT_MAX) return 0;
+    if (!adjoint_grid_ok(nz, nr)) return 0;
     const size_t n = (size_t)nz * nr;
     return (kWsFields * n + 4 * (size_t)tiles_of(nz, nr)) * sizeof(double);
 }

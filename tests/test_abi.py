@@ -216,13 +216,23 @@ def test_empty_batch_is_rejected():
 
 def test_adjoint_size_limits():
     """The adjoint takes nz >= 4 and nr >= 6 (its psi window mirrors up to
-    six rows at the axis and the wall); smaller grids get no workspace size,
-    and the calls return LBM_AXI_EINVAL before any device work."""
+    six rows at the axis and the wall) and one FP64 state below 4 GiB (its
+    kernels' 32-bit byte offsets); other grids get no workspace size, and
+    the calls return LBM_AXI_EINVAL before any device work."""
     from paper_1310_1871_amd import adjoint as A
     from paper_1310_1871_amd import lbm_axi as L
     ws = A._lib.lbm_axi_adjoint_workspace_bytes
     assert ws(4, 6) > 0 and ws(5, 8) > ws(4, 6)
     assert ws(3, 64) == 0 and ws(64, 5) == 0 and ws(1, 64) == 0
+    # one FP64 state, 72 nz nr bytes, stays below 4 GiB (32-bit byte offsets):
+    # 16383 x 3641 gives 4 294 836 216 bytes, one more row 4 296 015 792
+    assert 72 * 16383 * 3641 < 2 ** 32 <= 72 * 16383 * 3642
+    assert ws(16383, 3641) > 0 and ws(16383, 3642) == 0
+    assert ws(1 << 20, 1 << 10) == 0  # within nz (nr + 12) < 2^31, beyond 4 GiB
+    big = L.make_params(16383, 3642)
+    rc = A._lib.lbm_axi_adjoint_step(ctypes.byref(big), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                     ctypes.c_void_p(32), None, ctypes.c_void_p(16), 1 << 40, None)
+    assert rc == L.EINVAL
     p = L.make_params(3, 64)
     dummy = ctypes.c_void_p(16)  # never dereferenced: validation fails first
     rc = A._lib.lbm_axi_adjoint_step(ctypes.byref(p), dummy, dummy, ctypes.c_void_p(32), None, dummy, 1 << 20, None)
