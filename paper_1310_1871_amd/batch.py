@@ -50,6 +50,8 @@ class AxiBatch:
 
     def __init__(self, params, rho0, device="cuda", stream=None):
         n = len(params)
+        if len(rho0) != n:
+            raise ValueError(f"{len(rho0)} initial densities for {n} instances")
         self.params = list(params)
         arr = (L.Params * n)(*params)
         self._arr = arr

@@ -264,3 +264,12 @@ def test_largest_accepted_lattice(precision):
     assert L.lib.lbm_axi_check_params(ctypes.byref(big)) == L.EINVAL
     assert "4 GiB" in L.last_error()
     assert L.workspace_bytes(big) == 0
+
+
+def test_batch_binding_checks_its_lists():
+    """The batch binding refuses initial densities that do not pair one to
+    one with the instances' parameters (before any device work)."""
+    from paper_1310_1871_amd import batch as B
+    from paper_1310_1871_amd import lbm_axi as L
+    with pytest.raises(ValueError):
+        B.AxiBatch([L.make_params(64, 32), L.make_params(64, 32)], [None])
