@@ -143,9 +143,10 @@ def test_instances_beyond_4gib_of_the_workspace():
     nz, nr = 16383, 1500
     params, rhos = [], []
     for k in range(3):
-        rho, _, _ = random_state_fields(70 + k, nz, nr, rho_lo=0.4, rho_hi=1.8, u_amp=0.0)
+        # a random field of 127 columns, repeated 129 times along z
+        rho, _, _ = random_state_fields(70 + k, 127, nr, rho_lo=0.4, rho_hi=1.8, u_amp=0.0)
         params.append(L.make_params(nz, nr, G=-4.5, tau=0.9, wall=k % 2))
-        rhos.append(torch.from_numpy(rho).cuda())
+        rhos.append(torch.from_numpy(rho).cuda().repeat(1, nz // 127).contiguous())
     _say("batch instances beyond 4 GiB: 3 x 16383x1500 FP64")
     big = B.AxiBatch(params, rhos)
     big.step(6)
