@@ -129,6 +129,17 @@ def test_ragged_and_tiny_grids(nz, nr):
     _compare(nz, nr, rho, 200, G=-4.0, tau=0.9, wall=1, uz=uz, ur=ur)
 
 
+@pytest.mark.parametrize("G,tau,lo,hi", [(0.0, 0.51, 0.95, 1.05), (-4.0, 1.5, 0.7, 1.3)])
+def test_extreme_relaxation_times(G, tau, lo, hi):
+    """The ends of the relaxation times the scheme runs: tau = 0.51 (nu =
+    0.0033, 1/tau near 2) single phase, and tau = 1.5 (nu = 1/3, the
+    viscous axisymmetric source terms large) with the SC force; random
+    fields with velocity on the ragged 100 x 37 grid, 200 steps against the
+    oracle."""
+    rho, uz, ur = random_state_fields(int(tau * 100), 100, 37, rho_lo=lo, rho_hi=hi, u_amp=0.02)
+    _compare(100, 37, rho, 200, G=G, tau=tau, wall=1, uz=uz, ur=ur)
+
+
 def test_pipe_flow_body_force():
     """Single phase with the body force (Hagen–Poiseuille set-up, 16 x 16)."""
     rho = np.ones((16, 16))

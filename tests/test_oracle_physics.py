@@ -222,3 +222,21 @@ def test_thread_diverges_at_tau07():
         f = O.run(p, O.equilibrium(p, rho, 0 * rho, 0 * rho), 300)
         res[tau] = bool(np.isfinite(f).all())
     assert res == {0.7: False, 0.8: True}
+
+
+def test_axisymmetric_source_bounds_tau():
+    """An observed property of the scheme, not a value the paper prints: the
+    explicit axisymmetric source terms (Eqs. condition_h, H_terms), whose
+    viscous parts grow like nu u / r^2 on the first row (r = 1/2), bound
+    tau from above.  Single phase, random smooth fields with u ~ 0.02 on
+    100 x 37 with a free-slip wall, 200 steps: planar runs stay finite up
+    to tau = 2, axisymmetric ones at tau = 1.75 but not at tau = 2.  The
+    parity tests and workloads keep tau <= 1.5."""
+    from lbm_inputs import random_state_fields
+    rho, uz, ur = random_state_fields(200, 100, 37, rho_lo=0.9, rho_hi=1.1, u_amp=0.02)
+    res = {}
+    for tau, axisym in ((1.75, 1), (2.0, 1), (2.0, 0)):
+        p = O.make_params(100, 37, G=0.0, tau=tau, wall=1, axisym=axisym)
+        f = O.run(p, O.equilibrium(p, rho, uz, ur), 200)
+        res[(tau, axisym)] = bool(np.isfinite(f).all())
+    assert res == {(1.75, 1): True, (2.0, 1): False, (2.0, 0): True}
