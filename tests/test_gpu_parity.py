@@ -223,6 +223,18 @@ def test_large_tile_shape_ragged(wall):
     _compare(nz, nr, rho, 6, G=-5.0, tau=0.9, wall=wall, uz=uz, ur=ur)
 
 
+@pytest.mark.parametrize("nz,nr", [(65536, 6), (1, 16390)])
+def test_large_tiles_on_degenerate_shapes(nz, nr):
+    """Lattices that take the large 64 x 16 tiles (1024 or more of them)
+    in degenerate shapes: 65536 x 6, one tile row that is both the axis
+    and the wall tile with 6 of its 16 rows real; 1 x 16390, a single
+    column, so every tile's window wraps z many times (the narrow-lattice
+    path of the periodic wrap), ragged in r.  Random fields, 20 steps
+    against the oracle."""
+    rho, uz, ur = random_state_fields(nz + nr, nz, nr, rho_lo=0.6, rho_hi=1.4, u_amp=0.01)
+    _compare(nz, nr, rho, 20, G=-4.0, tau=0.9, wall=1, uz=uz, ur=ur)
+
+
 @pytest.mark.parametrize("nz,nr,flags,wall", [(4100, 515, 0, 0), (4100, 515, 4 | 2, 1), (2049, 520, 0, 1),
                                               (2048, 520, 8, 1), (4098, 515, 16, 0)])
 def test_node_pair_kernel(nz, nr, flags, wall):
